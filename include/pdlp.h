@@ -1,0 +1,218 @@
+/*
+ * pdlp.h - C ABI of the MI355X (gfx950) PDLP solver.
+ *
+ * The solver computes an approximate primal-dual solution of the linear program
+ *
+ *     minimize   c^T x
+ *     subject to G x >= h   (the first m1 = m - n_eq rows of K)
+ *                A x  = b   (the last n_eq rows of K)
+ *                l <= x <= u
+ *
+ * with K = [G; A] and q = [h; b] (Section 2, problem (1), and its saddle-point form (2)),
+ * by the PDHG iteration of Eq. (3) with the paper's enhancements: diagonal preconditioning
+ * (Section 3.5), adaptive step sizes (Algorithm 2), adaptive restarts from the normalized
+ * duality gap (Section 3.2), and primal-weight updates (Algorithm 3), driven by Algorithm 1.
+ * Termination uses the relative KKT criteria of Section 4.1, Eq. (6a)-(6c).
+ *
+ * All arithmetic runs in IEEE float64 on the GPU.  The iteration needs no host round trip:
+ * the host only enqueues work and reads back one small status record per block of
+ * check_every accepted steps.
+ *
+ * Conventions shared by every entry point
+ *  - Return value: a pdlp_status.  Negative values are API errors, non-negative values are
+ *    solve outcomes.  No C++ exception crosses this boundary.  After an error,
+ *    pdlp_last_error() describes it.
+ *  - Pointers passed as inputs may be host or device (HIP) pointers; the library inspects
+ *    each one.  Inputs are deep-copied: the caller may free them as soon as the call returns.
+ *  - Output pointers may be host or device pointers to caller-owned memory of the stated
+ *    length; NULL skips that output.
+ *  - All device work of a solver is enqueued on the HIP stream given to pdlp_create (NULL =
+ *    the default stream).  Every entry point has completed its device work when it returns.
+ *  - A solver is not thread-safe: calls on one solver must not overlap.
+ */
+#ifndef PDLP_H
+#define PDLP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pdlp_solver pdlp_solver;
+
+typedef enum pdlp_status {
+  PDLP_OPTIMAL = 0,              /* relative KKT error <= tol (Eq. (6a)-(6c))                 */
+  PDLP_ITERATION_LIMIT = 1,      /* iter_limit accepted PDHG steps taken                       */
+  PDLP_NUMERICAL_ERROR = 2,      /* non-finite value, or Algorithm 2 rejected max_retries times */
+  PDLP_NOT_SOLVED = 3,           /* pdlp_solve has not run yet                                 */
+  PDLP_ERR_INVALID_ARGUMENT = -1,
+  PDLP_ERR_OUT_OF_MEMORY = -2,
+  PDLP_ERR_DEVICE = -3,
+  PDLP_ERR_INVALID_STATE = -4
+} pdlp_status;
+
+/* Solver options.  pdlp_default_options() fills in the paper's PDLP settings. */
+typedef struct pdlp_options {
+  int32_t ruiz_iters;            /* Ruiz passes before Pock-Chambolle (Section 3.5): 10       */
+  int32_t pock_chambolle;        /* one Pock-Chambolle pass with alpha = 1: 1 (on)            */
+  int32_t adaptive_restarts;     /* restart scheme of Section 3.2: 1 (on)                     */
+  int32_t primal_weight_update;  /* Algorithm 3 at each restart: 1 (on)                       */
+  int32_t check_every;           /* accepted steps between restart/termination checks: 40     */
+  int32_t max_retries;           /* rejected attempts in a row that end the solve: 100        */
+  int32_t trace_iters;           /* keep scaled (x, y) after each of the first trace_iters
+                                    accepted steps (parity testing); 0 = off                  */
+  int32_t trace_capacity;        /* ring capacity of the attempt / check logs: 4096           */
+  int32_t time_kernels;          /* time every primal/dual step kernel with HIP events: 0    */
+  int32_t reserved0;
+  double beta_sufficient;        /* restart criterion (i):  0.1 (see the design notes)        */
+  double beta_necessary;         /* restart criterion (ii): 0.9                               */
+  double beta_artificial;        /* restart criterion (iii): 0.5                              */
+  double theta;                  /* primal-weight smoothing of Algorithm 3: 0.5               */
+  double primal_importance;      /* multiplies the initial primal weight: 1                   */
+  double eps_zero;               /* "small nonzero tolerance" of Section 3.3: 1e-10           */
+} pdlp_options;
+
+/* Counters and scalars of a solver (pdlp_get_info). */
+typedef struct pdlp_info {
+  int32_t status;                /* last pdlp_status of pdlp_solve                            */
+  int32_t output_is_average;     /* 1 if the returned point is the restart candidate average  */
+  int64_t m, n, n_eq, nnz;
+  int64_t iterations;            /* accepted PDHG steps k                                     */
+  int64_t attempts;              /* PDHG attempts (accepted + rejected)                       */
+  int64_t restarts;              /* outer-loop restarts n                                     */
+  int64_t checks;                /* restart/termination checks evaluated                      */
+  int64_t spmv_K, spmv_KT;       /* products with K~ and K~^T (2 of them = 1 KKT pass)        */
+  double omega;                  /* current primal weight                                     */
+  double eta_hat;                /* step size proposed for the next step                      */
+  double kkt[4];                 /* relative gap, primal, dual residual and their max at the
+                                    returned point (unscaled problem)                         */
+  double create_seconds;         /* host wall time of pdlp_create (copy, transpose, scaling)  */
+  double solve_seconds;          /* host wall time of the last pdlp_solve                     */
+  double step_bytes;             /* algorithmic HBM bytes of one accepted PDHG step           */
+} pdlp_info;
+
+/* One Algorithm-2 attempt, as logged by the solver. */
+typedef struct pdlp_attempt_rec {
+  int64_t k;                     /* accepted steps before this attempt                        */
+  double eta;                    /* step size tried                                           */
+  double eta_bar;                /* the largest step Eq. (5) allows (+inf if dy^T K dx = 0)   */
+  int32_t accepted;
+  int32_t pad;
+} pdlp_attempt_rec;
+
+/* One restart/termination check (Algorithm 1 at k = multiple of check_every). */
+typedef struct pdlp_check_rec {
+  int64_t k;
+  double mu_cur;                 /* normalized gap of the current iterate vs the anchor       */
+  double mu_avg;                 /* normalized gap of the average vs the anchor               */
+  double kkt;                    /* relative KKT error of the candidate                       */
+  double omega_after;            /* primal weight after this check                            */
+  double mu_anchor;              /* gap of the new anchor vs the old one (after a restart)    */
+  int32_t use_avg;               /* candidate = average (1) or current iterate (0)            */
+  int32_t mask;                  /* restart criteria met: 1 = (i), 2 = (ii), 4 = (iii)        */
+  int32_t terminated;
+  int32_t pad;
+} pdlp_check_rec;
+
+/* Fills *opts with the defaults listed in pdlp_options. */
+void pdlp_default_options(pdlp_options *opts);
+
+/*
+ * pdlp_create - validate and copy an LP onto the GPU and precondition it.
+ *   out        receives the new solver (NULL on failure).
+ *   m, n, n_eq K is m x n; its last n_eq rows are equalities, the first m - n_eq ">=" rows.
+ *              Requires n >= 1, m >= 0, 0 <= n_eq <= m, m and n below 2^31.
+ *   c          n costs;  q  m right-hand sides [h; b];  l, u  n bounds, +-INFINITY allowed.
+ *   row_ptr    m + 1 row offsets of K (int64, row_ptr[0] = 0, non-decreasing).
+ *   col_idx    row_ptr[m] column indices (int32), strictly increasing within each row.
+ *   val        row_ptr[m] finite values.
+ *   opts       NULL = pdlp_default_options().
+ *   hip_stream hipStream_t for all work of this solver, NULL = default stream.
+ * Errors: PDLP_ERR_INVALID_ARGUMENT for bad sizes, non-finite c, q or values, NaN bounds,
+ * l > u, l = +inf or u = -inf, column indices out of range, unsorted or duplicated within a
+ * row; PDLP_ERR_OUT_OF_MEMORY; PDLP_ERR_DEVICE for HIP failures.
+ * The LP is stored twice in CSR (K~ and a transposed copy K~^T, both preconditioned), so the
+ * device holds about 24 * nnz + 8 * (m + n) * 30 bytes.
+ */
+int pdlp_create(pdlp_solver **out, int64_t m, int64_t n, int64_t n_eq, const double *c,
+                const int64_t *row_ptr, const int32_t *col_idx, const double *val,
+                const double *q, const double *l, const double *u,
+                const pdlp_options *opts, void *hip_stream);
+
+/*
+ * pdlp_solve - run Algorithm 1 until the relative KKT error of a checked point is <= tol,
+ * iter_limit accepted steps have been taken (counted from creation), or a numerical error.
+ * A later call continues from the current state with the new tol and iter_limit.
+ * Returns the pdlp_status of the solve (or an API error).
+ */
+int pdlp_solve(pdlp_solver *s, double tol, int64_t iter_limit);
+
+/*
+ * pdlp_get - the returned point of the last solve, in the user's (unscaled) variables:
+ * x (n values), y (m values) and kkt (4 values: relative gap, primal residual, dual
+ * residual, max).  PDLP_ERR_INVALID_STATE before the first pdlp_solve.
+ */
+int pdlp_get(const pdlp_solver *s, double *x, double *y, double *kkt);
+
+/* pdlp_get_info - counters and scalars; see pdlp_info. */
+int pdlp_get_info(const pdlp_solver *s, pdlp_info *info);
+
+/* pdlp_destroy - free a solver and all its device memory.  NULL is allowed. */
+void pdlp_destroy(pdlp_solver *s);
+
+/* pdlp_last_error - text of the last error of s (or of the last failed pdlp_create when s is
+ * NULL).  Owned by the library, valid until the next call on s. */
+const char *pdlp_last_error(const pdlp_solver *s);
+
+/* ---- inspection entry points (parity tests and measurement) ---------------------------- */
+
+/* pdlp_get_scaling - the diagonal preconditioners: D1 (m values) and D2 (n values), with
+ * K~ = D1 K D2 (Section 3.5). */
+int pdlp_get_scaling(const pdlp_solver *s, double *D1, double *D2);
+
+/* pdlp_get_iterate - the current iterate z^{n,t} in the preconditioned variables
+ * (x~ = x / D2: n values, y~ = y / D1: m values). */
+int pdlp_get_iterate(const pdlp_solver *s, double *x_scaled, double *y_scaled);
+
+/*
+ * pdlp_get_trace - the solver's logs since creation.
+ *   att / att_cap / n_att   attempt records (the last att_cap are kept in the ring);
+ *   chk / chk_cap / n_chk   check records;
+ *   xs, ys                  scaled iterates after accepted steps 1..n_iter (n_iter <= trace_iters),
+ *                           stored row-wise: xs[(k-1)*n + j], ys[(k-1)*m + i].
+ * Any pointer may be NULL.  n_att / n_chk receive the total number logged (may exceed the cap).
+ */
+int pdlp_get_trace(const pdlp_solver *s, pdlp_attempt_rec *att, int64_t att_cap, int64_t *n_att,
+                   pdlp_check_rec *chk, int64_t chk_cap, int64_t *n_chk,
+                   double *xs, double *ys, int64_t *n_iter);
+
+/* pdlp_spmv - out = K~ x (transpose = 0; x: n values, out: m values) or out = K~^T x
+ * (transpose = 1; x: m values, out: n values) with the solver's preconditioned matrix and
+ * the same kernels the iteration uses.  x and out are device pointers. */
+int pdlp_spmv(pdlp_solver *s, int transpose, const double *x, double *out);
+
+/* pdlp_kernel_times - with options.time_kernels set, the summed HIP-event time in ms and
+ * the launch count of the primal step kernel (K~^T product, times[0], counts[0]) and of the
+ * dual step kernel (K~ product, times[1], counts[1]) over all solves so far. */
+int pdlp_kernel_times(const pdlp_solver *s, double *times_ms, int64_t *counts);
+
+/* pdlp_reset_kernel_times - zero the counters of pdlp_kernel_times. */
+int pdlp_reset_kernel_times(pdlp_solver *s);
+
+/*
+ * pdlp_build_schedule - host-only (no GPU needed): the row-block schedule the SpMV kernels use
+ * for a CSR matrix with nrows rows and offsets row_ptr.  Writes up to cap descriptors of four
+ * int32 {row0, count, kind | log2(lanes) << 8, split id} to desc, and sets *ndesc and *nsplit.
+ * kind 0: rows [row0, row0 + count) staged through LDS with 2^log2(lanes) lanes per row;
+ * kind 1: one row handled by a whole workgroup; kind 2: chunk `count` of a row too long for
+ * one workgroup (split id names the row's partial-sum table).
+ */
+int pdlp_build_schedule(const int64_t *row_ptr, int64_t nrows, int32_t *desc, int64_t cap,
+                        int64_t *ndesc, int64_t *nsplit);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDLP_H */

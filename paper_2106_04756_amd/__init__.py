@@ -1,0 +1,6 @@
+"""MI355X (gfx950) PDLP: the PDHG hot path of Applegate et al. in hand-written HIP.
+
+The solver lives in libpdlp_hip.so (C ABI in include/pdlp.h); `pdlp` is its binding.
+"""
+from .pdlp import (OPTIMAL, ITERATION_LIMIT, NUMERICAL_ERROR, NOT_SOLVED, Solver,  # noqa: F401
+                   default_options, lib, schedule, PdlpError, STATUS_NAMES)

@@ -1,0 +1,68 @@
+// Device-side views of the solver's data, shared by the kernels and the host driver.
+#pragma once
+
+#include <cstdint>
+
+#include "../../include/pdlp.h"
+#include "pdlp_internal.h"
+
+namespace pdlp {
+
+// One CSR copy with its row-block schedule.
+struct CsrDev {
+  const int64_t* rp;
+  const int32_t* ci;
+  const double* v;
+  int32_t nrows;
+  int32_t ndesc;
+  const RowDesc* desc;
+  const int32_t* split_nchunks;
+  const int32_t* split_base;
+  int32_t nsplit;
+  int32_t pad;
+  double* split_part;    // partial sums of split-row chunks
+  unsigned* split_cnt;   // chunk arrival counters (reset to 0 by the last arrival)
+};
+
+// Device vectors of a solver.  n-vectors are indexed by column j, m-vectors by row i.
+struct Bufs {
+  int32_t n, m, m1, pad;
+  const double* c;       // c~ = D2 c
+  const double* l;       // l~ = l / D2
+  const double* u;       // u~ = u / D2
+  const double* q;       // q~ = D1 q
+  const double* c0;      // the user's c, l, u, q
+  const double* l0;
+  const double* u0;
+  const double* q0;
+  const double* D1;
+  const double* D2;
+  double* X[2];          // current / next primal iterate (parity-selected)
+  double* Y[2];
+  double* KX[2];         // K~ x of X[.]
+  double* KTy;           // K~^T y of the current y (valid when DevState.kty_valid)
+  double* Sx;            // eta-weighted sums since the last restart
+  double* Sy;
+  double* XB;            // averages and their products (restart checks)
+  double* YB;
+  double* KXB;
+  double* KTYB;
+  double* XA;            // anchor z^{n,0}
+  double* YA;
+  double* GA[2];         // normalized-gap scratch, n + m each: |a_i| and b_i
+  double* GB[2];
+  pdlp_attempt_rec* att; // trace logs
+  pdlp_check_rec* chk;
+  double* tx;
+  double* ty;
+};
+
+enum Pred : int {
+  kPredAlways = 0,
+  kPredCheck = 1,
+  kPredCheckKty = 2,
+  kPredKty = 3,
+  kPredCheckRestart = 4
+};
+
+}  // namespace pdlp

@@ -1,0 +1,94 @@
+// Internal layout shared by the host driver and the gfx950 kernels of the PDLP solver.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace pdlp {
+
+constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
+constexpr int kStreamNnz = 2048;       // nonzeros staged through LDS per row block
+constexpr int kPerThread = kStreamNnz / kBlock;
+constexpr int kMaxLanesRow = 64;       // widest lane group of a staged row (one wavefront)
+constexpr int kVectorMax = 16384;      // longest row one workgroup reduces alone
+constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
+
+enum DescKind : int32_t { kStream = 0, kVector = 1, kSplit = 2 };
+
+// One unit of SpMV work for a workgroup.
+struct RowDesc {
+  int32_t row0;     // first row (kStream) or the row (kVector, kSplit)
+  int32_t count;    // rows (kStream) or chunk index (kSplit)
+  int32_t kind_l;   // kind | log2(lanes per row) << 8
+  int32_t aux;      // split id (kSplit)
+};
+
+struct Schedule {
+  std::vector<RowDesc> desc;
+  std::vector<int32_t> split_row;      // per split id: the row
+  std::vector<int32_t> split_nchunks;  // per split id: number of chunks
+  std::vector<int32_t> split_base;     // per split id: offset into the chunk-partial table
+  int64_t total_chunks = 0;
+};
+
+Schedule build_schedule(const int64_t* row_ptr, int64_t nrows);
+
+// Scalar state of one solve, resident in device memory.  Kernels read it at entry; only the
+// last workgroup of a kernel (after every other workgroup has arrived) writes it.
+struct DevState {
+  double eta;            // step size of the next attempt
+  double eta_hat;        // step size proposed by the last accepted attempt
+  double omega;          // primal weight
+  double w_pending;      // step of the last accepted iterate, not yet added to the averages
+  double s_eta;          // sum of steps since the last restart
+  double mu_prev;        // candidate gap at the previous check of this outer loop
+  double mu_anchor;      // gap of the anchor vs the previous anchor
+  double mu_cur, mu_avg, mu_c;
+  double tol;
+  double kkt[4];         // KKT errors of the last evaluated point
+  double dx_norm, dy_norm;
+  double q_norm, c_norm; // of the user's (unscaled) q and c
+  // normalized-gap solves, three slots
+  double gap_r[3];
+  double gap_num[3];
+  uint64_t gap_lo[3], gap_hi[3];
+  int32_t gap_state[3];  // 0 bisecting, 1 s* = inf, 2 r = 0 (mu = 0), 3 converged
+  int32_t pad0;
+  int64_t k;             // accepted steps
+  int64_t t;             // accepted steps since the last restart
+  int64_t n_outer;       // restarts
+  int64_t attempts;
+  int64_t retries;
+  int64_t iter_limit;
+  int64_t checks;
+  int64_t spmv_K, spmv_KT;
+  int64_t n_att_log, n_chk_log, n_iter_log;
+  int32_t parity;        // which buffer of X, Y, KX holds the current iterate
+  int32_t kty_valid;     // KTy holds K~^T y for the current y
+  int32_t check_pending; // k is a multiple of check_every and the check has not run
+  int32_t done;
+  int32_t status;
+  int32_t use_avg;       // candidate of the running check is the average
+  int32_t restart;       // the running check restarts
+  int32_t mask;
+  int32_t out_avg;       // the returned point is the average buffers
+  int32_t snap_pending;  // an accepted step waits for its trace snapshot
+  int32_t check_every;
+  int32_t max_retries;
+  int32_t trace_iters;
+  int32_t trace_cap;
+  int32_t restarts_on, pw_on;
+  double beta_suff, beta_nec, beta_art, theta, eps_zero;
+};
+
+// Small record the host reads after every enqueued block.
+struct HostStatus {
+  int64_t k;
+  int64_t attempts;
+  int32_t done;
+  int32_t status;
+  int32_t check_pending;
+  int32_t pad;
+};
+
+}  // namespace pdlp

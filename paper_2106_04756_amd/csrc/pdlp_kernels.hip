@@ -1,0 +1,1085 @@
+// gfx950 kernels of the PDLP solver (float64 throughout).
+//
+// Work layout
+//  * Both K~ and its transpose are stored in CSR (int64 row offsets, int32 columns, float64
+//    values).  Every product is a gather over one CSR copy; no value atomics anywhere.
+//  * A host-built schedule cuts the rows of each copy into descriptors: runs of short rows
+//    whose nonzeros (<= 2048) are staged through LDS and reduced by 2^p lanes per row, single
+//    rows reduced by a whole workgroup, and chunks of giant rows whose partial sums are
+//    combined, in chunk order, by the last chunk to arrive.  Workgroups walk the descriptor
+//    list with a fixed grid stride, so every sum has a fixed order and two runs are bitwise equal.
+//  * Each product carries its per-row epilogue (the PDHG primal or dual update, a norm, a
+//    store) so vectors are touched once per product.
+//  * Reductions: per-thread registers -> wave64 butterflies -> LDS across the 4 waves ->
+//    one partial per workgroup -> the last workgroup to arrive (agent-scope ticket) adds the
+//    partials in slot order and applies the scalar logic (step-size rule, restart tests).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/pdlp.h"
+#include "pdlp_device.h"
+
+namespace pdlp {
+
+// ------------------------------------------------------------------------------------------
+// small device helpers
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ void st_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// True in every thread of the workgroup that arrives last at `ticket` (of `total`).
+// Writes made before the call by any workgroup are visible to the last one after it.
+__device__ bool arrive_last(unsigned* ticket, unsigned total) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    s_last = (prev + 1u == total) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+__device__ __forceinline__ void reset_ticket(unsigned* ticket) {
+  if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// Sum of N per-thread values over the workgroup; the result is valid in thread 0.
+template <int N>
+__device__ void block_sum(double (&a)[N]) {
+  __shared__ double lds[4 * (N > 0 ? N : 1)];
+#pragma unroll
+  for (int k = 0; k < N; ++k) a[k] = wave_sum(a[k]);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) lds[w * N + k] = a[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] = ((lds[k] + lds[N + k]) + lds[2 * N + k]) + lds[3 * N + k];
+  }
+  __syncthreads();
+}
+
+__device__ double block_max(double v) {
+  __shared__ double lds[4];
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) v = fmax(fmax(lds[0], lds[1]), fmax(lds[2], lds[3]));
+  __syncthreads();
+  return v;
+}
+
+// Sum over `nslot` partial slots of N values each (slot-major), value k in a[k] of thread 0.
+template <int N>
+__device__ void sum_slots(const double* part, int nslot, double (&a)[N]) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) a[k] = 0.0;
+  for (int s = threadIdx.x; s < nslot; s += kBlock) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] += ld_agent(&part[size_t(s) * N + k]);
+  }
+  block_sum<N>(a);
+}
+
+template <int N>
+__device__ __forceinline__ void write_slot(double* part, int slot, const double (&a)[N]) {
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) st_agent(&part[size_t(slot) * N + k], a[k]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// CSR row reductions driven by the schedule
+// ------------------------------------------------------------------------------------------
+
+enum ElemMode { kProd = 0, kAbsMax = 1, kAbsSum = 2 };
+
+template <int MODE>
+__device__ __forceinline__ double comb(double a, double b) {
+  if constexpr (MODE == kAbsMax) return fmax(a, b);
+  else return a + b;
+}
+
+template <int MODE>
+__device__ __forceinline__ double block_comb(double v) {
+  if constexpr (MODE == kAbsMax) return block_max(v);
+  double a[1] = {v};
+  block_sum<1>(a);
+  return a[0];
+}
+
+// Reduction of one contiguous nonzero range [p0, p1) by the whole workgroup, result in thread 0.
+template <int MODE>
+__device__ double range_reduce(const CsrDev& A, const double* __restrict__ x, int64_t p0, int64_t p1) {
+  double s = 0.0;
+  int64_t e = p0 + threadIdx.x;
+  for (; e + 3 * kBlock < p1; e += 4 * kBlock) {
+    double v0 = A.v[e], v1 = A.v[e + kBlock], v2 = A.v[e + 2 * kBlock], v3 = A.v[e + 3 * kBlock];
+    if constexpr (MODE == kProd) {
+      const int32_t c0 = A.ci[e], c1 = A.ci[e + kBlock], c2 = A.ci[e + 2 * kBlock], c3 = A.ci[e + 3 * kBlock];
+      v0 *= x[c0];
+      v1 *= x[c1];
+      v2 *= x[c2];
+      v3 *= x[c3];
+    } else {
+      v0 = fabs(v0); v1 = fabs(v1); v2 = fabs(v2); v3 = fabs(v3);
+    }
+    s = comb<MODE>(comb<MODE>(comb<MODE>(comb<MODE>(s, v0), v1), v2), v3);
+  }
+  for (; e < p1; e += kBlock) {
+    double v = A.v[e];
+    if constexpr (MODE == kProd) v *= x[A.ci[e]];
+    else v = fabs(v);
+    s = comb<MODE>(s, v);
+  }
+  return block_comb<MODE>(s);
+}
+
+// Visit every row of A once: row value s = sum_j A_rj x_j (kProd) or max/sum |A_rj|, and
+// call epi.row(r, s, contrib).  Contributions of ordinary rows go to acc (per thread); those
+// of split rows go straight to partial slot gridDim.x + split id (if part != nullptr).
+template <int MODE, class Epi>
+__device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
+                         double (&acc)[Epi::N], double* part) {
+  __shared__ double s_prod[kStreamNnz];
+  __shared__ int32_t s_rp[kBlock + 1];
+  for (int d = blockIdx.x; d < A.ndesc; d += gridDim.x) {
+    const RowDesc D = A.desc[d];
+    const int kind = D.kind_l & 0xff;
+    if (kind == kStream) {
+      const int r0 = D.row0, nr = D.count, lg = D.kind_l >> 8;
+      const int64_t p0 = A.rp[r0];
+      for (int i = threadIdx.x; i <= nr; i += kBlock) s_rp[i] = int32_t(A.rp[r0 + i] - p0);
+      __syncthreads();
+      const int cnt = s_rp[nr];
+      int32_t cc[kPerThread];
+      double vv[kPerThread];
+#pragma unroll
+      for (int j = 0; j < kPerThread; ++j) {
+        const int e = threadIdx.x + j * kBlock;
+        if (e < cnt) {
+          vv[j] = A.v[p0 + e];
+          if constexpr (MODE == kProd) cc[j] = A.ci[p0 + e];
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kPerThread; ++j) {
+        const int e = threadIdx.x + j * kBlock;
+        if (e < cnt) {
+          if constexpr (MODE == kProd) s_prod[e] = vv[j] * x[cc[j]];
+          else s_prod[e] = fabs(vv[j]);
+        }
+      }
+      __syncthreads();
+      const int L = 1 << lg, g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
+      double s = 0.0;
+      if (g < nr) {
+        const int e1 = s_rp[g + 1];
+        for (int e = s_rp[g] + lane; e < e1; e += L) s = comb<MODE>(s, s_prod[e]);
+      }
+      for (int off = L >> 1; off > 0; off >>= 1) s = comb<MODE>(s, __shfl_xor(s, off, 64));
+      if (lane == 0 && g < nr) {
+        double c[Epi::N];
+        epi.row(r0 + g, s, c);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
+      }
+      __syncthreads();
+    } else if (kind == kVector) {
+      const int r = D.row0;
+      const double s = range_reduce<MODE>(A, x, A.rp[r], A.rp[r + 1]);
+      if (threadIdx.x == 0) {
+        double c[Epi::N];
+        epi.row(r, s, c);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
+      }
+    } else {
+      const int r = D.row0, ch = D.count, sid = D.aux;
+      const int64_t q0 = A.rp[r] + int64_t(ch) * kChunk;
+      const int64_t q1 = min(A.rp[r + 1], q0 + int64_t(kChunk));
+      const double s = range_reduce<MODE>(A, x, q0, q1);
+      const int base = A.split_base[sid], nch = A.split_nchunks[sid];
+      if (threadIdx.x == 0) st_agent(&A.split_part[base + ch], s);
+      if (arrive_last(&A.split_cnt[sid], unsigned(nch))) {
+        double t = 0.0;
+        for (int c = threadIdx.x; c < nch; c += kBlock) t = comb<MODE>(t, ld_agent(&A.split_part[base + c]));
+        t = block_comb<MODE>(t);
+        if (threadIdx.x == 0) {
+          __hip_atomic_store(&A.split_cnt[sid], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          double c[Epi::N];
+          epi.row(r, t, c);
+          if (part) {
+#pragma unroll
+            for (int k = 0; k < Epi::N; ++k) st_agent(&part[size_t(gridDim.x + sid) * Epi::N + k], c[k]);
+          }
+        }
+      }
+    }
+  }
+}
+
+// Same visit with the row values read from `stored` instead of recomputed.
+template <class Epi>
+__device__ void csr_rows_stored(const CsrDev& A, const double* __restrict__ stored, const Epi& epi,
+                                double (&acc)[Epi::N], double* part) {
+  for (int d = blockIdx.x; d < A.ndesc; d += gridDim.x) {
+    const RowDesc D = A.desc[d];
+    const int kind = D.kind_l & 0xff;
+    double c[Epi::N];
+    if (kind == kStream) {
+      if (threadIdx.x < D.count) {
+        const int r = D.row0 + threadIdx.x;
+        epi.row(r, stored[r], c);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
+      }
+    } else if (kind == kVector) {
+      if (threadIdx.x == 0) {
+        epi.row(D.row0, stored[D.row0], c);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
+      }
+    } else if (D.count == 0 && threadIdx.x == 0) {
+      epi.row(D.row0, stored[D.row0], c);
+      if (part) {
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) st_agent(&part[size_t(gridDim.x + D.aux) * Epi::N + k], c[k]);
+      }
+    }
+  }
+}
+
+// Visit every nonzero of A with its (row, column): f(e, r, col).
+template <class F>
+__device__ void csr_elements(const CsrDev& A, F f) {
+  for (int d = blockIdx.x; d < A.ndesc; d += gridDim.x) {
+    const RowDesc D = A.desc[d];
+    const int kind = D.kind_l & 0xff;
+    if (kind == kStream) {
+      const int lg = D.kind_l >> 8, L = 1 << lg;
+      const int g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
+      if (g < D.count) {
+        const int r = D.row0 + g;
+        for (int64_t e = A.rp[r] + lane; e < A.rp[r + 1]; e += L) f(e, r, A.ci[e]);
+      }
+    } else {
+      const int r = D.row0;
+      int64_t q0 = A.rp[r], q1 = A.rp[r + 1];
+      if (kind == kSplit) {
+        q0 += int64_t(D.count) * kChunk;
+        q1 = min(q1, q0 + int64_t(kChunk));
+      }
+      for (int64_t e = q0 + threadIdx.x; e < q1; e += kBlock) f(e, r, A.ci[e]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// predicates on the device state
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ bool attempt_runs(const DevState& S) {
+  return !S.done && !S.check_pending && S.k < S.iter_limit;
+}
+__device__ __forceinline__ bool check_runs(const DevState& S) {
+  return !S.done && S.check_pending;
+}
+__device__ bool pred_ok(const DevState& S, int pred) {
+  switch (pred) {
+    case kPredAlways: return true;
+    case kPredCheck: return check_runs(S);
+    case kPredCheckKty: return check_runs(S) && !S.kty_valid;
+    case kPredKty: return !S.kty_valid;
+    case kPredCheckRestart: return check_runs(S) && S.restart;
+    default: return false;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// the PDHG attempt (Algorithm 2): primal step fused with K~^T y, dual step fused with K~ x'
+// ------------------------------------------------------------------------------------------
+
+// x' = proj_[l,u](x - (eta/omega)(c - K^T y))   (Eq. (3), first line)
+struct PrimalEpi {
+  static constexpr int N = 1;
+  const double* __restrict__ c;
+  const double* __restrict__ l;
+  const double* __restrict__ u;
+  const double* __restrict__ x;
+  double* __restrict__ xn;
+  double* __restrict__ sx;
+  double* __restrict__ kty;
+  double tau, w;
+  int store_kty;
+  __device__ __forceinline__ void row(int j, double s, double (&out)[1]) const {
+    if (store_kty) kty[j] = s;
+    const double xj = x[j];
+    if (w != 0.0) sx[j] = sx[j] + w * xj;          // eta-weighted sum of the last accepted iterate
+    const double g = c[j] - s;
+    double xp = xj - tau * g;
+    xp = fmin(fmax(xp, l[j]), u[j]);
+    xn[j] = xp;
+    const double d = xp - xj;
+    out[0] = d * d;
+  }
+};
+
+// y' = proj_Y(y + eta*omega (q - 2 K x' + K x))   (Eq. (3), second line, with K x cached)
+struct DualEpi {
+  static constexpr int N = 2;
+  const double* __restrict__ q;
+  const double* __restrict__ y;
+  const double* __restrict__ kx;
+  double* __restrict__ yn;
+  double* __restrict__ kxn;
+  double* __restrict__ sy;
+  double sigma, w;
+  int m1;
+  __device__ __forceinline__ void row(int i, double s, double (&out)[2]) const {
+    const double yi = y[i];
+    const double kxi = kx[i];
+    if (w != 0.0) sy[i] = sy[i] + w * yi;
+    double v = yi + sigma * (q[i] - (2.0 * s - kxi));
+    if (i < m1) v = fmax(v, 0.0);
+    yn[i] = v;
+    kxn[i] = s;
+    const double dy = v - yi;
+    out[0] = dy * dy;
+    out[1] = dy * (s - kxi);
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA,
+                                                   unsigned* ticket) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const int P = S.parity;
+  const int kty_valid = S.kty_valid;
+  PrimalEpi epi{B.c, B.l, B.u, B.X[P], B.X[P ^ 1], B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  double acc[1] = {0.0};
+  if (kty_valid) csr_rows_stored(AT, B.KTy, epi, acc, partA);
+  else csr_rows<kProd>(AT, B.Y[P], epi, acc, partA);
+  block_sum<1>(acc);
+  write_slot<1>(partA, blockIdx.x, acc);
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) {
+      if (!kty_valid) st->spmv_KT += 1;
+    }
+    reset_ticket(ticket);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B, const double* partA,
+                                                 int nslotA, double* partB, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const int P = S.parity;
+  DualEpi epi{B.q, B.Y[P], B.KX[P], B.Y[P ^ 1], B.KX[P ^ 1], B.Sy, S.eta * S.omega, S.w_pending, B.m1};
+  double acc[2] = {0.0, 0.0};
+  csr_rows<kProd>(A, B.X[P ^ 1], epi, acc, partB);
+  block_sum<2>(acc);
+  write_slot<2>(partB, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  const int nslotB = gridDim.x + A.nsplit;
+  double ax[1], ay[2];
+  sum_slots<1>(partA, nslotA, ax);
+  sum_slots<2>(partB, nslotB, ay);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  const double eta = W.eta, omega = W.omega;
+  const double dx2 = ax[0], dy2 = ay[0], cross = ay[1];
+  // Algorithm 2: the largest step Eq. (5) allows, and the next proposal
+  const double num = omega * dx2 + dy2 / omega;
+  const double den = 2.0 * fabs(cross);
+  const double eta_bar = (den > 0.0) ? num / den : INFINITY;
+  const double k2 = double(W.k + 2);   // (k + 1) with a 1-based step counter
+  const double eta_next = fmin((1.0 - pow(k2, -0.3)) * eta_bar, (1.0 + pow(k2, -0.6)) * eta);
+  const bool ok = isfinite(dx2) && isfinite(dy2) && isfinite(cross) && isfinite(eta_next);
+  const bool accepted = ok && (eta <= eta_bar);
+  if (W.trace_cap > 0) {
+    pdlp_attempt_rec& rec = B.att[W.n_att_log % W.trace_cap];
+    rec.k = W.k;
+    rec.eta = eta;
+    rec.eta_bar = eta_bar;
+    rec.accepted = accepted ? 1 : 0;
+    rec.pad = 0;
+  }
+  W.n_att_log += 1;
+  W.attempts += 1;
+  W.spmv_K += 1;
+  W.w_pending = 0.0;
+  if (!ok) {
+    W.status = PDLP_NUMERICAL_ERROR;
+    W.done = 1;
+    return;
+  }
+  if (accepted) {
+    W.parity = P ^ 1;
+    W.w_pending = eta;
+    W.s_eta += eta;
+    W.eta_hat = eta_next;
+    W.eta = eta_next;
+    W.k += 1;
+    W.t += 1;
+    W.kty_valid = 0;
+    W.retries = 0;
+    if (W.k % W.check_every == 0) W.check_pending = 1;
+    if (W.k <= W.trace_iters) W.snap_pending = 1;
+  } else {
+    W.eta = eta_next;
+    W.retries += 1;
+    W.kty_valid = 1;
+    if (W.retries >= W.max_retries) {
+      W.status = PDLP_NUMERICAL_ERROR;
+      W.done = 1;
+    }
+  }
+}
+
+// Copy of the accepted iterate for the parity trace.
+__global__ __launch_bounds__(kBlock) void k_snapshot(DevState* st, Bufs B, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!S.snap_pending) return;
+  const int P = S.parity;
+  const int64_t kk = S.k - 1;
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < B.n) B.tx[kk * B.n + idx] = B.X[P][idx];
+    else B.ty[kk * B.m + (idx - B.n)] = B.Y[P][idx - B.n];
+  }
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) {
+      st->snap_pending = 0;
+      st->n_iter_log = S.k;
+    }
+    reset_ticket(ticket);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// plain products (restart checks, initialisation, the spmv entry point)
+// ------------------------------------------------------------------------------------------
+
+struct StoreEpi {
+  static constexpr int N = 1;
+  double* __restrict__ out;
+  __device__ __forceinline__ void row(int r, double s, double (&c)[1]) const {
+    out[r] = s;
+    c[0] = 0.0;
+  }
+};
+
+__global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, DevState* st, const double* in0,
+                                                 const double* in1, int in_parity, double* out0,
+                                                 double* out1, int out_parity, int pred,
+                                                 int count_as, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!pred_ok(S, pred)) return;
+  const double* in = (in_parity && S.parity) ? in1 : in0;
+  double* out = (out_parity && S.parity) ? out1 : out0;
+  StoreEpi epi{out};
+  double acc[1] = {0.0};
+  csr_rows<kProd>(A, in, epi, acc, nullptr);
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) {
+      if (count_as == 1) st->spmv_K += 1;
+      if (count_as == 2) st->spmv_KT += 1;
+      if (pred == kPredCheckKty || pred == kPredKty) st->kty_valid = 1;
+    }
+    reset_ticket(ticket);
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// preconditioning (Section 3.5)
+// ------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_row_norms(CsrDev A, double* out, int inf_norm) {
+  StoreEpi epi{out};
+  double acc[1] = {0.0};
+  if (inf_norm) csr_rows<kAbsMax>(A, nullptr, epi, acc, nullptr);
+  else csr_rows<kAbsSum>(A, nullptr, epi, acc, nullptr);
+}
+
+// d = 1/sqrt(norm) (1 for an empty row or column), D *= d.
+__global__ __launch_bounds__(kBlock) void k_scale_factors(const double* norms, double* fac, double* D, int len) {
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < len; i += gridDim.x * kBlock) {
+    const double r = norms[i];
+    const double d = (r > 0.0) ? 1.0 / sqrt(r) : 1.0;
+    fac[i] = d;
+    D[i] = D[i] * d;
+  }
+}
+
+// K~_ij <- (K~_ij * dr_i) * dc_j, on the row-major copy (transposed = 0) or on the
+// transposed copy (transposed = 1, where the CSR row is j and the column is i); the same
+// expression keeps the two copies bitwise transposes of each other.
+__global__ __launch_bounds__(kBlock) void k_scale_values(CsrDev A, double* v, const double* dr,
+                                                         const double* dc, int transposed) {
+  csr_elements(A, [&](int64_t e, int r, int col) {
+    const int i = transposed ? col : r;
+    const int j = transposed ? r : col;
+    v[e] = (v[e] * dr[i]) * dc[j];
+  });
+}
+
+// c~ = D2 c, l~ = l / D2, u~ = u / D2, q~ = D1 q
+__global__ __launch_bounds__(kBlock) void k_scale_vectors(Bufs B, double* c, double* l, double* u, double* q) {
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < B.n) {
+      const double d = B.D2[idx];
+      c[idx] = d * B.c0[idx];
+      l[idx] = B.l0[idx] / d;
+      u[idx] = B.u0[idx] / d;
+    } else {
+      const int i = int(idx - B.n);
+      q[i] = B.D1[i] * B.q0[i];
+    }
+  }
+}
+
+// Initial point x0 = proj_X(0), y0 = 0, anchors, sums and the scalars omega, eta_hat,
+// ||c||, ||q|| (Algorithm 1 initialisation, Section 3.3 InitializePrimalWeight).
+__global__ __launch_bounds__(kBlock) void k_init(CsrDev A, DevState* st, Bufs B, double* part,
+                                                 unsigned* ticket, double primal_importance,
+                                                 double eps_zero) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};   // ||c||^2, ||q||^2, ||c~||^2, ||q~||^2
+  double vmax = 0.0;
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < B.n) {
+      const int j = int(idx);
+      const double x0 = fmin(fmax(0.0, B.l[j]), B.u[j]);
+      B.X[0][j] = x0;
+      B.X[1][j] = x0;
+      B.XA[j] = x0;
+      B.Sx[j] = 0.0;
+      B.KTy[j] = 0.0;
+      a[0] += B.c0[j] * B.c0[j];
+      a[2] += B.c[j] * B.c[j];
+    } else {
+      const int i = int(idx - B.n);
+      B.Y[0][i] = 0.0;
+      B.Y[1][i] = 0.0;
+      B.YA[i] = 0.0;
+      B.Sy[i] = 0.0;
+      a[1] += B.q0[i] * B.q0[i];
+      a[3] += B.q[i] * B.q[i];
+    }
+  }
+  const int64_t nnz = A.nrows > 0 ? A.rp[A.nrows] : 0;
+  for (int64_t e = blockIdx.x * int64_t(kBlock) + threadIdx.x; e < nnz; e += int64_t(gridDim.x) * kBlock)
+    vmax = fmax(vmax, fabs(A.v[e]));
+  block_sum<4>(a);
+  vmax = block_max(vmax);
+  double o[5] = {a[0], a[1], a[2], a[3], vmax};
+  write_slot<5>(part, blockIdx.x, o);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[4];
+  {
+    double s4[4] = {0, 0, 0, 0};
+    for (int s = threadIdx.x; s < int(gridDim.x); s += kBlock)
+      for (int k = 0; k < 4; ++k) s4[k] += ld_agent(&part[size_t(s) * 5 + k]);
+    block_sum<4>(s4);
+    for (int k = 0; k < 4; ++k) t[k] = s4[k];
+  }
+  double mx = 0.0;
+  for (int s = threadIdx.x; s < int(gridDim.x); s += kBlock) mx = fmax(mx, ld_agent(&part[size_t(s) * 5 + 4]));
+  mx = block_max(mx);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  W.c_norm = sqrt(t[0]);
+  W.q_norm = sqrt(t[1]);
+  const double nc = sqrt(t[2]), nq = sqrt(t[3]);
+  W.omega = ((nc > eps_zero && nq > eps_zero) ? nc / nq : 1.0) * primal_importance;
+  W.eta_hat = (mx > 0.0) ? 1.0 / mx : 1.0;
+  W.eta = W.eta_hat;
+}
+
+// ------------------------------------------------------------------------------------------
+// restart / termination check (Algorithm 1 every check_every accepted steps)
+// ------------------------------------------------------------------------------------------
+
+// Add the pending weighted iterate to the sums and form the averages x_bar = S_x / S_eta.
+__global__ __launch_bounds__(kBlock) void k_check_prepare(DevState* st, Bufs B, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!check_runs(S)) return;
+  const int P = S.parity;
+  const double w = S.w_pending, se = S.s_eta;
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < B.n) {
+      double s = B.Sx[idx];
+      if (w != 0.0) {
+        s = s + w * B.X[P][idx];
+        B.Sx[idx] = s;
+      }
+      B.XB[idx] = s / se;
+    } else {
+      const int i = int(idx - B.n);
+      double s = B.Sy[i];
+      if (w != 0.0) {
+        s = s + w * B.Y[P][i];
+        B.Sy[i] = s;
+      }
+      B.YB[i] = s / se;
+    }
+  }
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) st->w_pending = 0.0;
+    reset_ticket(ticket);
+  }
+}
+
+struct PointPtrs {
+  const double* x;
+  const double* y;
+  const double* kty;
+  const double* kx;
+};
+
+__device__ __forceinline__ PointPtrs current_point(const Bufs& B, int P) {
+  return PointPtrs{B.X[P], B.Y[P], B.KTy, B.KX[P]};
+}
+__device__ __forceinline__ PointPtrs average_point(const Bufs& B) {
+  return PointPtrs{B.XB, B.YB, B.KTYB, B.KXB};
+}
+
+// Normalized duality gap (Section 3.2), set-up pass: for each slot, the trust-region data
+// |a_i| and b_i (distance to the box along sign(a_i)) and the radius.
+// mode 0: slot 0 = current iterate, slot 1 = average, both against the anchor.
+// mode 1: slot 0 = the restart candidate against the old anchor (after the weight update).
+__global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int mode, double* part,
+                                                      unsigned* ticket) {
+  const DevState& S = *st;
+  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  const int P = S.parity;
+  const int ns = (mode == 0) ? 2 : 1;
+  PointPtrs pt[2];
+  if (mode == 0) {
+    pt[0] = current_point(B, P);
+    pt[1] = average_point(B);
+  } else {
+    pt[0] = S.use_avg ? average_point(B) : current_point(B, P);
+    pt[1] = pt[0];
+  }
+  const double omega = S.omega;
+  const double sw = sqrt(omega);
+  double acc[6] = {0, 0, 0, 0, 0, 0};   // per slot: sum dx^2, sum dy^2, f(inf)
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    for (int s = 0; s < ns; ++s) {
+      double a, lo, hi;
+      if (idx < B.n) {
+        const int j = int(idx);
+        const double xj = pt[s].x[j];
+        const double d = xj - B.XA[j];
+        acc[3 * s] += d * d;
+        a = -(B.c[j] - pt[s].kty[j]) / sw;
+        lo = sw * (B.l[j] - xj);
+        hi = sw * (B.u[j] - xj);
+      } else {
+        const int i = int(idx - B.n);
+        const double yi = pt[s].y[i];
+        const double d = yi - B.YA[i];
+        acc[3 * s + 1] += d * d;
+        a = sw * (B.q[i] - pt[s].kx[i]);
+        lo = (i < B.m1) ? -yi / sw : -INFINITY;
+        hi = INFINITY;
+      }
+      lo = fmin(lo, 0.0);
+      hi = fmax(hi, 0.0);
+      double aa = fabs(a), b = (a > 0.0) ? hi : -lo;
+      if (a == 0.0) {
+        aa = 0.0;
+        b = 0.0;
+      }
+      B.GA[s][idx] = aa;
+      B.GB[s][idx] = b;
+      acc[3 * s + 2] += b * b;
+    }
+  }
+  block_sum<6>(acc);
+  write_slot<6>(part, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[6];
+  sum_slots<6>(part, gridDim.x, t);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  for (int s = 0; s < ns; ++s) {
+    const double r = sqrt(omega * t[3 * s] + t[3 * s + 1] / omega);
+    W.gap_r[s] = r;
+    W.gap_lo[s] = 0;
+    W.gap_hi[s] = 0x7FF0000000000000ull;   // +inf
+    if (r == 0.0) W.gap_state[s] = 2;
+    else if (t[3 * s + 2] <= r * r) W.gap_state[s] = 1;
+    else W.gap_state[s] = 0;
+  }
+  if (mode == 1) W.gap_state[1] = 2;
+}
+
+constexpr int kGapPts = 32;
+
+__device__ __forceinline__ uint64_t gap_point(uint64_t lo, uint64_t hi, int i) {
+  const uint64_t d = hi - lo;
+  return lo + (d >> 5) * uint64_t(i) + (((d & 31ull) * uint64_t(i)) >> 5);
+}
+
+// One bisection pass over the breakpoints of ||e(s)||^2 = sum min(s|a_i|, b_i)^2: evaluate
+// it at 31 points splitting [lo, hi] (as bit patterns of positive doubles, which order like
+// the values) and keep the sub-interval where it crosses r^2.
+__global__ __launch_bounds__(kBlock) void k_gap_bisect(DevState* st, Bufs B, int mode, double* part,
+                                                       unsigned* ticket) {
+  const DevState& S = *st;
+  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  const bool act0 = S.gap_state[0] == 0;
+  const bool act1 = (mode == 0) && S.gap_state[1] == 0;
+  if (!act0 && !act1) return;
+  double sp[2][kGapPts];
+#pragma unroll
+  for (int i = 0; i < kGapPts; ++i) {
+    sp[0][i] = __longlong_as_double((long long)gap_point(S.gap_lo[0], S.gap_hi[0], i + 1));
+    sp[1][i] = __longlong_as_double((long long)gap_point(S.gap_lo[1], S.gap_hi[1], i + 1));
+  }
+  double acc[2 * kGapPts];
+#pragma unroll
+  for (int i = 0; i < 2 * kGapPts; ++i) acc[i] = 0.0;
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (act0) {
+      const double aa = B.GA[0][idx], b = B.GB[0][idx];
+      if (aa != 0.0) {
+#pragma unroll
+        for (int i = 0; i < kGapPts; ++i) {
+          const double e = fmin(sp[0][i] * aa, b);
+          acc[i] += e * e;
+        }
+      }
+    }
+    if (act1) {
+      const double aa = B.GA[1][idx], b = B.GB[1][idx];
+      if (aa != 0.0) {
+#pragma unroll
+        for (int i = 0; i < kGapPts; ++i) {
+          const double e = fmin(sp[1][i] * aa, b);
+          acc[kGapPts + i] += e * e;
+        }
+      }
+    }
+  }
+  block_sum<2 * kGapPts>(acc);
+  write_slot<2 * kGapPts>(part, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[2 * kGapPts];
+  sum_slots<2 * kGapPts>(part, gridDim.x, t);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  for (int s = 0; s < 2; ++s) {
+    if (W.gap_state[s] != 0 || (s == 1 && mode != 0)) continue;
+    const double r2 = W.gap_r[s] * W.gap_r[s];
+    const uint64_t lo = W.gap_lo[s], hi = W.gap_hi[s];
+    // entry i holds f at point i + 1 (point 32 is hi itself); point 0 is lo
+    int i = 0;
+    while (i < kGapPts && t[s * kGapPts + i] < r2) ++i;
+    if (i == kGapPts) i = kGapPts - 1;
+    const uint64_t nlo = (i == 0) ? lo : gap_point(lo, hi, i);
+    const uint64_t nhi = gap_point(lo, hi, i + 1);
+    W.gap_lo[s] = nlo;
+    W.gap_hi[s] = nhi;
+    if (nhi - nlo <= 1) W.gap_state[s] = 3;
+  }
+}
+
+// mu = a^T e(s*) / r with s* the upper end of the final bracket (or +inf).
+__global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int mode, double* part,
+                                                      unsigned* ticket) {
+  const DevState& S = *st;
+  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  const int ns = (mode == 0) ? 2 : 1;
+  double sstar[2];
+  for (int s = 0; s < 2; ++s)
+    sstar[s] = (S.gap_state[s] == 1) ? INFINITY : __longlong_as_double((long long)S.gap_hi[s]);
+  double acc[2] = {0.0, 0.0};
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    for (int s = 0; s < ns; ++s) {
+      if (S.gap_state[s] == 2) continue;
+      const double aa = B.GA[s][idx], b = B.GB[s][idx];
+      if (aa != 0.0) acc[s] += aa * (isinf(sstar[s]) ? b : fmin(sstar[s] * aa, b));
+    }
+  }
+  block_sum<2>(acc);
+  write_slot<2>(part, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[2];
+  sum_slots<2>(part, gridDim.x, t);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  double mu[2];
+  for (int s = 0; s < 2; ++s) mu[s] = (W.gap_state[s] == 2) ? 0.0 : t[s] / W.gap_r[s];
+  if (mode == 0) {
+    W.mu_cur = mu[0];
+    W.mu_avg = mu[1];
+    W.use_avg = (mu[0] < mu[1]) ? 0 : 1;    // GetRestartCandidate: a tie picks the average
+    W.mu_c = W.use_avg ? mu[1] : mu[0];
+  } else {
+    W.mu_anchor = mu[0];
+    if (W.trace_cap > 0 && W.n_chk_log > 0) B.chk[(W.n_chk_log - 1) % W.trace_cap].mu_anchor = mu[0];
+  }
+}
+
+// Relative KKT error (Section 4.1, Eq. (6a)-(6c)) of a point on the user's unscaled problem:
+// x = D2 x~, K x = (K~ x~) / D1, y = D1 y~, K^T y = (K~^T y~) / D2.
+// mode 0: the restart candidate of a check, followed by the restart decision (criteria
+//         (i)-(iii)) and the primal-weight update (Algorithm 3);
+// mode 1: the current point before the first step (termination only);
+// mode 2: the returned point after the solve stopped.
+__global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, double* part,
+                                                unsigned* ticket) {
+  const DevState& S = *st;
+  if (mode == 0 && !check_runs(S)) return;
+  const int P = S.parity;
+  const bool avg = (mode == 0) ? (S.use_avg != 0) : (mode == 2 && S.out_avg != 0);
+  const PointPtrs pt = avg ? average_point(B) : current_point(B, P);
+  // pobj, dobj (q part), dobj (bound part), primal res^2, dual res^2, |dx|^2, |dy|^2
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < B.n) {
+      const int j = int(idx);
+      const double xs = pt.x[j];
+      const double x = B.D2[j] * xs;
+      const double g = B.c0[j] - pt.kty[j] / B.D2[j];
+      const double lj = B.l0[j], uj = B.u0[j];
+      const bool lf = isfinite(lj), uf = isfinite(uj);
+      double lam = g;
+      if (!lf && !uf) lam = 0.0;
+      else if (!lf) lam = fmin(g, 0.0);
+      else if (!uf) lam = fmax(g, 0.0);
+      const double dr = g - lam;
+      a[4] += dr * dr;
+      a[0] += B.c0[j] * x;
+      double bt = 0.0;
+      if (lf) bt += lj * fmax(lam, 0.0);
+      if (uf) bt += uj * fmin(lam, 0.0);
+      a[2] += bt;
+      const double d = xs - B.XA[j];
+      a[5] += d * d;
+    } else {
+      const int i = int(idx - B.n);
+      const double ys = pt.y[i];
+      const double y = B.D1[i] * ys;
+      const double kx = pt.kx[i] / B.D1[i];
+      const double r = (i < B.m1) ? fmax(B.q0[i] - kx, 0.0) : kx - B.q0[i];
+      a[3] += r * r;
+      a[1] += B.q0[i] * y;
+      const double d = ys - B.YA[i];
+      a[6] += d * d;
+    }
+  }
+  block_sum<7>(a);
+  write_slot<7>(part, blockIdx.x, a);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[7];
+  sum_slots<7>(part, gridDim.x, t);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  const double pobj = t[0], dobj = t[1] + t[2];
+  const double e_gap = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
+  const double e_pri = sqrt(t[3]) / (1.0 + W.q_norm);
+  const double e_dual = sqrt(t[4]) / (1.0 + W.c_norm);
+  const double kkt = fmax(e_gap, fmax(e_pri, e_dual));
+  W.kkt[0] = e_gap;
+  W.kkt[1] = e_pri;
+  W.kkt[2] = e_dual;
+  W.kkt[3] = kkt;
+  const bool conv = kkt <= W.tol;   // false for NaN
+  if (mode == 1) {
+    if (conv) {
+      W.done = 1;
+      W.status = PDLP_OPTIMAL;
+      W.out_avg = 0;
+    }
+    return;
+  }
+  if (mode == 2) {
+    if (W.status == PDLP_NUMERICAL_ERROR && conv) W.status = PDLP_OPTIMAL;
+    return;
+  }
+  W.checks += 1;
+  pdlp_check_rec* rec = nullptr;
+  if (W.trace_cap > 0) {
+    rec = &B.chk[W.n_chk_log % W.trace_cap];
+    rec->k = W.k;
+    rec->mu_cur = W.restarts_on ? W.mu_cur : NAN;
+    rec->mu_avg = W.restarts_on ? W.mu_avg : NAN;
+    rec->kkt = kkt;
+    rec->use_avg = W.use_avg;
+    rec->mask = 0;
+    rec->terminated = conv ? 1 : 0;
+    rec->mu_anchor = NAN;
+    rec->pad = 0;
+  }
+  W.n_chk_log += 1;
+  if (conv) {
+    W.done = 1;
+    W.status = PDLP_OPTIMAL;
+    W.out_avg = W.use_avg;
+    W.check_pending = 0;
+    if (rec) rec->omega_after = W.omega;
+    return;
+  }
+  int mask = 0;
+  if (W.restarts_on) {
+    if (W.n_outer > 0) {
+      if (W.mu_c <= W.beta_suff * W.mu_anchor) mask |= 1;
+      if (W.mu_c <= W.beta_nec * W.mu_anchor && W.mu_c > W.mu_prev) mask |= 2;
+    }
+    if (double(W.t) >= W.beta_art * double(W.k)) mask |= 4;
+  }
+  W.mask = mask;
+  W.restart = mask != 0;
+  if (W.restart) {
+    const double dxn = sqrt(t[5]), dyn = sqrt(t[6]);
+    W.dx_norm = dxn;
+    W.dy_norm = dyn;
+    if (W.pw_on && dxn > W.eps_zero && dyn > W.eps_zero)
+      W.omega = exp(W.theta * log(dyn / dxn) + (1.0 - W.theta) * log(W.omega));
+  }
+  if (rec) {
+    rec->mask = mask;
+    rec->omega_after = W.omega;
+  }
+}
+
+// Restart (Algorithm 1): z <- z_c, anchor <- z_c, sums cleared; then close the check.
+__global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!check_runs(S)) return;
+  const int P = S.parity;
+  if (S.restart) {
+    const bool avg = S.use_avg != 0;
+    for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+         idx += int64_t(gridDim.x) * kBlock) {
+      if (idx < B.n) {
+        const int j = int(idx);
+        double xc = B.X[P][j];
+        if (avg) {
+          xc = B.XB[j];
+          B.X[P][j] = xc;
+          B.KTy[j] = B.KTYB[j];
+        }
+        B.XA[j] = xc;
+        B.Sx[j] = 0.0;
+      } else {
+        const int i = int(idx - B.n);
+        double yc = B.Y[P][i];
+        if (avg) {
+          yc = B.YB[i];
+          B.Y[P][i] = yc;
+          B.KX[P][i] = B.KXB[i];
+        }
+        B.YA[i] = yc;
+        B.Sy[i] = 0.0;
+      }
+    }
+  }
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  if (threadIdx.x != 0) return;
+  DevState& W = *st;
+  if (W.restart) {
+    W.s_eta = 0.0;
+    W.t = 0;
+    W.n_outer += 1;
+    W.mu_prev = INFINITY;
+    W.kty_valid = 1;
+  } else {
+    W.mu_prev = W.mu_c;
+  }
+  W.restart = 0;
+  W.use_avg = 0;
+  W.check_pending = 0;
+  if (W.k >= W.iter_limit) {
+    W.done = 1;
+    W.status = PDLP_ITERATION_LIMIT;
+    W.out_avg = 0;
+  }
+}
+
+// Small state edits the host makes between solves.
+__global__ void k_set_solve_params(DevState* st, double tol, int64_t iter_limit) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->tol = tol;
+    st->iter_limit = iter_limit;
+    st->done = 0;
+    st->status = PDLP_NOT_SOLVED;
+  }
+}
+
+__global__ void k_mark_limit(DevState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (!st->done && !st->check_pending && st->k >= st->iter_limit) {
+      st->done = 1;
+      st->status = PDLP_ITERATION_LIMIT;
+      st->out_avg = 0;
+    }
+  }
+}
+
+// x = D2 x~ and y = D1 y~ of the returned point (or the current iterate, scaled = 1).
+__global__ __launch_bounds__(kBlock) void k_output(const DevState* st, Bufs B, double* xo, double* yo,
+                                                   int which) {
+  const DevState& S = *st;
+  const int P = S.parity;
+  const bool avg = (which == 0) && S.out_avg;
+  const double* xs = avg ? B.XB : B.X[P];
+  const double* ys = avg ? B.YB : B.Y[P];
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
+       idx += int64_t(gridDim.x) * kBlock) {
+    if (idx < B.n) xo[idx] = (which == 0) ? B.D2[idx] * xs[idx] : xs[idx];
+    else {
+      const int i = int(idx - B.n);
+      yo[i] = (which == 0) ? B.D1[i] * ys[i] : ys[i];
+    }
+  }
+}
+
+}  // namespace pdlp

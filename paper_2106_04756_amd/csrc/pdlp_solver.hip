@@ -1,0 +1,744 @@
+// Host driver of the PDLP solver behind the C ABI of include/pdlp.h.
+//
+// pdlp_create validates the LP, builds the transposed CSR copy and the row schedules on the
+// host, uploads everything once, and preconditions on the device.  pdlp_solve enqueues
+// blocks of check_every PDHG attempts followed by one restart/termination check; every
+// kernel reads its go/no-go from the device state, so the host never waits inside a block.
+// Two blocks are kept in flight: the host reads the status record of block b-1 while block b
+// runs, and stops when that record says the solve is over.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pdlp.h"
+#include "host_prep.h"
+#include "pdlp_device.h"
+#include "pdlp_internal.h"
+#include "pdlp_kernels.hip"
+
+using namespace pdlp;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum Ticket {
+  kTkPrimal = 0, kTkDual, kTkSnap, kTkSpmv, kTkInit, kTkPrep, kTkGapSetup, kTkGapBisect,
+  kTkGapFinal, kTkKkt, kTkApply, kNumTickets
+};
+
+constexpr int kBisectPasses = 13;   // 32-way splits of the 2^63 positive doubles
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct pdlp_solver {
+  hipStream_t stream = nullptr;
+  int64_t m = 0, n = 0, n_eq = 0, nnz = 0;
+  pdlp_options opts{};
+  std::vector<void*> allocs;
+  CsrDev K{}, KT{};
+  double* vK = nullptr;
+  double* vKT = nullptr;
+  Bufs B{};
+  DevState* st = nullptr;
+  double* partA = nullptr;
+  double* partB = nullptr;
+  double* partX = nullptr;
+  unsigned* tickets = nullptr;
+  double* outbuf = nullptr;
+  int gA = 1, gB = 1, gE = 1, maxG = 1;
+  DevState* h_st = nullptr;            // pinned, two records
+  hipEvent_t blk_ev[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> tev[2];
+  double t_ms[2] = {0.0, 0.0};
+  int64_t t_cnt[2] = {0, 0};
+  std::string err;
+  bool solved = false;
+  bool initial_checked = false;
+  double create_seconds = 0.0, solve_seconds = 0.0;
+  int last_status = PDLP_NOT_SOLVED;
+  double bytes_A = 0.0, bytes_B = 0.0;
+
+  ~pdlp_solver() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) (void)hipFree(p);
+    if (h_st) (void)hipHostFree(h_st);
+    for (int b = 0; b < 2; ++b) {
+      if (blk_ev[b]) (void)hipEventDestroy(blk_ev[b]);
+      for (hipEvent_t e : tev[b]) (void)hipEventDestroy(e);
+    }
+  }
+
+  template <class T>
+  hipError_t alloc(T** p, size_t count) {
+    const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+    if (e == hipSuccess) allocs.push_back(*p);
+    return e;
+  }
+};
+
+#define PDLP_HIP(s, call)                                                                  \
+  do {                                                                                     \
+    hipError_t e_ = (call);                                                                \
+    if (e_ != hipSuccess) {                                                                \
+      (s)->err = std::string(#call) + ": " + hipGetErrorString(e_);                        \
+      return e_ == hipErrorOutOfMemory ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_DEVICE;          \
+    }                                                                                      \
+  } while (0)
+
+#define PDLP_LAUNCH(s) PDLP_HIP(s, hipGetLastError())
+
+namespace {
+
+template <class T>
+int fetch_input(pdlp_solver* s, const T* p, size_t count, std::vector<T>& tmp, const T** out) {
+  if (count == 0) {
+    *out = p;
+    return 0;
+  }
+  if (is_device_ptr(p)) {
+    tmp.resize(count);
+    PDLP_HIP(s, hipMemcpy(tmp.data(), p, count * sizeof(T), hipMemcpyDeviceToHost));
+    *out = tmp.data();
+  } else {
+    *out = p;
+  }
+  return 0;
+}
+
+int write_output(pdlp_solver* s, void* dst, const void* src_dev, size_t bytes) {
+  if (!dst || bytes == 0) return 0;
+  const hipMemcpyKind kind = is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  PDLP_HIP(s, hipMemcpyAsync(dst, src_dev, bytes, kind, s->stream));
+  PDLP_HIP(s, hipStreamSynchronize(s->stream));
+  return 0;
+}
+
+int upload_schedule(pdlp_solver* s, const Schedule& sc, int64_t nrows, CsrDev& A) {
+  RowDesc* d_desc;
+  PDLP_HIP(s, s->alloc(&d_desc, sc.desc.size()));
+  if (!sc.desc.empty())
+    PDLP_HIP(s, hipMemcpy(d_desc, sc.desc.data(), sc.desc.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
+  int32_t *nch, *base;
+  PDLP_HIP(s, s->alloc(&nch, sc.split_nchunks.size()));
+  PDLP_HIP(s, s->alloc(&base, sc.split_base.size()));
+  if (!sc.split_nchunks.empty()) {
+    PDLP_HIP(s, hipMemcpy(nch, sc.split_nchunks.data(), sc.split_nchunks.size() * 4, hipMemcpyHostToDevice));
+    PDLP_HIP(s, hipMemcpy(base, sc.split_base.data(), sc.split_base.size() * 4, hipMemcpyHostToDevice));
+  }
+  double* part;
+  unsigned* cnt;
+  PDLP_HIP(s, s->alloc(&part, size_t(sc.total_chunks)));
+  PDLP_HIP(s, s->alloc(&cnt, sc.split_row.size()));
+  PDLP_HIP(s, hipMemset(cnt, 0, std::max<size_t>(sc.split_row.size(), 1) * sizeof(unsigned)));
+  A.nrows = int32_t(nrows);
+  A.ndesc = int32_t(sc.desc.size());
+  A.desc = d_desc;
+  A.split_nchunks = nch;
+  A.split_base = base;
+  A.nsplit = int32_t(sc.split_row.size());
+  A.split_part = part;
+  A.split_cnt = cnt;
+  return 0;
+}
+
+int grid_for(const CsrDev& A, int maxG) { return std::max(1, std::min(A.ndesc, maxG)); }
+
+int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double* in1, int in_par,
+                double* out0, double* out1, int out_par, int pred, int count_as) {
+  k_spmv<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out0, out1,
+                                                       out_par, pred, count_as,
+                                                       s->tickets + kTkSpmv);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
+int enqueue_gap(pdlp_solver* s, int mode) {
+  unsigned* tk = s->tickets;
+  k_gap_setup<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, tk + kTkGapSetup);
+  PDLP_LAUNCH(s);
+  for (int p = 0; p < kBisectPasses; ++p) {
+    k_gap_bisect<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, tk + kTkGapBisect);
+    PDLP_LAUNCH(s);
+  }
+  k_gap_final<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, tk + kTkGapFinal);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
+int enqueue_block(pdlp_solver* s, int par) {
+  const pdlp_options& o = s->opts;
+  unsigned* tk = s->tickets;
+  Bufs& B = s->B;
+  const int nslotA = s->gA + s->KT.nsplit;
+  for (int i = 0; i < o.check_every; ++i) {
+    if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i], s->stream));
+    k_primal<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA, tk + kTkPrimal);
+    PDLP_LAUNCH(s);
+    if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 1], s->stream));
+    k_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partA, nslotA, s->partB, tk + kTkDual);
+    PDLP_LAUNCH(s);
+    if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 2], s->stream));
+    if (o.trace_iters > 0) {
+      k_snapshot<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkSnap);
+      PDLP_LAUNCH(s);
+    }
+  }
+  // restart / termination check
+  int rc;
+  if (o.adaptive_restarts) {
+    k_check_prepare<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkPrep);
+    PDLP_LAUNCH(s);
+    if ((rc = launch_spmv(s, s->KT, B.YB, nullptr, 0, B.KTYB, nullptr, 0, kPredCheck, 2))) return rc;
+    if ((rc = launch_spmv(s, s->K, B.XB, nullptr, 0, B.KXB, nullptr, 0, kPredCheck, 1))) return rc;
+  }
+  if ((rc = launch_spmv(s, s->KT, B.Y[0], B.Y[1], 1, B.KTy, nullptr, 0, kPredCheckKty, 2))) return rc;
+  if (o.adaptive_restarts && (rc = enqueue_gap(s, 0))) return rc;
+  k_kkt<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, 0, s->partX, tk + kTkKkt);
+  PDLP_LAUNCH(s);
+  if (o.adaptive_restarts && (rc = enqueue_gap(s, 1))) return rc;
+  k_check_apply<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkApply);
+  PDLP_LAUNCH(s);
+  PDLP_HIP(s, hipMemcpyAsync(&s->h_st[par], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+  PDLP_HIP(s, hipEventRecord(s->blk_ev[par], s->stream));
+  return 0;
+}
+
+int wait_block(pdlp_solver* s, int par) {
+  PDLP_HIP(s, hipEventSynchronize(s->blk_ev[par]));
+  if (s->opts.time_kernels) {
+    for (int i = 0; i < s->opts.check_every; ++i) {
+      float a = 0.f, b = 0.f;
+      PDLP_HIP(s, hipEventElapsedTime(&a, s->tev[par][3 * i], s->tev[par][3 * i + 1]));
+      PDLP_HIP(s, hipEventElapsedTime(&b, s->tev[par][3 * i + 1], s->tev[par][3 * i + 2]));
+      s->t_ms[0] += a;
+      s->t_ms[1] += b;
+    }
+    s->t_cnt[0] += s->opts.check_every;
+    s->t_cnt[1] += s->opts.check_every;
+  }
+  return 0;
+}
+
+bool block_stops(const DevState& h) {
+  return h.done || (!h.check_pending && h.k >= h.iter_limit);
+}
+
+int read_state(const pdlp_solver* s, DevState* out) {
+  pdlp_solver* w = const_cast<pdlp_solver*>(s);
+  PDLP_HIP(w, hipMemcpyAsync(&w->h_st[0], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+  PDLP_HIP(w, hipStreamSynchronize(s->stream));
+  *out = w->h_st[0];
+  return 0;
+}
+
+int precondition(pdlp_solver* s) {
+  const int gK = grid_for(s->K, s->maxG), gT = grid_for(s->KT, s->maxG);
+  const int gm = std::max<int64_t>(1, std::min<int64_t>((s->m + kBlock - 1) / kBlock, s->maxG));
+  const int gn = std::max<int64_t>(1, std::min<int64_t>((s->n + kBlock - 1) / kBlock, s->maxG));
+  double* rn = s->B.GA[0];
+  double* cn = s->B.GA[1];
+  double* rf = s->B.GB[0];
+  double* cf = s->B.GB[1];
+  double* D1 = const_cast<double*>(s->B.D1);
+  double* D2 = const_cast<double*>(s->B.D2);
+  const int passes = s->opts.ruiz_iters + (s->opts.pock_chambolle ? 1 : 0);
+  for (int p = 0; p < passes; ++p) {
+    const int inf_norm = (p < s->opts.ruiz_iters) ? 1 : 0;
+    k_row_norms<<<gK, kBlock, 0, s->stream>>>(s->K, rn, inf_norm);
+    PDLP_LAUNCH(s);
+    k_row_norms<<<gT, kBlock, 0, s->stream>>>(s->KT, cn, inf_norm);
+    PDLP_LAUNCH(s);
+    if (s->m > 0) {
+      k_scale_factors<<<gm, kBlock, 0, s->stream>>>(rn, rf, D1, int(s->m));
+      PDLP_LAUNCH(s);
+    }
+    k_scale_factors<<<gn, kBlock, 0, s->stream>>>(cn, cf, D2, int(s->n));
+    PDLP_LAUNCH(s);
+    k_scale_values<<<gK, kBlock, 0, s->stream>>>(s->K, s->vK, rf, cf, 0);
+    PDLP_LAUNCH(s);
+    k_scale_values<<<gT, kBlock, 0, s->stream>>>(s->KT, s->vKT, rf, cf, 1);
+    PDLP_LAUNCH(s);
+  }
+  k_scale_vectors<<<s->gE, kBlock, 0, s->stream>>>(s->B, const_cast<double*>(s->B.c),
+                                                   const_cast<double*>(s->B.l),
+                                                   const_cast<double*>(s->B.u),
+                                                   const_cast<double*>(s->B.q));
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
+int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double* c,
+                const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* q,
+                const double* l, const double* u) {
+  if (!c || !row_ptr || !l || !u || (m > 0 && !q)) {
+    s->err = "null input pointer";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  if (n < 1 || m < 0 || n_eq < 0 || n_eq > m || m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31)) {
+    s->err = "invalid sizes (need n >= 1, m >= 0, 0 <= n_eq <= m, m, n < 2^31)";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  int rc;
+  std::vector<int64_t> t_rp;
+  std::vector<int32_t> t_ci;
+  std::vector<double> t_v, t_c, t_q, t_l, t_u;
+  const int64_t* rp;
+  if ((rc = fetch_input(s, row_ptr, size_t(m) + 1, t_rp, &rp))) return rc;
+  const int64_t nnz = rp[m];
+  if (rp[0] != 0 || nnz < 0) {
+    s->err = "row_ptr[0] must be 0 and row_ptr[m] >= 0";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  if (nnz > 0 && (!col_idx || !val)) {
+    s->err = "null col_idx or val";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  const int32_t* ci;
+  const double *v, *hc, *hq, *hl, *hu;
+  if ((rc = fetch_input(s, col_idx, size_t(nnz), t_ci, &ci))) return rc;
+  if ((rc = fetch_input(s, val, size_t(nnz), t_v, &v))) return rc;
+  if ((rc = fetch_input(s, c, size_t(n), t_c, &hc))) return rc;
+  if ((rc = fetch_input(s, q, size_t(m), t_q, &hq))) return rc;
+  if ((rc = fetch_input(s, l, size_t(n), t_l, &hl))) return rc;
+  if ((rc = fetch_input(s, u, size_t(n), t_u, &hu))) return rc;
+  const std::string bad = validate_lp(m, n, n_eq, hc, rp, ci, v, hq, hl, hu);
+  if (!bad.empty()) {
+    s->err = bad;
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  s->m = m;
+  s->n = n;
+  s->n_eq = n_eq;
+  s->nnz = nnz;
+
+  std::vector<int64_t> rpT;
+  std::vector<int32_t> ciT;
+  std::vector<double> vT;
+  transpose_csr(m, n, rp, ci, v, rpT, ciT, vT);
+  const Schedule schK = build_schedule(rp, m);
+  const Schedule schT = build_schedule(rpT.data(), n);
+
+  int dev = 0;
+  PDLP_HIP(s, hipGetDevice(&dev));
+  int ncu = 0;
+  PDLP_HIP(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  s->maxG = std::max(1, ncu * 8);
+
+  // the two CSR copies
+  int64_t *d_rp, *d_rpT;
+  int32_t *d_ci, *d_ciT;
+  PDLP_HIP(s, s->alloc(&d_rp, size_t(m) + 1));
+  PDLP_HIP(s, s->alloc(&d_ci, size_t(nnz)));
+  PDLP_HIP(s, s->alloc(&s->vK, size_t(nnz)));
+  PDLP_HIP(s, s->alloc(&d_rpT, size_t(n) + 1));
+  PDLP_HIP(s, s->alloc(&d_ciT, size_t(nnz)));
+  PDLP_HIP(s, s->alloc(&s->vKT, size_t(nnz)));
+  PDLP_HIP(s, hipMemcpy(d_rp, rp, (size_t(m) + 1) * 8, hipMemcpyHostToDevice));
+  PDLP_HIP(s, hipMemcpy(d_rpT, rpT.data(), (size_t(n) + 1) * 8, hipMemcpyHostToDevice));
+  if (nnz > 0) {
+    PDLP_HIP(s, hipMemcpy(d_ci, ci, size_t(nnz) * 4, hipMemcpyHostToDevice));
+    PDLP_HIP(s, hipMemcpy(s->vK, v, size_t(nnz) * 8, hipMemcpyHostToDevice));
+    PDLP_HIP(s, hipMemcpy(d_ciT, ciT.data(), size_t(nnz) * 4, hipMemcpyHostToDevice));
+    PDLP_HIP(s, hipMemcpy(s->vKT, vT.data(), size_t(nnz) * 8, hipMemcpyHostToDevice));
+  }
+  s->K.rp = d_rp;
+  s->K.ci = d_ci;
+  s->K.v = s->vK;
+  s->KT.rp = d_rpT;
+  s->KT.ci = d_ciT;
+  s->KT.v = s->vKT;
+  if ((rc = upload_schedule(s, schK, m, s->K))) return rc;
+  if ((rc = upload_schedule(s, schT, n, s->KT))) return rc;
+  std::vector<int64_t>().swap(rpT);
+  std::vector<int32_t>().swap(ciT);
+  std::vector<double>().swap(vT);
+
+  // vectors
+  Bufs& B = s->B;
+  B.n = int32_t(n);
+  B.m = int32_t(m);
+  B.m1 = int32_t(m - n_eq);
+  const size_t N = size_t(n), M = size_t(m), NM = size_t(n + m);
+  double *c_, *l_, *u_, *q_, *c0, *l0, *u0, *q0, *D1, *D2;
+  PDLP_HIP(s, s->alloc(&c_, N));
+  PDLP_HIP(s, s->alloc(&l_, N));
+  PDLP_HIP(s, s->alloc(&u_, N));
+  PDLP_HIP(s, s->alloc(&q_, M));
+  PDLP_HIP(s, s->alloc(&c0, N));
+  PDLP_HIP(s, s->alloc(&l0, N));
+  PDLP_HIP(s, s->alloc(&u0, N));
+  PDLP_HIP(s, s->alloc(&q0, M));
+  PDLP_HIP(s, s->alloc(&D1, M));
+  PDLP_HIP(s, s->alloc(&D2, N));
+  B.c = c_; B.l = l_; B.u = u_; B.q = q_;
+  B.c0 = c0; B.l0 = l0; B.u0 = u0; B.q0 = q0;
+  B.D1 = D1; B.D2 = D2;
+  for (int p = 0; p < 2; ++p) {
+    PDLP_HIP(s, s->alloc(&B.X[p], N));
+    PDLP_HIP(s, s->alloc(&B.Y[p], M));
+    PDLP_HIP(s, s->alloc(&B.KX[p], M));
+    PDLP_HIP(s, s->alloc(&B.GA[p], NM));
+    PDLP_HIP(s, s->alloc(&B.GB[p], NM));
+  }
+  PDLP_HIP(s, s->alloc(&B.KTy, N));
+  PDLP_HIP(s, s->alloc(&B.Sx, N));
+  PDLP_HIP(s, s->alloc(&B.Sy, M));
+  PDLP_HIP(s, s->alloc(&B.XB, N));
+  PDLP_HIP(s, s->alloc(&B.YB, M));
+  PDLP_HIP(s, s->alloc(&B.KXB, M));
+  PDLP_HIP(s, s->alloc(&B.KTYB, N));
+  PDLP_HIP(s, s->alloc(&B.XA, N));
+  PDLP_HIP(s, s->alloc(&B.YA, M));
+  PDLP_HIP(s, s->alloc(&s->outbuf, NM));
+  const int cap = std::max(0, s->opts.trace_capacity);
+  PDLP_HIP(s, s->alloc(&B.att, size_t(std::max(cap, 1))));
+  PDLP_HIP(s, s->alloc(&B.chk, size_t(std::max(cap, 1))));
+  const size_t ti = size_t(std::max(0, s->opts.trace_iters));
+  PDLP_HIP(s, s->alloc(&B.tx, ti * N));
+  PDLP_HIP(s, s->alloc(&B.ty, ti * M));
+  PDLP_HIP(s, hipMemcpy(c0, hc, N * 8, hipMemcpyHostToDevice));
+  PDLP_HIP(s, hipMemcpy(l0, hl, N * 8, hipMemcpyHostToDevice));
+  PDLP_HIP(s, hipMemcpy(u0, hu, N * 8, hipMemcpyHostToDevice));
+  if (m > 0) PDLP_HIP(s, hipMemcpy(q0, hq, M * 8, hipMemcpyHostToDevice));
+  {
+    std::vector<double> ones(std::max(N, M), 1.0);
+    PDLP_HIP(s, hipMemcpy(D2, ones.data(), N * 8, hipMemcpyHostToDevice));
+    if (m > 0) PDLP_HIP(s, hipMemcpy(D1, ones.data(), M * 8, hipMemcpyHostToDevice));
+  }
+
+  // grids and reduction scratch
+  s->gA = grid_for(s->KT, s->maxG);
+  s->gB = grid_for(s->K, s->maxG);
+  s->gE = int(std::max<int64_t>(1, std::min<int64_t>(int64_t((NM + kBlock - 1) / kBlock), s->maxG)));
+  PDLP_HIP(s, s->alloc(&s->partA, size_t(s->gA + s->KT.nsplit)));
+  PDLP_HIP(s, s->alloc(&s->partB, size_t(s->gB + s->K.nsplit) * 2));
+  PDLP_HIP(s, s->alloc(&s->partX, size_t(s->gE) * 64));
+  PDLP_HIP(s, s->alloc(&s->tickets, size_t(kNumTickets)));
+  PDLP_HIP(s, hipMemset(s->tickets, 0, kNumTickets * sizeof(unsigned)));
+
+  // device state
+  DevState h{};
+  h.mu_prev = INFINITY;
+  h.mu_anchor = INFINITY;
+  h.tol = 0.0;
+  h.iter_limit = 0;
+  h.kty_valid = 1;
+  h.status = PDLP_NOT_SOLVED;
+  h.check_every = s->opts.check_every;
+  h.max_retries = s->opts.max_retries;
+  h.trace_iters = s->opts.trace_iters;
+  h.trace_cap = cap;
+  h.restarts_on = s->opts.adaptive_restarts;
+  h.pw_on = s->opts.primal_weight_update;
+  h.beta_suff = s->opts.beta_sufficient;
+  h.beta_nec = s->opts.beta_necessary;
+  h.beta_art = s->opts.beta_artificial;
+  h.theta = s->opts.theta;
+  h.eps_zero = s->opts.eps_zero;
+  PDLP_HIP(s, s->alloc(&s->st, 1));
+  PDLP_HIP(s, hipMemcpy(s->st, &h, sizeof(DevState), hipMemcpyHostToDevice));
+  PDLP_HIP(s, hipHostMalloc(reinterpret_cast<void**>(&s->h_st), 2 * sizeof(DevState), hipHostMallocDefault));
+  for (int b = 0; b < 2; ++b) {
+    PDLP_HIP(s, hipEventCreate(&s->blk_ev[b]));
+    if (s->opts.time_kernels) {
+      s->tev[b].resize(size_t(3 * s->opts.check_every));
+      for (auto& e : s->tev[b]) PDLP_HIP(s, hipEventCreate(&e));
+    }
+  }
+
+  // preconditioning, then x0 = proj_X(0), y0 = 0 and K x0
+  if ((rc = precondition(s))) return rc;
+  k_init<<<s->gE, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partX, s->tickets + kTkInit,
+                                          s->opts.primal_importance, s->opts.eps_zero);
+  PDLP_LAUNCH(s);
+  if ((rc = launch_spmv(s, s->K, B.X[0], nullptr, 0, B.KX[0], nullptr, 0, kPredAlways, 0))) return rc;
+  PDLP_HIP(s, hipStreamSynchronize(s->stream));
+
+  s->bytes_A = 8.0 * double(n + 1) + 12.0 * double(nnz) + 8.0 * double(m) + 64.0 * double(n);
+  s->bytes_B = 8.0 * double(m + 1) + 12.0 * double(nnz) + 8.0 * double(n) + 56.0 * double(m);
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+void pdlp_default_options(pdlp_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->ruiz_iters = 10;
+  o->pock_chambolle = 1;
+  o->adaptive_restarts = 1;
+  o->primal_weight_update = 1;
+  o->check_every = 40;
+  o->max_retries = 100;
+  o->trace_iters = 0;
+  o->trace_capacity = 4096;
+  o->time_kernels = 0;
+  o->beta_sufficient = 0.1;
+  o->beta_necessary = 0.9;
+  o->beta_artificial = 0.5;
+  o->theta = 0.5;
+  o->primal_importance = 1.0;
+  o->eps_zero = 1e-10;
+}
+
+int pdlp_create(pdlp_solver** out, int64_t m, int64_t n, int64_t n_eq, const double* c,
+                const int64_t* row_ptr, const int32_t* col_idx, const double* val, const double* q,
+                const double* l, const double* u, const pdlp_options* opts, void* hip_stream) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  const double t0 = now_s();
+  pdlp_solver* s = nullptr;
+  try {
+    s = new pdlp_solver();
+  } catch (...) {
+    g_create_error = "host allocation failed";
+    return PDLP_ERR_OUT_OF_MEMORY;
+  }
+  if (opts) s->opts = *opts;
+  else pdlp_default_options(&s->opts);
+  const pdlp_options& o = s->opts;
+  if (o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || o.trace_iters < 0 ||
+      o.trace_capacity < 0 || !(o.theta >= 0.0 && o.theta <= 1.0) || !(o.primal_importance > 0.0) ||
+      !(o.eps_zero >= 0.0) || !(o.beta_sufficient > 0.0) || !(o.beta_necessary > 0.0) ||
+      !(o.beta_artificial > 0.0)) {
+    g_create_error = "invalid options";
+    delete s;
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  s->stream = static_cast<hipStream_t>(hip_stream);
+  int rc;
+  try {
+    rc = create_impl(s, m, n, n_eq, c, row_ptr, col_idx, val, q, l, u);
+  } catch (const std::bad_alloc&) {
+    s->err = "host allocation failed";
+    rc = PDLP_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    s->err = "unexpected host exception";
+    rc = PDLP_ERR_DEVICE;
+  }
+  if (rc != 0) {
+    g_create_error = s->err;
+    delete s;
+    return rc;
+  }
+  s->create_seconds = now_s() - t0;
+  *out = s;
+  return 0;
+}
+
+int pdlp_solve(pdlp_solver* s, double tol, int64_t iter_limit) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  if (!(tol >= 0.0) || iter_limit < 0) {
+    s->err = "tol must be >= 0 and iter_limit >= 0";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  const double t0 = now_s();
+  int rc;
+  k_set_solve_params<<<1, 1, 0, s->stream>>>(s->st, tol, iter_limit);
+  PDLP_LAUNCH(s);
+  if (!s->initial_checked) {
+    k_kkt<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, 1, s->partX, s->tickets + kTkKkt);
+    PDLP_LAUNCH(s);
+    s->initial_checked = true;
+  }
+  DevState h;
+  if ((rc = read_state(s, &h))) return rc;
+  if (!block_stops(h)) {
+    int b = 0;
+    for (;;) {
+      if ((rc = enqueue_block(s, b & 1))) return rc;
+      if (b > 0) {
+        if ((rc = wait_block(s, (b - 1) & 1))) return rc;
+        if (block_stops(s->h_st[(b - 1) & 1])) break;
+      }
+      ++b;
+    }
+    if ((rc = wait_block(s, b & 1))) return rc;
+  }
+  k_mark_limit<<<1, 1, 0, s->stream>>>(s->st);
+  PDLP_LAUNCH(s);
+  if ((rc = read_state(s, &h))) return rc;
+  if (h.status != PDLP_OPTIMAL) {
+    // KKT error of the returned (current) point, which needs K~^T y of the current y
+    if ((rc = launch_spmv(s, s->KT, s->B.Y[0], s->B.Y[1], 1, s->B.KTy, nullptr, 0, kPredKty, 2))) return rc;
+    k_kkt<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, 2, s->partX, s->tickets + kTkKkt);
+    PDLP_LAUNCH(s);
+    if ((rc = read_state(s, &h))) return rc;
+  }
+  s->solved = true;
+  s->last_status = h.status;
+  s->solve_seconds = now_s() - t0;
+  return h.status;
+}
+
+int pdlp_get(const pdlp_solver* cs, double* x, double* y, double* kkt) {
+  if (!cs) return PDLP_ERR_INVALID_ARGUMENT;
+  pdlp_solver* s = const_cast<pdlp_solver*>(cs);
+  if (!s->solved) {
+    s->err = "pdlp_get before pdlp_solve";
+    return PDLP_ERR_INVALID_STATE;
+  }
+  int rc;
+  if (x || y) {
+    k_output<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, s->outbuf, s->outbuf + s->n, 0);
+    PDLP_LAUNCH(s);
+    if ((rc = write_output(s, x, s->outbuf, size_t(s->n) * 8))) return rc;
+    if ((rc = write_output(s, y, s->outbuf + s->n, size_t(s->m) * 8))) return rc;
+  }
+  if (kkt) {
+    DevState h;
+    if ((rc = read_state(s, &h))) return rc;
+    if (is_device_ptr(kkt)) PDLP_HIP(s, hipMemcpy(kkt, h.kkt, 4 * 8, hipMemcpyHostToDevice));
+    else std::memcpy(kkt, h.kkt, 4 * 8);
+  }
+  return 0;
+}
+
+int pdlp_get_info(const pdlp_solver* cs, pdlp_info* info) {
+  if (!cs || !info) return PDLP_ERR_INVALID_ARGUMENT;
+  DevState h;
+  int rc;
+  if ((rc = read_state(cs, &h))) return rc;
+  std::memset(info, 0, sizeof(*info));
+  info->status = cs->last_status;
+  info->output_is_average = h.out_avg;
+  info->m = cs->m;
+  info->n = cs->n;
+  info->n_eq = cs->n_eq;
+  info->nnz = cs->nnz;
+  info->iterations = h.k;
+  info->attempts = h.attempts;
+  info->restarts = h.n_outer;
+  info->checks = h.checks;
+  info->spmv_K = h.spmv_K;
+  info->spmv_KT = h.spmv_KT;
+  info->omega = h.omega;
+  info->eta_hat = h.eta_hat;
+  for (int i = 0; i < 4; ++i) info->kkt[i] = h.kkt[i];
+  info->create_seconds = cs->create_seconds;
+  info->solve_seconds = cs->solve_seconds;
+  info->step_bytes = cs->bytes_A + cs->bytes_B;
+  return 0;
+}
+
+void pdlp_destroy(pdlp_solver* s) { delete s; }
+
+const char* pdlp_last_error(const pdlp_solver* s) {
+  if (!s) return g_create_error.c_str();
+  return s->err.c_str();
+}
+
+int pdlp_get_scaling(const pdlp_solver* cs, double* D1, double* D2) {
+  if (!cs) return PDLP_ERR_INVALID_ARGUMENT;
+  pdlp_solver* s = const_cast<pdlp_solver*>(cs);
+  int rc;
+  if ((rc = write_output(s, D1, s->B.D1, size_t(s->m) * 8))) return rc;
+  if ((rc = write_output(s, D2, s->B.D2, size_t(s->n) * 8))) return rc;
+  return 0;
+}
+
+int pdlp_get_iterate(const pdlp_solver* cs, double* xs, double* ys) {
+  if (!cs) return PDLP_ERR_INVALID_ARGUMENT;
+  pdlp_solver* s = const_cast<pdlp_solver*>(cs);
+  int rc;
+  k_output<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, s->outbuf, s->outbuf + s->n, 1);
+  PDLP_LAUNCH(s);
+  if ((rc = write_output(s, xs, s->outbuf, size_t(s->n) * 8))) return rc;
+  if ((rc = write_output(s, ys, s->outbuf + s->n, size_t(s->m) * 8))) return rc;
+  return 0;
+}
+
+int pdlp_get_trace(const pdlp_solver* cs, pdlp_attempt_rec* att, int64_t att_cap, int64_t* n_att,
+                   pdlp_check_rec* chk, int64_t chk_cap, int64_t* n_chk, double* xs, double* ys,
+                   int64_t* n_iter) {
+  if (!cs) return PDLP_ERR_INVALID_ARGUMENT;
+  pdlp_solver* s = const_cast<pdlp_solver*>(cs);
+  DevState h;
+  int rc;
+  if ((rc = read_state(s, &h))) return rc;
+  const int64_t cap = h.trace_cap;
+  auto ring = [&](auto* dst, int64_t dcap, const auto* src, int64_t total) -> int {
+    using T = std::remove_pointer_t<decltype(dst)>;
+    if (!dst || cap == 0) return 0;
+    const int64_t have = std::min(total, cap);
+    const int64_t first = total - have;     // index of the oldest kept record
+    std::vector<T> tmp(static_cast<size_t>(cap));
+    PDLP_HIP(s, hipMemcpy(tmp.data(), src, size_t(cap) * sizeof(T), hipMemcpyDeviceToHost));
+    const int64_t nout = std::min(have, dcap);
+    std::vector<T> ord(size_t(std::max<int64_t>(nout, 1)));
+    for (int64_t i = 0; i < nout; ++i) ord[size_t(i)] = tmp[size_t((first + i) % cap)];
+    if (nout > 0) {
+      if (is_device_ptr(dst)) PDLP_HIP(s, hipMemcpy(dst, ord.data(), size_t(nout) * sizeof(T), hipMemcpyHostToDevice));
+      else std::memcpy(dst, ord.data(), size_t(nout) * sizeof(T));
+    }
+    return 0;
+  };
+  if ((rc = ring(att, att_cap, s->B.att, h.n_att_log))) return rc;
+  if ((rc = ring(chk, chk_cap, s->B.chk, h.n_chk_log))) return rc;
+  if (n_att) *n_att = h.n_att_log;
+  if (n_chk) *n_chk = h.n_chk_log;
+  const int64_t ni = std::min<int64_t>(h.n_iter_log, cs->opts.trace_iters);
+  if (n_iter) *n_iter = ni;
+  if (ni > 0) {
+    if ((rc = write_output(s, xs, s->B.tx, size_t(ni) * size_t(s->n) * 8))) return rc;
+    if ((rc = write_output(s, ys, s->B.ty, size_t(ni) * size_t(s->m) * 8))) return rc;
+  }
+  return 0;
+}
+
+int pdlp_spmv(pdlp_solver* s, int transpose, const double* x, double* out) {
+  if (!s || !x || !out) return PDLP_ERR_INVALID_ARGUMENT;
+  int rc;
+  const CsrDev& A = transpose ? s->KT : s->K;
+  if ((rc = launch_spmv(s, A, x, nullptr, 0, out, nullptr, 0, kPredAlways, 0))) return rc;
+  PDLP_HIP(s, hipStreamSynchronize(s->stream));
+  return 0;
+}
+
+int pdlp_kernel_times(const pdlp_solver* s, double* times_ms, int64_t* counts) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  if (times_ms) {
+    times_ms[0] = s->t_ms[0];
+    times_ms[1] = s->t_ms[1];
+  }
+  if (counts) {
+    counts[0] = s->t_cnt[0];
+    counts[1] = s->t_cnt[1];
+  }
+  return 0;
+}
+
+int pdlp_reset_kernel_times(pdlp_solver* s) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  s->t_ms[0] = s->t_ms[1] = 0.0;
+  s->t_cnt[0] = s->t_cnt[1] = 0;
+  return 0;
+}
+
+}  // extern "C"

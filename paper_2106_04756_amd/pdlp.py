@@ -1,0 +1,287 @@
+"""Python binding of the gfx950 PDLP solver (argument marshalling only).
+
+Every step of the solve runs in libpdlp_hip.so; this module converts arrays to pointers and
+structs to dicts.  Inputs may be NumPy arrays (host) or torch tensors (host or device); the
+library deep-copies them.  The solver's HIP stream defaults to torch's current stream when a
+GPU is visible.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdlp_hip.so")
+
+OPTIMAL, ITERATION_LIMIT, NUMERICAL_ERROR, NOT_SOLVED = 0, 1, 2, 3
+ERR_INVALID_ARGUMENT, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INVALID_STATE = -1, -2, -3, -4
+STATUS_NAMES = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "NUMERICAL_ERROR", 3: "NOT_SOLVED",
+                -1: "INVALID_ARGUMENT", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "INVALID_STATE"}
+
+EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_get_info",
+            "pdlp_destroy", "pdlp_last_error", "pdlp_get_scaling", "pdlp_get_iterate",
+            "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
+            "pdlp_build_schedule"]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("ruiz_iters", ctypes.c_int32), ("pock_chambolle", ctypes.c_int32),
+                ("adaptive_restarts", ctypes.c_int32), ("primal_weight_update", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("max_retries", ctypes.c_int32),
+                ("trace_iters", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("beta_sufficient", ctypes.c_double), ("beta_necessary", ctypes.c_double),
+                ("beta_artificial", ctypes.c_double), ("theta", ctypes.c_double),
+                ("primal_importance", ctypes.c_double), ("eps_zero", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("output_is_average", ctypes.c_int32),
+                ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("n_eq", ctypes.c_int64),
+                ("nnz", ctypes.c_int64), ("iterations", ctypes.c_int64),
+                ("attempts", ctypes.c_int64), ("restarts", ctypes.c_int64),
+                ("checks", ctypes.c_int64), ("spmv_K", ctypes.c_int64), ("spmv_KT", ctypes.c_int64),
+                ("omega", ctypes.c_double), ("eta_hat", ctypes.c_double),
+                ("kkt", ctypes.c_double * 4), ("create_seconds", ctypes.c_double),
+                ("solve_seconds", ctypes.c_double), ("step_bytes", ctypes.c_double)]
+
+
+class AttemptRec(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("eta", ctypes.c_double), ("eta_bar", ctypes.c_double),
+                ("accepted", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class CheckRec(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("mu_cur", ctypes.c_double), ("mu_avg", ctypes.c_double),
+                ("kkt", ctypes.c_double), ("omega_after", ctypes.c_double),
+                ("mu_anchor", ctypes.c_double), ("use_avg", ctypes.c_int32),
+                ("mask", ctypes.c_int32), ("terminated", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_lib = None
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpdlp_hip.so (built in place by paper_2106_04756_amd.build); fail loudly if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2106_04756_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.pdlp_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.pdlp_default_options.restype = None
+        L.pdlp_create.argtypes = [ctypes.POINTER(P), I64, I64, I64, P, P, P, P, P, P, P,
+                                  ctypes.POINTER(Options), P]
+        L.pdlp_create.restype = ctypes.c_int
+        L.pdlp_solve.argtypes = [P, ctypes.c_double, I64]
+        L.pdlp_solve.restype = ctypes.c_int
+        L.pdlp_get.argtypes = [P, P, P, P]
+        L.pdlp_get.restype = ctypes.c_int
+        L.pdlp_get_info.argtypes = [P, ctypes.POINTER(Info)]
+        L.pdlp_get_info.restype = ctypes.c_int
+        L.pdlp_destroy.argtypes = [P]
+        L.pdlp_destroy.restype = None
+        L.pdlp_last_error.argtypes = [P]
+        L.pdlp_last_error.restype = ctypes.c_char_p
+        L.pdlp_get_scaling.argtypes = [P, P, P]
+        L.pdlp_get_scaling.restype = ctypes.c_int
+        L.pdlp_get_iterate.argtypes = [P, P, P]
+        L.pdlp_get_iterate.restype = ctypes.c_int
+        L.pdlp_get_trace.argtypes = [P, P, I64, P, P, I64, P, P, P, P]
+        L.pdlp_get_trace.restype = ctypes.c_int
+        L.pdlp_spmv.argtypes = [P, ctypes.c_int, P, P]
+        L.pdlp_spmv.restype = ctypes.c_int
+        L.pdlp_kernel_times.argtypes = [P, P, P]
+        L.pdlp_kernel_times.restype = ctypes.c_int
+        L.pdlp_reset_kernel_times.argtypes = [P]
+        L.pdlp_reset_kernel_times.restype = ctypes.c_int
+        L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P]
+        L.pdlp_build_schedule.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+class PdlpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def default_options(**overrides) -> Options:
+    o = Options()
+    lib().pdlp_default_options(ctypes.byref(o))
+    for k, v in overrides.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a, dtype):
+    """(pointer, keep-alive) of a NumPy array or torch tensor of the given dtype."""
+    if a is None:
+        return None, None
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):          # torch tensor
+        import torch
+        tdt = {np.float64: torch.float64, np.int64: torch.int64, np.int32: torch.int32}[dtype]
+        if a.dtype != tdt or not a.is_contiguous():
+            a = a.to(tdt).contiguous()
+        return ctypes.c_void_p(a.data_ptr()), a
+    arr = np.ascontiguousarray(a, dtype=dtype)
+    return ctypes.c_void_p(arr.ctypes.data), arr
+
+
+def _default_stream():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except Exception:
+        pass
+    return None
+
+
+def schedule(row_ptr) -> tuple[np.ndarray, int]:
+    """Host-only: the SpMV row-block schedule of a CSR matrix (descriptors as an (k, 4) int32
+    array, number of split rows)."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    nd = ctypes.c_int64()
+    ns = ctypes.c_int64()
+    rc = lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, None, 0, ctypes.byref(nd), ctypes.byref(ns))
+    if rc != 0:
+        raise PdlpError(rc, "pdlp_build_schedule failed")
+    desc = np.zeros((nd.value, 4), dtype=np.int32)
+    rc = lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, desc.ctypes.data, nd.value,
+                                   ctypes.byref(nd), ctypes.byref(ns))
+    return desc, ns.value
+
+
+class Solver:
+    """One LP on the GPU.  See include/pdlp.h for the semantics of every call."""
+
+    def __init__(self, m, n, n_eq, c, row_ptr, col_idx, val, q, l, u, options: Options | None = None,
+                 stream=None, **option_overrides):
+        L = lib()
+        if options is None:
+            options = default_options(**option_overrides)
+        elif option_overrides:
+            for k, v in option_overrides.items():
+                setattr(options, k, v)
+        self.options = options
+        self.m, self.n, self.n_eq = int(m), int(n), int(n_eq)
+        keep = []
+        ptrs = []
+        for a, dt in ((c, np.float64), (row_ptr, np.int64), (col_idx, np.int32), (val, np.float64),
+                      (q, np.float64), (l, np.float64), (u, np.float64)):
+            p, k = _ptr(a, dt)
+            keep.append(k)
+            ptrs.append(p)
+        self._stream = stream if stream is not None else _default_stream()
+        h = ctypes.c_void_p()
+        rc = L.pdlp_create(ctypes.byref(h), self.m, self.n, self.n_eq, *ptrs, ctypes.byref(options),
+                           self._stream)
+        if rc != 0:
+            raise PdlpError(rc, L.pdlp_last_error(None).decode())
+        self._h = h
+
+    @classmethod
+    def from_lp(cls, lp, **kw):
+        return cls(lp.m, lp.n, lp.n_eq, lp.c, lp.row_ptr, lp.col_idx, lp.val, lp.q, lp.l, lp.u, **kw)
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PdlpError(rc, lib().pdlp_last_error(self._h).decode())
+        return rc
+
+    def solve(self, tol: float = 1e-8, iter_limit: int = 100000) -> int:
+        return self._check(lib().pdlp_solve(self._h, float(tol), int(iter_limit)))
+
+    def get(self):
+        x = np.empty(self.n)
+        y = np.empty(self.m)
+        kkt = np.empty(4)
+        self._check(lib().pdlp_get(self._h, x.ctypes.data, y.ctypes.data if self.m else None, kkt.ctypes.data))
+        return x, y, kkt
+
+    def get_into(self, x=None, y=None):
+        """Write the returned point into caller tensors / arrays (host or device)."""
+        px, kx = _ptr(x, np.float64) if x is not None else (None, None)
+        py, ky = _ptr(y, np.float64) if y is not None else (None, None)
+        self._check(lib().pdlp_get(self._h, px, py, None))
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(lib().pdlp_get_info(self._h, ctypes.byref(inf)))
+        d = {f: getattr(inf, f) for f, _ in Info._fields_}
+        d["kkt"] = list(inf.kkt)
+        return d
+
+    def scaling(self):
+        D1 = np.empty(self.m)
+        D2 = np.empty(self.n)
+        self._check(lib().pdlp_get_scaling(self._h, D1.ctypes.data if self.m else None, D2.ctypes.data))
+        return D1, D2
+
+    def iterate(self):
+        xs = np.empty(self.n)
+        ys = np.empty(self.m)
+        self._check(lib().pdlp_get_iterate(self._h, xs.ctypes.data, ys.ctypes.data if self.m else None))
+        return xs, ys
+
+    def trace(self) -> dict:
+        cap = max(int(self.options.trace_capacity), 1)
+        att = (AttemptRec * cap)()
+        chk = (CheckRec * cap)()
+        na, nc, ni = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        ti = int(self.options.trace_iters)
+        xs = np.empty((max(ti, 1), self.n))
+        ys = np.empty((max(ti, 1), max(self.m, 1)))
+        self._check(lib().pdlp_get_trace(self._h, ctypes.cast(att, P), cap, ctypes.byref(na),
+                                         ctypes.cast(chk, P), cap, ctypes.byref(nc),
+                                         xs.ctypes.data if ti else None,
+                                         ys.ctypes.data if (ti and self.m) else None,
+                                         ctypes.byref(ni)))
+        na_k = min(na.value, cap)
+        nc_k = min(nc.value, cap)
+        attempts = [(a.k, a.eta, a.eta_bar, bool(a.accepted)) for a in att[:na_k]]
+        checks = [dict(k=r.k, mu_cur=r.mu_cur, mu_avg=r.mu_avg, kkt=r.kkt, omega_after=r.omega_after,
+                       mu_anchor=r.mu_anchor, use_avg=bool(r.use_avg), mask=r.mask,
+                       terminated=bool(r.terminated)) for r in chk[:nc_k]]
+        return dict(attempts=attempts, n_attempts=na.value, checks=checks, n_checks=nc.value,
+                    xs=xs[:ni.value], ys=ys[:ni.value, :self.m], n_iter=ni.value)
+
+    def spmv(self, x, out, transpose=False):
+        """out = K~ x (or K~^T x) on device tensors."""
+        px, kx = _ptr(x, np.float64)
+        po, ko = _ptr(out, np.float64)
+        self._check(lib().pdlp_spmv(self._h, 1 if transpose else 0, px, po))
+
+    def kernel_times(self):
+        t = np.zeros(2)
+        c = np.zeros(2, dtype=np.int64)
+        self._check(lib().pdlp_kernel_times(self._h, t.ctypes.data, c.ctypes.data))
+        return t, c
+
+    def reset_kernel_times(self):
+        self._check(lib().pdlp_reset_kernel_times(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pdlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

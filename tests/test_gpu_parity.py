@@ -1,0 +1,244 @@
+"""GPU parity of the HIP solver against the CPU oracle (run on an MI355X).
+
+Every case prints what it runs before touching the GPU.  The bars:
+  * preconditioning D1, D2 and the products: relative 1e-13 (round-off of sums in another order);
+  * the first 100 accepted iterates: relative 1e-11 per iterate, separately for x and y, and
+    identical accept/reject, candidate and restart decisions;
+  * a full solve: the oracle's own KKT evaluation of the GPU's answer <= 1e-8 and the
+    objective matching HiGHS;
+  * integer-like outcomes (status, counts, decisions): exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+from scipy.optimize import linprog
+
+import paper_2106_04756_amd as P
+from oracle import pdlp_oracle as O
+from workloads import lpgen
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    P.lib()
+
+
+def make(lp, **kw):
+    return P.Solver.from_lp(lp, **kw)
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+# ------------------------------------------------------------------------------------------
+
+def test_spmv_matches_scipy_on_ragged_shapes():
+    """Unscaled products (no preconditioning) on every schedule path: short rows staged in
+    LDS, wavefront-sized rows, one-workgroup rows, split giant rows, empty rows/columns."""
+    import torch
+    rng = np.random.default_rng(5)
+    m, n = 3000, 70000
+    lens = np.concatenate([rng.poisson(3, m - 6), [0, 600, 5000, 16385, 40000, 70000]])
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        cs = rng.choice(n, size=min(ln, n), replace=False)
+        rows.append(np.full(cs.size, i))
+        cols.append(cs)
+    K = sp.csr_matrix((rng.standard_normal(int(lens.sum())), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(m, n))
+    K.sort_indices()
+    lp = lpgen.from_csr(K, np.ones(n), np.zeros(m), np.zeros(n), np.full(n, 1.0), n_eq=0)
+    say("spmv ragged", m, n, K.nnz)
+    s = make(lp, ruiz_iters=0, pock_chambolle=0)
+    for trial in range(2):
+        x = rng.standard_normal(n)
+        y = rng.standard_normal(m)
+        out = torch.empty(m, dtype=torch.float64, device="cuda")
+        s.spmv(torch.from_numpy(x).cuda(), out)
+        ref = K @ x
+        scale = abs(K) @ np.abs(x)
+        assert np.all(np.abs(out.cpu().numpy() - ref) <= 1e-13 * scale + 1e-300)
+        outT = torch.empty(n, dtype=torch.float64, device="cuda")
+        s.spmv(torch.from_numpy(y).cuda(), outT, transpose=True)
+        refT = K.T @ y
+        scaleT = abs(K.T) @ np.abs(y)
+        assert np.all(np.abs(outT.cpu().numpy() - refT) <= 1e-13 * scaleT + 1e-300)
+
+
+def test_preconditioning_matches_oracle():
+    for lp in (lpgen.config0(), lpgen.large_plain(11, 2000, 4000), lpgen.pagerank_lp(2, 30000)):
+        say("scaling", lp.name, lp.m, lp.n, lp.nnz)
+        s = make(lp)
+        D1, D2 = s.scaling()
+        _, _, _, _, _, oD1, oD2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
+        assert np.max(np.abs(D1 / oD1 - 1)) < 1e-13
+        assert np.max(np.abs(D2 / oD2 - 1)) < 1e-13
+
+
+def _trajectory_parity(lp, iters=100, opts=None, **kw):
+    opts = opts or O.Options()
+    say("trajectory", lp.name, lp.m, lp.n, lp.nnz, kw)
+    s = make(lp, trace_iters=iters, **kw)
+    st = s.solve(1e-30, iters)
+    assert st == P.ITERATION_LIMIT
+    tr = s.trace()
+    ref = O.solve_lp(lp, tol=1e-30, iter_limit=iters, opts=opts, trace_iters=iters)
+    assert tr["n_iter"] == iters == len(ref.trace.iterates)
+    worst = 0.0
+    for k in range(iters):
+        kk, xo, yo = ref.trace.iterates[k]
+        ex = rel(tr["xs"][k], xo)
+        ey = rel(tr["ys"][k], yo) if lp.m else 0.0
+        worst = max(worst, ex, ey)
+        assert ex <= 1e-11 and ey <= 1e-11, (k + 1, ex, ey)
+    ga = tr["attempts"]
+    oa = ref.trace.attempts
+    assert len(ga) == len(oa)
+    for g, o in zip(ga, oa):
+        assert g[0] == o[0] and g[3] == o[3]
+        assert abs(g[1] - o[1]) <= 1e-11 * o[1]
+        if math.isfinite(o[2]):
+            assert abs(g[2] - o[2]) <= 1e-9 * o[2]
+    gc, oc = tr["checks"], ref.trace.checks
+    assert len(gc) == len(oc)
+    for g, o in zip(gc, oc):
+        assert g["k"] == o["k"] and g["use_avg"] == o["use_avg"] and g["mask"] == o["mask"]
+        assert abs(g["omega_after"] - o["omega_after"]) <= 1e-11 * o["omega_after"]
+        for key in ("mu_cur", "mu_avg"):
+            if math.isfinite(o[key]):
+                assert abs(g[key] - o[key]) <= 1e-9 * max(abs(o[key]), 1e-300), key
+    return worst
+
+
+def test_trajectory_parity_config0():
+    _trajectory_parity(lpgen.config0())
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_trajectory_parity_other_small_lps(seed):
+    _trajectory_parity(lpgen.large_plain(seed + 20, 400, 900))
+    _trajectory_parity(lpgen.add_empty_row_and_column(lpgen.tiny_plain(seed, 150, 300, 60, 4)))
+
+
+def test_trajectory_parity_pagerank_small():
+    _trajectory_parity(lpgen.pagerank_lp(2, 20000))
+
+
+def test_solve_config0_to_1e8():
+    lp = lpgen.config0()
+    say("solve config0")
+    s = make(lp)
+    st = s.solve(1e-8, 100000)
+    assert st == P.OPTIMAL
+    x, y, kkt = s.get()
+    k = O.kkt(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, x, y)
+    assert k["kkt"] <= 1e-8
+    assert abs(k["kkt"] - kkt[3]) <= 1e-10
+    K = lp.K()
+    res = linprog(lp.c, A_ub=-K[:lp.m1], b_ub=-lp.q[:lp.m1], A_eq=K[lp.m1:], b_eq=lp.q[lp.m1:],
+                  bounds=list(zip(lp.l, lp.u)), method="highs")
+    assert abs(k["pobj"] - res.fun) <= 1e-7 * abs(res.fun)
+    ref = O.solve_lp(lp, tol=1e-8)
+    info = s.info()
+    # beyond the first iterates the two trajectories may part on a near-tie; the work to
+    # reach 1e-8 stays of the same size
+    assert 0.5 * ref.k <= info["iterations"] <= 2 * ref.k
+
+
+def test_solve_pagerank_matches_stationary_vector():
+    N = 20000
+    lp = lpgen.pagerank_lp(2, N)
+    say("solve pagerank", N)
+    s = make(lp)
+    assert s.solve(1e-8, 200000) == P.OPTIMAL
+    x, y, kkt = s.get()
+    K = lp.K()
+    assert O.kkt(lp.c, K, lp.q, lp.l, lp.u, lp.n_eq, x, y)["kkt"] <= 1e-8
+    S = -(K[:N, :N] - sp.eye(N)) / 0.85
+    pi = np.full(N, 1.0 / N)
+    for _ in range(400):
+        pi = 0.85 * (S @ pi) + 0.15 / N
+    assert np.abs(x - pi).sum() < 1e-6
+
+
+def test_two_runs_are_bitwise_equal_and_resume_is_seamless():
+    lp = lpgen.large_plain(31, 3000, 7000)
+    say("determinism", lp.nnz)
+    a = make(lp)
+    b = make(lp)
+    a.solve(1e-30, 300)
+    b.solve(1e-30, 120)
+    b.solve(1e-30, 300)          # resume from k = 120
+    xa, ya = a.iterate()
+    xb, yb = b.iterate()
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    ia, ib = a.info(), b.info()
+    assert ia["iterations"] == ib["iterations"] == 300 and ia["omega"] == ib["omega"]
+
+
+def test_edge_cases():
+    # no constraints at all: min c^T x over a box
+    n = 7
+    c = np.array([1.0, -2.0, 0.5, -0.1, 3.0, -4.0, 0.0])
+    lp = lpgen.LP(m=0, n=n, n_eq=0, c=c, row_ptr=np.zeros(1, np.int64), col_idx=np.zeros(0, np.int32),
+                  val=np.zeros(0), q=np.zeros(0), l=-np.ones(n), u=2 * np.ones(n))
+    say("edge m=0")
+    s = make(lp)
+    assert s.solve(1e-10, 10000) == P.OPTIMAL
+    x, _, kkt = s.get()
+    np.testing.assert_allclose(x, np.where(c > 0, -1.0, np.where(c < 0, 2.0, x)), atol=1e-9)
+    # only equalities, and only inequalities
+    base = lpgen.tiny_plain(3, 60, 150, 0, 4)
+    say("edge all equalities")
+    s = make(base)
+    assert s.solve(1e-8, 200000) == P.OPTIMAL
+    base2 = lpgen.tiny_plain(4, 60, 150, 60, 4)
+    say("edge all inequalities")
+    s = make(base2)
+    assert s.solve(1e-8, 200000) == P.OPTIMAL
+    # iteration limit 0 and tolerance 0
+    say("edge limits")
+    s = make(lpgen.config0())
+    assert s.solve(1e-8, 0) == P.ITERATION_LIMIT
+    assert s.info()["iterations"] == 0
+    assert s.solve(0.0, 57) == P.ITERATION_LIMIT
+    assert s.info()["iterations"] == 57
+    _, _, kkt = s.get()
+    assert np.all(np.isfinite(kkt))
+
+
+def test_get_before_solve_and_device_outputs():
+    import torch
+    lp = lpgen.config0()
+    say("api states")
+    s = make(lp)
+    with pytest.raises(P.PdlpError):
+        s.get()
+    s.solve(1e-8, 200)
+    x, y, _ = s.get()
+    xd = torch.empty(lp.n, dtype=torch.float64, device="cuda")
+    yd = torch.empty(lp.m, dtype=torch.float64, device="cuda")
+    s.get_into(xd, yd)
+    assert np.array_equal(xd.cpu().numpy(), x) and np.array_equal(yd.cpu().numpy(), y)
+    # device-pointer inputs give the same solver
+    t = {k: torch.from_numpy(np.asarray(getattr(lp, k))).cuda() for k in
+         ("c", "row_ptr", "col_idx", "val", "q", "l", "u")}
+    s2 = P.Solver(lp.m, lp.n, lp.n_eq, t["c"], t["row_ptr"], t["col_idx"], t["val"], t["q"], t["l"], t["u"])
+    s2.solve(1e-8, 200)
+    x2, y2, _ = s2.get()
+    assert np.array_equal(x, x2) and np.array_equal(y, y2)
