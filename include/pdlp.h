@@ -92,6 +92,19 @@ typedef struct pdlp_info {
   double step_bytes;             /* algorithmic HBM bytes of one accepted PDHG step           */
 } pdlp_info;
 
+/* Scalars of a checkpoint (pdlp_get_state / pdlp_set_state). */
+typedef struct pdlp_state {
+  int64_t k;                     /* accepted steps                                            */
+  int64_t t;                     /* accepted steps since the last restart                     */
+  int64_t n_outer;               /* restarts so far                                           */
+  double eta_hat;                /* step size the next step starts from                       */
+  double omega;                  /* primal weight                                             */
+  double s_eta;                  /* sum of the steps of the iterates in the average           */
+  double mu_prev;                /* candidate gap at the previous check (+inf after a restart)*/
+  double mu_anchor;              /* gap of the anchor vs the previous anchor (+inf before the
+                                    first restart)                                            */
+} pdlp_state;
+
 /* One Algorithm-2 attempt, as logged by the solver. */
 typedef struct pdlp_attempt_rec {
   int64_t k;                     /* accepted steps before this attempt                        */
@@ -166,6 +179,23 @@ void pdlp_destroy(pdlp_solver *s);
 const char *pdlp_last_error(const pdlp_solver *s);
 
 /* ---- inspection entry points (parity tests and measurement) ---------------------------- */
+
+/*
+ * pdlp_get_state - checkpoint of Algorithm 1 before its next step, in the preconditioned
+ * variables: the iterate x~ (n values), y~ (m), the anchor z^{n,0} xa (n), ya (m), the
+ * step-weighted sums of the iterates since the last restart sx (n), sy (m) (the average is
+ * sx / s_eta), and the scalars in *st.  Any pointer may be NULL.
+ */
+int pdlp_get_state(const pdlp_solver *s, double *x, double *y, double *xa, double *ya,
+                   double *sx, double *sy, pdlp_state *st);
+
+/*
+ * pdlp_set_state - resume Algorithm 1 from a checkpoint with the layout of pdlp_get_state
+ * (all six vectors and st are required).  The next pdlp_solve continues from it without a
+ * new termination check at its start.  Used for warm starts and for replaying single steps.
+ */
+int pdlp_set_state(pdlp_solver *s, const double *x, const double *y, const double *xa,
+                   const double *ya, const double *sx, const double *sy, const pdlp_state *st);
 
 /* pdlp_get_scaling - the diagonal preconditioners: D1 (m values) and D2 (n values), with
  * K~ = D1 K D2 (Section 3.5). */

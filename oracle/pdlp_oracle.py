@@ -65,6 +65,7 @@ class Trace:
     attempts: list = field(default_factory=list)   # (k, eta, eta_bar, accepted)
     iterates: list = field(default_factory=list)   # (k, x_scaled, y_scaled) after accepted steps
     checks: list = field(default_factory=list)     # dicts, one per restart/termination check
+    states: list = field(default_factory=list)     # full solver state before each step (if asked)
     trace_iters: int = 0
 
 
@@ -372,7 +373,7 @@ def power_iteration_norm(K, iters, seed=0) -> float:
 # ------------------------------------------------------------------------------------------
 
 def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None = None,
-          trace_iters: int = 0, record_trace: bool = False) -> Result:
+          trace_iters: int = 0, record_trace: bool = False, record_states: int = 0) -> Result:
     """Algorithm 1 after preconditioning: adaptive steps (Algorithm 2), eta-weighted
     averages, restart candidate, restart criteria, primal weight updates (Algorithm 3).
 
@@ -383,7 +384,11 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
     (reading Z15).  eta_hat is carried across restarts (Z7).  The average covers the
     iterates accepted since the last restart, weighted by the step each was taken with (Z20).
     After a restart mu_anchor = mu(z^{n,0}, z^{n-1,0}) is computed with the updated primal
-    weight (Z10).  At the iteration limit the current iterate is returned."""
+    weight (Z10).  At the iteration limit the current iterate is returned.
+
+    record_states = K keeps, for k = 0..K, the complete state the loop holds before taking
+    step k + 1 (iterate, anchor, weighted sums, step size, primal weight, counters, gap
+    memory), so a single step can be replayed from it."""
     opts = opts or Options()
     K = sp.csr_matrix(K, dtype=np.float64)
     m, n = K.shape
@@ -396,7 +401,7 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
     Kt, ct, qt, lt, ut, D1, D2 = precondition(K, c, q, l, u, opts.ruiz_iters,
                                               opts.pock_chambolle, opts.pc_alpha)
     KtT = Kt.T.tocsr()
-    tr = Trace(trace_iters=trace_iters) if (record_trace or trace_iters > 0) else None
+    tr = Trace(trace_iters=trace_iters) if (record_trace or trace_iters > 0 or record_states) else None
 
     def unscaled_kkt(xs, ys):
         return kkt(c, K, q, l, u, n_eq, D2 * xs, D1 * ys)
@@ -432,6 +437,11 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
         return finish(OPTIMAL, x, y)
 
     while True:
+        if tr is not None and k <= record_states and (not tr.states or tr.states[-1]["k"] != k):
+            tr.states.append(dict(k=k, t=t, n_outer=n_outer, x=x.copy(), y=y.copy(), xa=xa.copy(),
+                                  ya=ya.copy(), Sx=Sx.copy(), Sy=Sy.copy(), Seta=Seta,
+                                  eta_hat=eta_hat, omega=omega, mu_prev=mu_prev,
+                                  mu_anchor=mu_anchor))
         if k >= iter_limit:
             return finish(ITERATION_LIMIT, x, y)
         # ---- AdaptiveStepOfPDHG (Algorithm 2) ----
@@ -525,7 +535,8 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
         rec["omega_after"] = omega
 
 
-def solve_lp(lp, tol=1e-8, iter_limit=100000, opts=None, trace_iters=0, record_trace=False):
+def solve_lp(lp, tol=1e-8, iter_limit=100000, opts=None, trace_iters=0, record_trace=False,
+             record_states=0):
     """solve() on a workloads.lpgen.LP."""
     return solve(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, tol, iter_limit, opts,
-                 trace_iters, record_trace)
+                 trace_iters, record_trace, record_states)

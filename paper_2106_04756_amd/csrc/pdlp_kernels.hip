@@ -1044,6 +1044,33 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, un
   }
 }
 
+// Resume from a checkpoint: vectors already copied into X[0], Y[0], XA, YA, Sx, Sy.
+__global__ void k_set_state(DevState* st, pdlp_state v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    DevState& W = *st;
+    W.k = v.k;
+    W.t = v.t;
+    W.n_outer = v.n_outer;
+    W.eta_hat = v.eta_hat;
+    W.eta = v.eta_hat;
+    W.omega = v.omega;
+    W.s_eta = v.s_eta;
+    W.mu_prev = v.mu_prev;
+    W.mu_anchor = v.mu_anchor;
+    W.w_pending = 0.0;
+    W.parity = 0;
+    W.kty_valid = 0;
+    W.check_pending = 0;
+    W.done = 0;
+    W.status = PDLP_NOT_SOLVED;
+    W.retries = 0;
+    W.restart = 0;
+    W.use_avg = 0;
+    W.out_avg = 0;
+    W.snap_pending = 0;
+  }
+}
+
 // Small state edits the host makes between solves.
 __global__ void k_set_solve_params(DevState* st, double tol, int64_t iter_limit) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {

@@ -654,6 +654,76 @@ const char* pdlp_last_error(const pdlp_solver* s) {
   return s->err.c_str();
 }
 
+int pdlp_get_state(const pdlp_solver* cs, double* x, double* y, double* xa, double* ya, double* sx,
+                   double* sy, pdlp_state* out) {
+  if (!cs) return PDLP_ERR_INVALID_ARGUMENT;
+  pdlp_solver* s = const_cast<pdlp_solver*>(cs);
+  DevState h;
+  int rc;
+  if ((rc = read_state(s, &h))) return rc;
+  const int P = h.parity;
+  const size_t N = size_t(s->n), M = size_t(s->m);
+  std::vector<double> hx(N), hy(M), hsx(N), hsy(M);
+  PDLP_HIP(s, hipMemcpy(hx.data(), s->B.X[P], N * 8, hipMemcpyDeviceToHost));
+  if (M) PDLP_HIP(s, hipMemcpy(hy.data(), s->B.Y[P], M * 8, hipMemcpyDeviceToHost));
+  PDLP_HIP(s, hipMemcpy(hsx.data(), s->B.Sx, N * 8, hipMemcpyDeviceToHost));
+  if (M) PDLP_HIP(s, hipMemcpy(hsy.data(), s->B.Sy, M * 8, hipMemcpyDeviceToHost));
+  // the last accepted iterate may still be waiting to enter the sums
+  if (h.w_pending != 0.0) {
+    for (size_t j = 0; j < N; ++j) hsx[j] = hsx[j] + h.w_pending * hx[j];
+    for (size_t i = 0; i < M; ++i) hsy[i] = hsy[i] + h.w_pending * hy[i];
+  }
+  auto put = [&](double* dst, const double* src, size_t cnt) -> int {
+    if (!dst || cnt == 0) return 0;
+    if (is_device_ptr(dst)) PDLP_HIP(s, hipMemcpy(dst, src, cnt * 8, hipMemcpyHostToDevice));
+    else std::memcpy(dst, src, cnt * 8);
+    return 0;
+  };
+  if ((rc = put(x, hx.data(), N)) || (rc = put(y, hy.data(), M)) || (rc = put(sx, hsx.data(), N)) ||
+      (rc = put(sy, hsy.data(), M)))
+    return rc;
+  if ((rc = write_output(s, xa, s->B.XA, N * 8))) return rc;
+  if ((rc = write_output(s, ya, s->B.YA, M * 8))) return rc;
+  if (out) {
+    out->k = h.k;
+    out->t = h.t;
+    out->n_outer = h.n_outer;
+    out->eta_hat = h.eta_hat;
+    out->omega = h.omega;
+    out->s_eta = h.s_eta;
+    out->mu_prev = h.mu_prev;
+    out->mu_anchor = h.mu_anchor;
+  }
+  return 0;
+}
+
+int pdlp_set_state(pdlp_solver* s, const double* x, const double* y, const double* xa,
+                   const double* ya, const double* sx, const double* sy, const pdlp_state* v) {
+  if (!s || !x || !xa || !sx || !v || (s->m > 0 && (!y || !ya || !sy))) return PDLP_ERR_INVALID_ARGUMENT;
+  if (v->k < 0 || v->t < 0 || v->t > v->k || v->n_outer < 0 || !(v->eta_hat > 0.0) ||
+      !(v->omega > 0.0) || !(v->s_eta >= 0.0) || !std::isfinite(v->eta_hat) || !std::isfinite(v->omega)) {
+    s->err = "invalid checkpoint scalars";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  const size_t N = size_t(s->n), M = size_t(s->m);
+  auto get = [&](double* dst, const double* src, size_t cnt) -> int {
+    if (cnt == 0) return 0;
+    const hipMemcpyKind kind = is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    PDLP_HIP(s, hipMemcpyAsync(dst, src, cnt * 8, kind, s->stream));
+    return 0;
+  };
+  int rc;
+  if ((rc = get(s->B.X[0], x, N)) || (rc = get(s->B.Y[0], y, M)) || (rc = get(s->B.XA, xa, N)) ||
+      (rc = get(s->B.YA, ya, M)) || (rc = get(s->B.Sx, sx, N)) || (rc = get(s->B.Sy, sy, M)))
+    return rc;
+  k_set_state<<<1, 1, 0, s->stream>>>(s->st, *v);
+  PDLP_LAUNCH(s);
+  if ((rc = launch_spmv(s, s->K, s->B.X[0], nullptr, 0, s->B.KX[0], nullptr, 0, kPredAlways, 0))) return rc;
+  PDLP_HIP(s, hipStreamSynchronize(s->stream));
+  s->initial_checked = true;
+  return 0;
+}
+
 int pdlp_get_scaling(const pdlp_solver* cs, double* D1, double* D2) {
   if (!cs) return PDLP_ERR_INVALID_ARGUMENT;
   pdlp_solver* s = const_cast<pdlp_solver*>(cs);

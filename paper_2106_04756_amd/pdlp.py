@@ -21,7 +21,8 @@ STATUS_NAMES = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "NUMERICAL_ERROR", 3: "NO
                 -1: "INVALID_ARGUMENT", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "INVALID_STATE"}
 
 EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_get_info",
-            "pdlp_destroy", "pdlp_last_error", "pdlp_get_scaling", "pdlp_get_iterate",
+            "pdlp_destroy", "pdlp_last_error", "pdlp_get_state", "pdlp_set_state",
+            "pdlp_get_scaling", "pdlp_get_iterate",
             "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
             "pdlp_build_schedule"]
 
@@ -48,6 +49,12 @@ class Info(ctypes.Structure):
                 ("solve_seconds", ctypes.c_double), ("step_bytes", ctypes.c_double)]
 
 
+class State(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("t", ctypes.c_int64), ("n_outer", ctypes.c_int64),
+                ("eta_hat", ctypes.c_double), ("omega", ctypes.c_double), ("s_eta", ctypes.c_double),
+                ("mu_prev", ctypes.c_double), ("mu_anchor", ctypes.c_double)]
+
+
 class AttemptRec(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("eta", ctypes.c_double), ("eta_bar", ctypes.c_double),
                 ("accepted", ctypes.c_int32), ("pad", ctypes.c_int32)]
@@ -69,6 +76,12 @@ def lib() -> ctypes.CDLL:
     """Load libpdlp_hip.so (built in place by paper_2106_04756_amd.build); fail loudly if absent."""
     global _lib
     if _lib is None:
+        # Load torch's HIP runtime first so the library and torch share one runtime (the
+        # library links libamdhip64.so.7 by soname and binds to the copy already loaded).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2106_04756_amd.build`")
         L = ctypes.CDLL(LIB_PATH)
@@ -87,6 +100,10 @@ def lib() -> ctypes.CDLL:
         L.pdlp_destroy.restype = None
         L.pdlp_last_error.argtypes = [P]
         L.pdlp_last_error.restype = ctypes.c_char_p
+        L.pdlp_get_state.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(State)]
+        L.pdlp_get_state.restype = ctypes.c_int
+        L.pdlp_set_state.argtypes = [P, P, P, P, P, P, P, ctypes.POINTER(State)]
+        L.pdlp_set_state.restype = ctypes.c_int
         L.pdlp_get_scaling.argtypes = [P, P, P]
         L.pdlp_get_scaling.restype = ctypes.c_int
         L.pdlp_get_iterate.argtypes = [P, P, P]
@@ -219,6 +236,32 @@ class Solver:
         d = {f: getattr(inf, f) for f, _ in Info._fields_}
         d["kkt"] = list(inf.kkt)
         return d
+
+    _STATE_KEYS = ("k", "t", "n_outer", "eta_hat", "omega", "s_eta", "mu_prev", "mu_anchor")
+
+    def get_state(self) -> dict:
+        """Checkpoint in the preconditioned variables (see pdlp_get_state)."""
+        n, m = self.n, self.m
+        v = {k: np.empty(n if k in ("x", "xa", "Sx") else m) for k in ("x", "y", "xa", "ya", "Sx", "Sy")}
+        st = State()
+        ptr = {k: (a.ctypes.data if a.size else None) for k, a in v.items()}
+        self._check(lib().pdlp_get_state(self._h, ptr["x"], ptr["y"], ptr["xa"], ptr["ya"], ptr["Sx"],
+                                         ptr["Sy"], ctypes.byref(st)))
+        v.update({k: getattr(st, k) for k in self._STATE_KEYS})
+        v["Seta"] = v.pop("s_eta")
+        return v
+
+    def set_state(self, state: dict):
+        """Resume from a checkpoint with the keys of get_state (the oracle's state records
+        use the same names)."""
+        arrs = {k: np.ascontiguousarray(state[k], dtype=np.float64) for k in ("x", "y", "xa", "ya", "Sx", "Sy")}
+        st = State(k=int(state["k"]), t=int(state["t"]), n_outer=int(state["n_outer"]),
+                   eta_hat=float(state["eta_hat"]), omega=float(state["omega"]),
+                   s_eta=float(state["Seta"]), mu_prev=float(state["mu_prev"]),
+                   mu_anchor=float(state["mu_anchor"]))
+        p = {k: (a.ctypes.data if a.size else None) for k, a in arrs.items()}
+        self._check(lib().pdlp_set_state(self._h, p["x"], p["y"], p["xa"], p["ya"], p["Sx"], p["Sy"],
+                                         ctypes.byref(st)))
 
     def scaling(self):
         D1 = np.empty(self.m)
