@@ -231,15 +231,16 @@ int pdlp_kernel_times(const pdlp_solver *s, double *times_ms, int64_t *counts);
 int pdlp_reset_kernel_times(pdlp_solver *s);
 
 /*
- * pdlp_build_schedule - host-only (no GPU needed): the row-block schedule the SpMV kernels use
- * for a CSR matrix with nrows rows and offsets row_ptr.  Writes up to cap descriptors of four
- * int32 {row0, count, kind | log2(lanes) << 8, split id} to desc, and sets *ndesc and *nsplit.
- * kind 0: rows [row0, row0 + count) staged through LDS with 2^log2(lanes) lanes per row;
- * kind 1: one row handled by a whole workgroup; kind 2: chunk `count` of a row too long for
- * one workgroup (split id names the row's partial-sum table).
+ * pdlp_build_schedule - host-only (no GPU needed): the work schedule the CSR products use
+ * for a matrix with nrows rows and offsets row_ptr.  Rows of at most 512 nonzeros are
+ * grouped by the lane count L = 2^p (the smallest with length <= 8 L) and listed in *perm
+ * (nrows entries at most, may be NULL); a wavefront task {a, b, 0 | p << 8, 0} covers rows
+ * perm[a .. a + b).  Longer rows get workgroup tasks {row, 0, 1, 0}; rows above 16384
+ * nonzeros are cut into chunks {row, chunk, 2, split id}.  Writes up to cap tasks of four
+ * int32 (wavefront tasks first) to desc and sets *ndesc (all tasks) and *nsplit.
  */
 int pdlp_build_schedule(const int64_t *row_ptr, int64_t nrows, int32_t *desc, int64_t cap,
-                        int64_t *ndesc, int64_t *nsplit);
+                        int64_t *ndesc, int64_t *nsplit, int32_t *perm);
 
 #ifdef __cplusplus
 }

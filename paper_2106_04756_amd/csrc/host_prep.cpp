@@ -15,10 +15,10 @@ namespace pdlp {
 
 namespace {
 
+// smallest p (p <= 6) with len <= kElemsPerLane * 2^p
 int lanes_log2_for(int64_t len) {
-  // smallest L = 2^p (p <= 6) with ceil(len / L) <= kPerThread
   int p = 0;
-  while (p < 6 && (int64_t(kPerThread) << p) < len) ++p;
+  while (p < 6 && (int64_t(kElemsPerLane) << p) < len) ++p;
   return p;
 }
 
@@ -26,48 +26,32 @@ int lanes_log2_for(int64_t len) {
 
 Schedule build_schedule(const int64_t* rp, int64_t nrows) {
   Schedule s;
-  int32_t cur_r0 = 0, cur_rows = 0;
-  int64_t cur_nnz = 0;
-  int cur_lg = 0;
-  auto flush = [&]() {
-    if (cur_rows > 0) s.desc.push_back(RowDesc{cur_r0, cur_rows, int32_t(kStream | (cur_lg << 8)), 0});
-    cur_rows = 0;
-    cur_nnz = 0;
-    cur_lg = 0;
-  };
-  const int64_t stream_max_len = int64_t(kPerThread) * kMaxLanesRow;
+  std::vector<std::vector<int32_t>> bins(7);
   for (int64_t i = 0; i < nrows; ++i) {
     const int64_t len = rp[i + 1] - rp[i];
-    if (len > stream_max_len) {
-      flush();
-      if (len <= kVectorMax) {
-        s.desc.push_back(RowDesc{int32_t(i), 0, kVector, 0});
-      } else {
-        const int32_t id = int32_t(s.split_row.size());
-        const int32_t nch = int32_t((len + kChunk - 1) / kChunk);
-        s.split_row.push_back(int32_t(i));
-        s.split_nchunks.push_back(nch);
-        s.split_base.push_back(int32_t(s.total_chunks));
-        s.total_chunks += nch;
-        for (int32_t c = 0; c < nch; ++c) s.desc.push_back(RowDesc{int32_t(i), c, kSplit, id});
-      }
-      continue;
-    }
-    const int lg_new = std::max(cur_lg, lanes_log2_for(len));
-    if (cur_rows > 0 &&
-        ((int64_t(cur_rows + 1) << lg_new) > kBlock || cur_nnz + len > kStreamNnz)) {
-      flush();
-    }
-    if (cur_rows == 0) {
-      cur_r0 = int32_t(i);
-      cur_lg = lanes_log2_for(len);
+    if (len <= kWaveMaxLen) {
+      bins[size_t(lanes_log2_for(len))].push_back(int32_t(i));
+    } else if (len <= kVectorMax) {
+      s.block.push_back(RowDesc{int32_t(i), 0, kVector, 0});
     } else {
-      cur_lg = lg_new;
+      const int32_t id = int32_t(s.split_row.size());
+      const int32_t nch = int32_t((len + kChunk - 1) / kChunk);
+      s.split_row.push_back(int32_t(i));
+      s.split_nchunks.push_back(nch);
+      s.split_base.push_back(int32_t(s.total_chunks));
+      s.total_chunks += nch;
+      for (int32_t c = 0; c < nch; ++c) s.block.push_back(RowDesc{int32_t(i), c, kSplit, id});
     }
-    ++cur_rows;
-    cur_nnz += len;
   }
-  flush();
+  for (int p = 0; p <= 6; ++p) {
+    const std::vector<int32_t>& b = bins[size_t(p)];
+    const int32_t per_task = int32_t((64 >> p) * kRounds);
+    for (size_t off = 0; off < b.size(); off += size_t(per_task)) {
+      const int32_t cnt = int32_t(std::min<size_t>(size_t(per_task), b.size() - off));
+      s.wave.push_back(RowDesc{int32_t(s.perm.size() + off), cnt, int32_t(kWaveRows | (p << 8)), 0});
+    }
+    s.perm.insert(s.perm.end(), b.begin(), b.end());
+  }
   return s;
 }
 
@@ -121,14 +105,17 @@ void transpose_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, c
 }  // namespace pdlp
 
 extern "C" int pdlp_build_schedule(const int64_t* row_ptr, int64_t nrows, int32_t* desc,
-                                   int64_t cap, int64_t* ndesc, int64_t* nsplit) {
+                                   int64_t cap, int64_t* ndesc, int64_t* nsplit, int32_t* perm) {
   if (!row_ptr || nrows < 0 || !ndesc) return -1;
   pdlp::Schedule s = pdlp::build_schedule(row_ptr, nrows);
-  *ndesc = int64_t(s.desc.size());
+  *ndesc = int64_t(s.wave.size() + s.block.size());
   if (nsplit) *nsplit = int64_t(s.split_row.size());
   if (desc) {
-    const int64_t nc = std::min<int64_t>(cap, int64_t(s.desc.size()));
-    std::memcpy(desc, s.desc.data(), size_t(nc) * sizeof(pdlp::RowDesc));
+    std::vector<pdlp::RowDesc> all(s.wave);
+    all.insert(all.end(), s.block.begin(), s.block.end());
+    const int64_t nc = std::min<int64_t>(cap, int64_t(all.size()));
+    std::memcpy(desc, all.data(), size_t(nc) * sizeof(pdlp::RowDesc));
   }
+  if (perm && !s.perm.empty()) std::memcpy(perm, s.perm.data(), s.perm.size() * sizeof(int32_t));
   return 0;
 }

@@ -14,8 +14,12 @@ struct CsrDev {
   const int32_t* ci;
   const double* v;
   int32_t nrows;
-  int32_t ndesc;
-  const RowDesc* desc;
+  int32_t nwave;         // wavefront tasks
+  int32_t nblock;        // workgroup tasks
+  int32_t pad0;
+  const int32_t* perm;
+  const RowDesc* wave;
+  const RowDesc* block;
   const int32_t* split_nchunks;
   const int32_t* split_base;
   int32_t nsplit;

@@ -7,24 +7,30 @@
 namespace pdlp {
 
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
-constexpr int kStreamNnz = 2048;       // nonzeros staged through LDS per row block
-constexpr int kPerThread = kStreamNnz / kBlock;
-constexpr int kMaxLanesRow = 64;       // widest lane group of a staged row (one wavefront)
+constexpr int kWaves = kBlock / 64;
+constexpr int kElemsPerLane = 8;       // a row of length len gets L = min pow2 with len <= 8 L lanes
+constexpr int kWaveMaxLen = kElemsPerLane * 64;   // longer rows are reduced by a whole workgroup
+constexpr int kRounds = 4;             // rows per lane group in one wavefront task
 constexpr int kVectorMax = 16384;      // longest row one workgroup reduces alone
 constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
 
-enum DescKind : int32_t { kStream = 0, kVector = 1, kSplit = 2 };
+enum DescKind : int32_t { kWaveRows = 0, kVector = 1, kSplit = 2 };
 
-// One unit of SpMV work for a workgroup.
+// One unit of SpMV work.
+//  kWaveRows: rows perm[a .. a + b) for one wavefront, 2^(kind_l >> 8) lanes per row
+//  kVector:   row a, reduced by one workgroup
+//  kSplit:    chunk b of row a (split id aux), reduced by one workgroup, combined by the last
 struct RowDesc {
-  int32_t row0;     // first row (kStream) or the row (kVector, kSplit)
-  int32_t count;    // rows (kStream) or chunk index (kSplit)
+  int32_t a;
+  int32_t b;
   int32_t kind_l;   // kind | log2(lanes per row) << 8
-  int32_t aux;      // split id (kSplit)
+  int32_t aux;
 };
 
 struct Schedule {
-  std::vector<RowDesc> desc;
+  std::vector<int32_t> perm;           // rows up to kWaveMaxLen long, grouped by lane count
+  std::vector<RowDesc> wave;           // wavefront tasks over perm
+  std::vector<RowDesc> block;          // workgroup tasks (long rows and chunks of giant rows)
   std::vector<int32_t> split_row;      // per split id: the row
   std::vector<int32_t> split_nchunks;  // per split id: number of chunks
   std::vector<int32_t> split_base;     // per split id: offset into the chunk-partial table

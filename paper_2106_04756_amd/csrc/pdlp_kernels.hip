@@ -164,58 +164,15 @@ __device__ double range_reduce(const CsrDev& A, const double* __restrict__ x, in
   return block_comb<MODE>(s);
 }
 
-// Visit every row of A once: row value s = sum_j A_rj x_j (kProd) or max/sum |A_rj|, and
-// call epi.row(r, s, contrib).  Contributions of ordinary rows go to acc (per thread); those
-// of split rows go straight to partial slot gridDim.x + split id (if part != nullptr).
+// Long rows (kVector) and chunks of giant rows (kSplit), one workgroup each.
 template <int MODE, class Epi>
-__device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
-                         double (&acc)[Epi::N], double* part) {
-  __shared__ double s_prod[kStreamNnz];
-  __shared__ int32_t s_rp[kBlock + 1];
-  for (int d = blockIdx.x; d < A.ndesc; d += gridDim.x) {
-    const RowDesc D = A.desc[d];
+__device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const double* __restrict__ x,
+                                                const Epi& epi, double (&acc)[Epi::N], double* part) {
+  for (int d = blockIdx.x; d < A.nblock; d += gridDim.x) {
+    const RowDesc D = A.block[d];
     const int kind = D.kind_l & 0xff;
-    if (kind == kStream) {
-      const int r0 = D.row0, nr = D.count, lg = D.kind_l >> 8;
-      const int64_t p0 = A.rp[r0];
-      for (int i = threadIdx.x; i <= nr; i += kBlock) s_rp[i] = int32_t(A.rp[r0 + i] - p0);
-      __syncthreads();
-      const int cnt = s_rp[nr];
-      int32_t cc[kPerThread];
-      double vv[kPerThread];
-#pragma unroll
-      for (int j = 0; j < kPerThread; ++j) {
-        const int e = threadIdx.x + j * kBlock;
-        if (e < cnt) {
-          vv[j] = A.v[p0 + e];
-          if constexpr (MODE == kProd) cc[j] = A.ci[p0 + e];
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < kPerThread; ++j) {
-        const int e = threadIdx.x + j * kBlock;
-        if (e < cnt) {
-          if constexpr (MODE == kProd) s_prod[e] = vv[j] * x[cc[j]];
-          else s_prod[e] = fabs(vv[j]);
-        }
-      }
-      __syncthreads();
-      const int L = 1 << lg, g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
-      double s = 0.0;
-      if (g < nr) {
-        const int e1 = s_rp[g + 1];
-        for (int e = s_rp[g] + lane; e < e1; e += L) s = comb<MODE>(s, s_prod[e]);
-      }
-      for (int off = L >> 1; off > 0; off >>= 1) s = comb<MODE>(s, __shfl_xor(s, off, 64));
-      if (lane == 0 && g < nr) {
-        double c[Epi::N];
-        epi.row(r0 + g, s, c);
-#pragma unroll
-        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
-      }
-      __syncthreads();
-    } else if (kind == kVector) {
-      const int r = D.row0;
+    const int r = D.a;
+    if (kind == kVector) {
       const double s = range_reduce<MODE>(A, x, A.rp[r], A.rp[r + 1]);
       if (threadIdx.x == 0) {
         double c[Epi::N];
@@ -224,7 +181,7 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
         for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
       }
     } else {
-      const int r = D.row0, ch = D.count, sid = D.aux;
+      const int ch = D.b, sid = D.aux;
       const int64_t q0 = A.rp[r] + int64_t(ch) * kChunk;
       const int64_t q1 = min(A.rp[r + 1], q0 + int64_t(kChunk));
       const double s = range_reduce<MODE>(A, x, q0, q1);
@@ -248,29 +205,99 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
   }
 }
 
+// Visit every row of A once: row value s = sum_j A_rj x_j (kProd) or max/sum |A_rj|, and
+// call epi.row(r, s, contrib).  Rows up to kWaveMaxLen long are handled by wavefronts on
+// their own (no LDS, no workgroup barrier): a group of L = 2^p lanes per row, each lane
+// loading at most kElemsPerLane nonzeros at once, then an xor-butterfly across the group.
+// Contributions of ordinary rows go to acc (per thread); those of split rows go straight to
+// partial slot gridDim.x + split id (if part != nullptr).
+template <int MODE, class Epi>
+__device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
+                         double (&acc)[Epi::N], double* part) {
+  const int lane64 = threadIdx.x & 63;
+  const int nw = gridDim.x * kWaves;
+  const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
+  for (int t = w0; t < A.nwave; t += nw) {
+    const RowDesc D = A.wave[t];
+    const int lg = D.kind_l >> 8, L = 1 << lg;
+    const int g = lane64 >> lg, lane = lane64 & (L - 1);
+    const int per_round = 64 >> lg;
+    for (int base = 0; base < D.b; base += per_round) {
+      const int slot = base + g;
+      const bool active = slot < D.b;
+      int r = 0;
+      double s = 0.0;
+      if (active) {
+        r = A.perm[D.a + slot];
+        const int64_t q0 = A.rp[r], p1 = A.rp[r + 1];
+        if (p1 > q0) {
+          // Branch-free loads: every lane loads kElemsPerLane entries with the index clamped
+          // into the row, so all loads (and then all gathers) are in flight together; entries
+          // past the row end are masked to +0.0, which leaves the sum bit-identical.
+          const int64_t p0 = q0 + lane;
+          double v[kElemsPerLane];
+          int32_t c[kElemsPerLane];
+#pragma unroll
+          for (int k = 0; k < kElemsPerLane; ++k) {
+            const int64_t e = p0 + int64_t(k) * L;
+            const int64_t ec = (e < p1) ? e : p1 - 1;
+            v[k] = A.v[ec];
+            if constexpr (MODE == kProd) c[k] = A.ci[ec];
+          }
+          if constexpr (MODE == kProd) {
+            double xv[kElemsPerLane];
+#pragma unroll
+            for (int k = 0; k < kElemsPerLane; ++k) xv[k] = x[c[k]];
+#pragma unroll
+            for (int k = 0; k < kElemsPerLane; ++k) {
+              const double t = v[k] * xv[k];
+              s = s + ((p0 + int64_t(k) * L < p1) ? t : 0.0);
+            }
+          } else {
+#pragma unroll
+            for (int k = 0; k < kElemsPerLane; ++k)
+              s = comb<MODE>(s, (p0 + int64_t(k) * L < p1) ? fabs(v[k]) : 0.0);
+          }
+        }
+      }
+      for (int off = L >> 1; off > 0; off >>= 1) s = comb<MODE>(s, __shfl_xor(s, off, 64));
+      if (active && lane == 0) {
+        double cc[Epi::N];
+        epi.row(r, s, cc);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
+      }
+    }
+  }
+  csr_block_tasks<MODE>(A, x, epi, acc, part);
+}
+
 // Same visit with the row values read from `stored` instead of recomputed.
 template <class Epi>
 __device__ void csr_rows_stored(const CsrDev& A, const double* __restrict__ stored, const Epi& epi,
                                 double (&acc)[Epi::N], double* part) {
-  for (int d = blockIdx.x; d < A.ndesc; d += gridDim.x) {
-    const RowDesc D = A.desc[d];
+  const int nw = gridDim.x * kWaves;
+  const int lane64 = threadIdx.x & 63;
+  double c[Epi::N];
+  for (int t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < A.nwave; t += nw) {
+    const RowDesc D = A.wave[t];
+    for (int slot = lane64; slot < D.b; slot += 64) {
+      const int r = A.perm[D.a + slot];
+      epi.row(r, stored[r], c);
+#pragma unroll
+      for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
+    }
+  }
+  for (int d = blockIdx.x; d < A.nblock; d += gridDim.x) {
+    const RowDesc D = A.block[d];
     const int kind = D.kind_l & 0xff;
-    double c[Epi::N];
-    if (kind == kStream) {
-      if (threadIdx.x < D.count) {
-        const int r = D.row0 + threadIdx.x;
-        epi.row(r, stored[r], c);
+    if (threadIdx.x != 0) continue;
+    if (kind == kVector) {
+      epi.row(D.a, stored[D.a], c);
 #pragma unroll
-        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
-      }
-    } else if (kind == kVector) {
-      if (threadIdx.x == 0) {
-        epi.row(D.row0, stored[D.row0], c);
-#pragma unroll
-        for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
-      }
-    } else if (D.count == 0 && threadIdx.x == 0) {
-      epi.row(D.row0, stored[D.row0], c);
+      for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
+    } else if (D.b == 0) {
+      epi.row(D.a, stored[D.a], c);
       if (part) {
 #pragma unroll
         for (int k = 0; k < Epi::N; ++k) st_agent(&part[size_t(gridDim.x + D.aux) * Epi::N + k], c[k]);
@@ -282,25 +309,31 @@ __device__ void csr_rows_stored(const CsrDev& A, const double* __restrict__ stor
 // Visit every nonzero of A with its (row, column): f(e, r, col).
 template <class F>
 __device__ void csr_elements(const CsrDev& A, F f) {
-  for (int d = blockIdx.x; d < A.ndesc; d += gridDim.x) {
-    const RowDesc D = A.desc[d];
-    const int kind = D.kind_l & 0xff;
-    if (kind == kStream) {
-      const int lg = D.kind_l >> 8, L = 1 << lg;
-      const int g = threadIdx.x >> lg, lane = threadIdx.x & (L - 1);
-      if (g < D.count) {
-        const int r = D.row0 + g;
+  const int nw = gridDim.x * kWaves;
+  const int lane64 = threadIdx.x & 63;
+  for (int t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < A.nwave; t += nw) {
+    const RowDesc D = A.wave[t];
+    const int lg = D.kind_l >> 8, L = 1 << lg;
+    const int g = lane64 >> lg, lane = lane64 & (L - 1);
+    const int per_round = 64 >> lg;
+    for (int base = 0; base < D.b; base += per_round) {
+      const int slot = base + g;
+      if (slot < D.b) {
+        const int r = A.perm[D.a + slot];
         for (int64_t e = A.rp[r] + lane; e < A.rp[r + 1]; e += L) f(e, r, A.ci[e]);
       }
-    } else {
-      const int r = D.row0;
-      int64_t q0 = A.rp[r], q1 = A.rp[r + 1];
-      if (kind == kSplit) {
-        q0 += int64_t(D.count) * kChunk;
-        q1 = min(q1, q0 + int64_t(kChunk));
-      }
-      for (int64_t e = q0 + threadIdx.x; e < q1; e += kBlock) f(e, r, A.ci[e]);
     }
+  }
+  for (int d = blockIdx.x; d < A.nblock; d += gridDim.x) {
+    const RowDesc D = A.block[d];
+    const int kind = D.kind_l & 0xff;
+    const int r = D.a;
+    int64_t q0 = A.rp[r], q1 = A.rp[r + 1];
+    if (kind == kSplit) {
+      q0 += int64_t(D.b) * kChunk;
+      q1 = min(q1, q0 + int64_t(kChunk));
+    }
+    for (int64_t e = q0 + threadIdx.x; e < q1; e += kBlock) f(e, r, A.ci[e]);
   }
 }
 

@@ -135,10 +135,17 @@ int write_output(pdlp_solver* s, void* dst, const void* src_dev, size_t bytes) {
 }
 
 int upload_schedule(pdlp_solver* s, const Schedule& sc, int64_t nrows, CsrDev& A) {
-  RowDesc* d_desc;
-  PDLP_HIP(s, s->alloc(&d_desc, sc.desc.size()));
-  if (!sc.desc.empty())
-    PDLP_HIP(s, hipMemcpy(d_desc, sc.desc.data(), sc.desc.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
+  int32_t* d_perm;
+  RowDesc *d_wave, *d_block;
+  PDLP_HIP(s, s->alloc(&d_perm, sc.perm.size()));
+  PDLP_HIP(s, s->alloc(&d_wave, sc.wave.size()));
+  PDLP_HIP(s, s->alloc(&d_block, sc.block.size()));
+  if (!sc.perm.empty())
+    PDLP_HIP(s, hipMemcpy(d_perm, sc.perm.data(), sc.perm.size() * 4, hipMemcpyHostToDevice));
+  if (!sc.wave.empty())
+    PDLP_HIP(s, hipMemcpy(d_wave, sc.wave.data(), sc.wave.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
+  if (!sc.block.empty())
+    PDLP_HIP(s, hipMemcpy(d_block, sc.block.data(), sc.block.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
   int32_t *nch, *base;
   PDLP_HIP(s, s->alloc(&nch, sc.split_nchunks.size()));
   PDLP_HIP(s, s->alloc(&base, sc.split_base.size()));
@@ -152,8 +159,11 @@ int upload_schedule(pdlp_solver* s, const Schedule& sc, int64_t nrows, CsrDev& A
   PDLP_HIP(s, s->alloc(&cnt, sc.split_row.size()));
   PDLP_HIP(s, hipMemset(cnt, 0, std::max<size_t>(sc.split_row.size(), 1) * sizeof(unsigned)));
   A.nrows = int32_t(nrows);
-  A.ndesc = int32_t(sc.desc.size());
-  A.desc = d_desc;
+  A.nwave = int32_t(sc.wave.size());
+  A.nblock = int32_t(sc.block.size());
+  A.perm = d_perm;
+  A.wave = d_wave;
+  A.block = d_block;
   A.split_nchunks = nch;
   A.split_base = base;
   A.nsplit = int32_t(sc.split_row.size());
@@ -162,7 +172,10 @@ int upload_schedule(pdlp_solver* s, const Schedule& sc, int64_t nrows, CsrDev& A
   return 0;
 }
 
-int grid_for(const CsrDev& A, int maxG) { return std::max(1, std::min(A.ndesc, maxG)); }
+int grid_for(const CsrDev& A, int maxG) {
+  const int by_wave = (A.nwave + kWaves - 1) / kWaves;
+  return std::max(1, std::min(std::max(by_wave, A.nblock), maxG));
+}
 
 int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double* in1, int in_par,
                 double* out0, double* out1, int out_par, int pred, int count_as) {

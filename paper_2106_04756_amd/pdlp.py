@@ -116,7 +116,7 @@ def lib() -> ctypes.CDLL:
         L.pdlp_kernel_times.restype = ctypes.c_int
         L.pdlp_reset_kernel_times.argtypes = [P]
         L.pdlp_reset_kernel_times.restype = ctypes.c_int
-        L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P]
+        L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P, P]
         L.pdlp_build_schedule.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -162,19 +162,21 @@ def _default_stream():
     return None
 
 
-def schedule(row_ptr) -> tuple[np.ndarray, int]:
-    """Host-only: the SpMV row-block schedule of a CSR matrix (descriptors as an (k, 4) int32
-    array, number of split rows)."""
+def schedule(row_ptr):
+    """Host-only: the SpMV schedule of a CSR matrix: (tasks as an (k, 4) int32 array of
+    {a, b, kind | log2(lanes) << 8, split id}, number of split rows, row permutation)."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     nd = ctypes.c_int64()
     ns = ctypes.c_int64()
-    rc = lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, None, 0, ctypes.byref(nd), ctypes.byref(ns))
+    rc = lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, None, 0, ctypes.byref(nd),
+                                   ctypes.byref(ns), None)
     if rc != 0:
         raise PdlpError(rc, "pdlp_build_schedule failed")
     desc = np.zeros((nd.value, 4), dtype=np.int32)
-    rc = lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, desc.ctypes.data, nd.value,
-                                   ctypes.byref(nd), ctypes.byref(ns))
-    return desc, ns.value
+    perm = np.full(max(rp.size - 1, 1), -1, dtype=np.int32)
+    lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, desc.ctypes.data, nd.value,
+                              ctypes.byref(nd), ctypes.byref(ns), perm.ctypes.data)
+    return desc, ns.value, perm[:rp.size - 1]
 
 
 class Solver:

@@ -16,7 +16,7 @@ from workloads import lpgen
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "pdlp.h")
 
-STREAM_NNZ, BLOCK, PER_THREAD, VEC_MAX, CHUNK = 2048, 256, 8, 16384, 16384
+ELEMS_PER_LANE, WAVE_MAX, VEC_MAX, CHUNK, ROUNDS = 8, 512, 16384, 16384, 4
 
 
 def _declared_functions():
@@ -52,34 +52,37 @@ def test_default_options_are_the_papers():
 
 
 def _check_schedule(row_ptr):
-    desc, nsplit = P.schedule(row_ptr)
+    desc, nsplit, perm = P.schedule(row_ptr)
     nrows = row_ptr.size - 1
+    lens = np.diff(row_ptr)
     seen = np.zeros(nrows, dtype=np.int64)
     chunks = {}
-    for row0, count, kl, aux in desc:
+    perm_used = np.zeros(perm.size, dtype=np.int64)
+    for a, b, kl, aux in desc:
         kind, lg = kl & 0xFF, kl >> 8
         if kind == 0:
             L = 1 << lg
-            rows = np.arange(row0, row0 + count)
-            lens = row_ptr[rows + 1] - row_ptr[rows]
-            assert count >= 1 and count * L <= BLOCK
-            assert lens.sum() <= STREAM_NNZ
-            assert lens.max() <= PER_THREAD * L
+            assert 1 <= b <= (64 // L) * ROUNDS
+            rows = perm[a:a + b]
+            perm_used[a:a + b] += 1
+            assert np.all(lens[rows] <= ELEMS_PER_LANE * L)
+            if lg > 0:
+                assert np.all(lens[rows] > ELEMS_PER_LANE * L // 2)
             seen[rows] += 1
         elif kind == 1:
-            ln = row_ptr[row0 + 1] - row_ptr[row0]
-            assert PER_THREAD * 64 < ln <= VEC_MAX
-            seen[row0] += 1
+            assert WAVE_MAX < lens[a] <= VEC_MAX
+            seen[a] += 1
         else:
             assert kind == 2
-            chunks.setdefault((row0, aux), []).append(count)
+            chunks.setdefault((a, aux), []).append(b)
     for (row, sid), cs in chunks.items():
-        ln = row_ptr[row + 1] - row_ptr[row]
-        assert ln > VEC_MAX
-        assert sorted(cs) == list(range(-(-ln // CHUNK)))
+        assert lens[row] > VEC_MAX
+        assert sorted(cs) == list(range(-(-lens[row] // CHUNK)))
         seen[row] += 1
     assert len({sid for (_, sid) in chunks}) == nsplit
     assert np.all(seen == 1)
+    short = int((lens <= WAVE_MAX).sum())
+    assert np.all(perm_used[:short] == 1)
     return desc, nsplit
 
 
