@@ -55,6 +55,107 @@ Schedule build_schedule(const int64_t* rp, int64_t nrows) {
   return s;
 }
 
+namespace {
+
+// Appends wavefront tasks for the panel rows [k0, k1) (all of one lane class `lg`).
+void push_wave_tasks(Schedule& s, int64_t k0, int64_t k1, int lg) {
+  const int64_t per_task = int64_t((64 >> lg) * kRounds);
+  for (int64_t off = k0; off < k1; off += per_task) {
+    const int32_t cnt = int32_t(std::min<int64_t>(per_task, k1 - off));
+    s.wave.push_back(RowDesc{int32_t(off), cnt, int32_t(kWaveRows | (lg << 8)), 0});
+  }
+}
+
+}  // namespace
+
+bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
+                  double max_prow_frac, PanelLayout& L) {
+  const int64_t nnz = rp[nrows];
+  L = PanelLayout();
+  L.P = P;
+  // column cuts with about nnz / P nonzeros per panel
+  std::vector<int64_t> colcnt(size_t(ncols) + 1, 0);
+  for (int64_t e = 0; e < nnz; ++e) colcnt[size_t(ci[e]) + 1]++;
+  for (int64_t j = 0; j < ncols; ++j) colcnt[size_t(j) + 1] += colcnt[size_t(j)];
+  std::vector<int32_t> cut(size_t(P) + 1, int32_t(ncols));
+  cut[0] = 0;
+  for (int p = 1; p < P; ++p) {
+    const int64_t target = nnz * p / P;
+    cut[size_t(p)] = int32_t(std::lower_bound(colcnt.begin(), colcnt.end(), target) - colcnt.begin());
+    cut[size_t(p)] = std::max(cut[size_t(p)], cut[size_t(p) - 1]);
+  }
+  std::vector<int64_t>().swap(colcnt);
+  // panel-row lengths: seg[r * P + p] = nonzeros of row r in panel p
+  std::vector<int32_t> seg(size_t(nrows) * size_t(P), 0);
+  int64_t nprow = 0;
+  for (int64_t r = 0; r < nrows; ++r) {
+    int p = 0;
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+      while (ci[e] >= cut[size_t(p) + 1]) ++p;
+      seg[size_t(r) * P + p]++;
+    }
+    for (int q = 0; q < P; ++q) nprow += seg[size_t(r) * P + q] > 0;
+  }
+  if (double(nprow) > max_prow_frac * double(std::max<int64_t>(nnz, 1))) return false;
+  // order panel rows: panel, then lane class (wavefront rows by p, then long rows), then row
+  L.prow_ptr.reserve(size_t(nprow) + 1);
+  L.prow_ptr.push_back(0);
+  L.prow_row.reserve(size_t(nprow));
+  std::vector<int32_t> prow_of(size_t(nrows) * size_t(P), -1);
+  L.wave_begin.push_back(0);
+  L.block_begin.push_back(0);
+  Schedule& S = L.sched;
+  for (int p = 0; p < P; ++p) {
+    for (int cls = 0; cls <= 7; ++cls) {           // 0..6 lane classes, 7 = long rows
+      const int64_t k0 = int64_t(L.prow_row.size());
+      for (int64_t r = 0; r < nrows; ++r) {
+        const int64_t len = seg[size_t(r) * P + p];
+        if (len == 0) continue;
+        const int c = (len <= kWaveMaxLen) ? lanes_log2_for(len) : 7;
+        if (c != cls) continue;
+        prow_of[size_t(r) * P + p] = int32_t(L.prow_row.size());
+        L.prow_row.push_back(int32_t(r));
+        L.prow_ptr.push_back(L.prow_ptr.back() + len);
+        if (cls == 7) {
+          const int32_t k = int32_t(L.prow_row.size() - 1);
+          if (len <= kVectorMax) {
+            S.block.push_back(RowDesc{k, 0, kVector, 0});
+          } else {
+            const int32_t id = int32_t(S.split_row.size());
+            const int32_t nch = int32_t((len + kChunk - 1) / kChunk);
+            S.split_row.push_back(k);
+            S.split_nchunks.push_back(nch);
+            S.split_base.push_back(int32_t(S.total_chunks));
+            S.total_chunks += nch;
+            for (int32_t cc = 0; cc < nch; ++cc) S.block.push_back(RowDesc{k, cc, kSplit, id});
+          }
+        }
+      }
+      if (cls < 7) push_wave_tasks(S, k0, int64_t(L.prow_row.size()), cls);
+    }
+    L.wave_begin.push_back(int32_t(S.wave.size()));
+    L.block_begin.push_back(int32_t(S.block.size()));
+  }
+  // source index of every panel-ordered nonzero, and each row's panel rows in panel order
+  L.src.resize(size_t(nnz));
+  L.slot_ptr.assign(size_t(nrows) + 1, 0);
+  L.slot_idx.reserve(size_t(nprow));
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t e = rp[r];
+    for (int p = 0; p < P; ++p) {
+      const int32_t len = seg[size_t(r) * P + p];
+      if (len == 0) continue;
+      const int32_t k = prow_of[size_t(r) * P + p];
+      int64_t dst = L.prow_ptr[size_t(k)];
+      for (int32_t t = 0; t < len; ++t) L.src[size_t(dst + t)] = e + t;
+      e += len;
+      L.slot_idx.push_back(k);
+    }
+    L.slot_ptr[size_t(r) + 1] = int64_t(L.slot_idx.size());
+  }
+  return true;
+}
+
 std::string validate_lp(int64_t m, int64_t n, int64_t n_eq, const double* c, const int64_t* rp,
                         const int32_t* ci, const double* v, const double* q, const double* l,
                         const double* u) {

@@ -13,13 +13,20 @@ struct CsrDev {
   const int64_t* rp;
   const int32_t* ci;
   const double* v;
-  int32_t nrows;
+  int32_t nrows;         // rows of the layout (panel rows in panel mode)
   int32_t nwave;         // wavefront tasks
   int32_t nblock;        // workgroup tasks
-  int32_t pad0;
-  const int32_t* perm;
+  int32_t npanel;        // 1 = plain row layout, else XCD column panels
+  const int32_t* perm;   // row of each wavefront slot (nullptr: identity)
   const RowDesc* wave;
   const RowDesc* block;
+  const int32_t* wave_begin;   // npanel + 1 task offsets per panel
+  const int32_t* block_begin;
+  const int32_t* prow_row;     // panel mode: original row of each panel row
+  const int64_t* slot_ptr;     // panel mode: panel rows of original row r: slot_idx[slot_ptr[r] ..]
+  const int32_t* slot_idx;
+  int32_t nrows_orig;
+  int32_t pad1;
   const int32_t* split_nchunks;
   const int32_t* split_base;
   int32_t nsplit;
@@ -66,7 +73,9 @@ enum Pred : int {
   kPredCheck = 1,
   kPredCheckKty = 2,
   kPredKty = 3,
-  kPredCheckRestart = 4
+  kPredCheckRestart = 4,
+  kPredAttempt = 5,
+  kPredAttemptKty = 6
 };
 
 }  // namespace pdlp

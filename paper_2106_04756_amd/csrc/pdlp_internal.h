@@ -39,6 +39,29 @@ struct Schedule {
 
 Schedule build_schedule(const int64_t* row_ptr, int64_t nrows);
 
+// XCD column panels of one CSR copy.  The gathered dimension (columns) is cut into P ranges of
+// about equal nonzero count; the nonzeros of panel p form "panel rows" (row r restricted to
+// panel p), stored panel after panel, each panel's rows grouped by lane count.  Workgroup b
+// runs on XCD b mod 8 and only works on panel b mod P, so the slice of the gathered vector it
+// touches stays in that XCD's L2.  A second, row-ordered pass adds the panel partial sums of
+// each row in panel order.
+struct PanelLayout {
+  int P = 1;
+  std::vector<int64_t> prow_ptr;       // total panel rows + 1
+  std::vector<int32_t> prow_row;       // original row of each panel row
+  std::vector<int64_t> src;            // row-major nonzero index of each panel-ordered nonzero
+  std::vector<int64_t> slot_ptr;       // nrows + 1
+  std::vector<int32_t> slot_idx;       // panel rows of each row, in panel order
+  Schedule sched;                      // tasks over panel rows (perm empty = identity)
+  std::vector<int32_t> wave_begin;     // P + 1 offsets of each panel's wavefront tasks
+  std::vector<int32_t> block_begin;    // P + 1 offsets of each panel's workgroup tasks
+};
+
+// Builds the layout with P panels; returns false (and leaves `out` unusable) when the panel
+// rows would cost more than `max_prow_frac` of the nonzeros.
+bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
+                  double max_prow_frac, PanelLayout& out);
+
 // Scalar state of one solve, resident in device memory.  Kernels read it at entry; only the
 // last workgroup of a kernel (after every other workgroup has arrived) writes it.
 struct DevState {

@@ -165,10 +165,25 @@ __device__ double range_reduce(const CsrDev& A, const double* __restrict__ x, in
 }
 
 // Long rows (kVector) and chunks of giant rows (kSplit), one workgroup each.
+// Task ranges of this workgroup: panel blockIdx mod npanel (its XCD when npanel = 8), and the
+// workgroup's index and count among those of that panel.
+struct PanelSlice {
+  int p, lb, nb;
+};
+__device__ __forceinline__ PanelSlice panel_slice(const CsrDev& A) {
+  PanelSlice ps;
+  ps.p = int(blockIdx.x) % A.npanel;
+  ps.lb = int(blockIdx.x) / A.npanel;
+  ps.nb = int(gridDim.x) / A.npanel;
+  return ps;
+}
+
 template <int MODE, class Epi>
 __device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const double* __restrict__ x,
                                                 const Epi& epi, double (&acc)[Epi::N], double* part) {
-  for (int d = blockIdx.x; d < A.nblock; d += gridDim.x) {
+  const PanelSlice ps = panel_slice(A);
+  const int d1 = A.block_begin[ps.p + 1];
+  for (int d = A.block_begin[ps.p] + ps.lb; d < d1; d += ps.nb) {
     const RowDesc D = A.block[d];
     const int kind = D.kind_l & 0xff;
     const int r = D.a;
@@ -215,9 +230,11 @@ template <int MODE, class Epi>
 __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
                          double (&acc)[Epi::N], double* part) {
   const int lane64 = threadIdx.x & 63;
-  const int nw = gridDim.x * kWaves;
-  const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kWaves + (threadIdx.x >> 6));
-  for (int t = w0; t < A.nwave; t += nw) {
+  const PanelSlice ps = panel_slice(A);
+  const int nw = ps.nb * kWaves;
+  const int t1 = A.wave_begin[ps.p + 1];
+  const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[ps.p] + ps.lb * kWaves + (threadIdx.x >> 6));
+  for (int t = w0; t < t1; t += nw) {
     const RowDesc D = A.wave[t];
     const int lg = D.kind_l >> 8, L = 1 << lg;
     const int g = lane64 >> lg, lane = lane64 & (L - 1);
@@ -228,7 +245,7 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
       int r = 0;
       double s = 0.0;
       if (active) {
-        r = A.perm[D.a + slot];
+        r = A.perm ? A.perm[D.a + slot] : D.a + slot;
         const int64_t q0 = A.rp[r], p1 = A.rp[r + 1];
         if (p1 > q0) {
           // Branch-free loads: every lane loads kElemsPerLane entries with the index clamped
@@ -282,7 +299,7 @@ __device__ void csr_rows_stored(const CsrDev& A, const double* __restrict__ stor
   for (int t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < A.nwave; t += nw) {
     const RowDesc D = A.wave[t];
     for (int slot = lane64; slot < D.b; slot += 64) {
-      const int r = A.perm[D.a + slot];
+      const int r = A.perm ? A.perm[D.a + slot] : D.a + slot;
       epi.row(r, stored[r], c);
 #pragma unroll
       for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
@@ -307,6 +324,7 @@ __device__ void csr_rows_stored(const CsrDev& A, const double* __restrict__ stor
 }
 
 // Visit every nonzero of A with its (row, column): f(e, r, col).
+// (In panel mode the row passed to f is the original row of the panel row.)
 template <class F>
 __device__ void csr_elements(const CsrDev& A, F f) {
   const int nw = gridDim.x * kWaves;
@@ -319,21 +337,43 @@ __device__ void csr_elements(const CsrDev& A, F f) {
     for (int base = 0; base < D.b; base += per_round) {
       const int slot = base + g;
       if (slot < D.b) {
-        const int r = A.perm[D.a + slot];
-        for (int64_t e = A.rp[r] + lane; e < A.rp[r + 1]; e += L) f(e, r, A.ci[e]);
+        const int k = A.perm ? A.perm[D.a + slot] : D.a + slot;
+        const int r = A.prow_row ? A.prow_row[k] : k;
+        for (int64_t e = A.rp[k] + lane; e < A.rp[k + 1]; e += L) f(e, r, A.ci[e]);
       }
     }
   }
   for (int d = blockIdx.x; d < A.nblock; d += gridDim.x) {
     const RowDesc D = A.block[d];
     const int kind = D.kind_l & 0xff;
-    const int r = D.a;
-    int64_t q0 = A.rp[r], q1 = A.rp[r + 1];
+    const int k = D.a;
+    const int r = A.prow_row ? A.prow_row[k] : k;
+    int64_t q0 = A.rp[k], q1 = A.rp[k + 1];
     if (kind == kSplit) {
       q0 += int64_t(D.b) * kChunk;
       q1 = min(q1, q0 + int64_t(kChunk));
     }
     for (int64_t e = q0 + threadIdx.x; e < q1; e += kBlock) f(e, r, A.ci[e]);
+  }
+}
+
+// Panel mode, second pass: the value of original row r is the sum (or max) of its panel
+// rows' partial values, taken in panel order; then epi.row(r, s, contrib).
+template <int MODE, class Epi>
+__device__ void combine_rows(const CsrDev& A, const double* __restrict__ part,
+                             const double* __restrict__ stored, const Epi& epi, double (&acc)[Epi::N]) {
+  for (int r = blockIdx.x * kBlock + threadIdx.x; r < A.nrows_orig; r += gridDim.x * kBlock) {
+    double s = 0.0;
+    if (stored) {
+      s = stored[r];
+    } else {
+      const int64_t j1 = A.slot_ptr[r + 1];
+      for (int64_t j = A.slot_ptr[r]; j < j1; ++j) s = comb<MODE>(s, part[A.slot_idx[j]]);
+    }
+    double c[Epi::N];
+    epi.row(r, s, c);
+#pragma unroll
+    for (int k = 0; k < Epi::N; ++k) acc[k] += c[k];
   }
 }
 
@@ -354,6 +394,8 @@ __device__ bool pred_ok(const DevState& S, int pred) {
     case kPredCheckKty: return check_runs(S) && !S.kty_valid;
     case kPredKty: return !S.kty_valid;
     case kPredCheckRestart: return check_runs(S) && S.restart;
+    case kPredAttempt: return attempt_runs(S);
+    case kPredAttemptKty: return attempt_runs(S) && !S.kty_valid;
     default: return false;
   }
 }
@@ -412,39 +454,11 @@ struct DualEpi {
   }
 };
 
-__global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA,
-                                                   unsigned* ticket) {
-  const DevState& S = *st;
-  if (!attempt_runs(S)) return;
-  const int P = S.parity;
-  const int kty_valid = S.kty_valid;
-  PrimalEpi epi{B.c, B.l, B.u, B.X[P], B.X[P ^ 1], B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
-  double acc[1] = {0.0};
-  if (kty_valid) csr_rows_stored(AT, B.KTy, epi, acc, partA);
-  else csr_rows<kProd>(AT, B.Y[P], epi, acc, partA);
-  block_sum<1>(acc);
-  write_slot<1>(partA, blockIdx.x, acc);
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) {
-      if (!kty_valid) st->spmv_KT += 1;
-    }
-    reset_ticket(ticket);
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B, const double* partA,
-                                                 int nslotA, double* partB, unsigned* ticket) {
-  const DevState& S = *st;
-  if (!attempt_runs(S)) return;
-  const int P = S.parity;
-  DualEpi epi{B.q, B.Y[P], B.KX[P], B.Y[P ^ 1], B.KX[P ^ 1], B.Sy, S.eta * S.omega, S.w_pending, B.m1};
-  double acc[2] = {0.0, 0.0};
-  csr_rows<kProd>(A, B.X[P ^ 1], epi, acc, partB);
-  block_sum<2>(acc);
-  write_slot<2>(partB, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  reset_ticket(ticket);
-  const int nslotB = gridDim.x + A.nsplit;
+// Algorithm 2 decision, run by the last workgroup of the dual-step kernel: the largest step
+// Eq. (5) allows, the next proposal, accept or retry, and the bookkeeping of Algorithm 1.
+__device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA, int nslotA,
+                               const double* partB, int nslotB) {
+  const int P = st->parity;
   double ax[1], ay[2];
   sum_slots<1>(partA, nslotA, ax);
   sum_slots<2>(partB, nslotB, ay);
@@ -500,6 +514,41 @@ __global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B,
   }
 }
 
+__global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA,
+                                                   unsigned* ticket) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const int P = S.parity;
+  const int kty_valid = S.kty_valid;
+  PrimalEpi epi{B.c, B.l, B.u, B.X[P], B.X[P ^ 1], B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  double acc[1] = {0.0};
+  if (kty_valid) csr_rows_stored(AT, B.KTy, epi, acc, partA);
+  else csr_rows<kProd>(AT, B.Y[P], epi, acc, partA);
+  block_sum<1>(acc);
+  write_slot<1>(partA, blockIdx.x, acc);
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) {
+      if (!kty_valid) st->spmv_KT += 1;
+    }
+    reset_ticket(ticket);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B, const double* partA,
+                                                 int nslotA, double* partB, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const int P = S.parity;
+  DualEpi epi{B.q, B.Y[P], B.KX[P], B.Y[P ^ 1], B.KX[P ^ 1], B.Sy, S.eta * S.omega, S.w_pending, B.m1};
+  double acc[2] = {0.0, 0.0};
+  csr_rows<kProd>(A, B.X[P ^ 1], epi, acc, partB);
+  block_sum<2>(acc);
+  write_slot<2>(partB, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  finish_attempt(st, B, partA, nslotA, partB, int(gridDim.x) + A.nsplit);
+}
+
 // Copy of the accepted iterate for the parity trace.
 __global__ __launch_bounds__(kBlock) void k_snapshot(DevState* st, Bufs B, unsigned* ticket) {
   const DevState& S = *st;
@@ -552,6 +601,86 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, DevState* st, const d
     }
     reset_ticket(ticket);
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// XCD column-panel mode: first pass per panel row, second pass per row in panel order
+// ------------------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, const double* in0,
+                                                       const double* in1, int in_parity, double* out,
+                                                       int pred, int mode) {
+  const DevState& S = *st;
+  if (!pred_ok(S, pred)) return;
+  const double* in = (in_parity && S.parity) ? in1 : in0;
+  StoreEpi epi{out};
+  double acc[1] = {0.0};
+  if (mode == kProd) csr_rows<kProd>(A, in, epi, acc, nullptr);
+  else if (mode == kAbsMax) csr_rows<kAbsMax>(A, nullptr, epi, acc, nullptr);
+  else csr_rows<kAbsSum>(A, nullptr, epi, acc, nullptr);
+}
+
+__global__ __launch_bounds__(kBlock) void k_primal_combine(CsrDev AT, DevState* st, Bufs B,
+                                                           const double* part, double* partA,
+                                                           unsigned* ticket) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const int P = S.parity;
+  const int kty_valid = S.kty_valid;
+  PrimalEpi epi{B.c, B.l, B.u, B.X[P], B.X[P ^ 1], B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  double acc[1] = {0.0};
+  combine_rows<kProd>(AT, part, kty_valid ? B.KTy : nullptr, epi, acc);
+  block_sum<1>(acc);
+  write_slot<1>(partA, blockIdx.x, acc);
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) {
+      if (!kty_valid) st->spmv_KT += 1;
+    }
+    reset_ticket(ticket);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_dual_combine(CsrDev A, DevState* st, Bufs B,
+                                                         const double* part, const double* partA,
+                                                         int nslotA, double* partB, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const int P = S.parity;
+  DualEpi epi{B.q, B.Y[P], B.KX[P], B.Y[P ^ 1], B.KX[P ^ 1], B.Sy, S.eta * S.omega, S.w_pending, B.m1};
+  double acc[2] = {0.0, 0.0};
+  combine_rows<kProd>(A, part, nullptr, epi, acc);
+  block_sum<2>(acc);
+  write_slot<2>(partB, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  finish_attempt(st, B, partA, nslotA, partB, int(gridDim.x));
+}
+
+__global__ __launch_bounds__(kBlock) void k_spmv_combine(CsrDev A, DevState* st, const double* part,
+                                                         double* out0, double* out1, int out_parity,
+                                                         int pred, int count_as, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!pred_ok(S, pred)) return;
+  double* out = (out_parity && S.parity) ? out1 : out0;
+  StoreEpi epi{out};
+  double acc[1] = {0.0};
+  combine_rows<kProd>(A, part, nullptr, epi, acc);
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) {
+      if (count_as == 1) st->spmv_K += 1;
+      if (count_as == 2) st->spmv_KT += 1;
+      if (pred == kPredCheckKty || pred == kPredKty) st->kty_valid = 1;
+    }
+    reset_ticket(ticket);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_norm_combine(CsrDev A, const double* part, double* out,
+                                                         int inf_norm) {
+  StoreEpi epi{out};
+  double acc[1] = {0.0};
+  if (inf_norm) combine_rows<kAbsMax>(A, part, nullptr, epi, acc);
+  else combine_rows<kAbsSum>(A, part, nullptr, epi, acc);
 }
 
 // ------------------------------------------------------------------------------------------

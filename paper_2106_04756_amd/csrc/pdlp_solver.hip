@@ -63,6 +63,9 @@ struct pdlp_solver {
   double* partA = nullptr;
   double* partB = nullptr;
   double* partX = nullptr;
+  double* partPK = nullptr;           // panel-row partials of the K~ products (panel mode)
+  double* partPT = nullptr;           // panel-row partials of the K~^T products (panel mode)
+  int gAc = 1, gBc = 1;               // grids of the row-ordered second passes
   unsigned* tickets = nullptr;
   double* outbuf = nullptr;
   int gA = 1, gB = 1, gE = 1, maxG = 1;
@@ -134,36 +137,31 @@ int write_output(pdlp_solver* s, void* dst, const void* src_dev, size_t bytes) {
   return 0;
 }
 
-int upload_schedule(pdlp_solver* s, const Schedule& sc, int64_t nrows, CsrDev& A) {
-  int32_t* d_perm;
-  RowDesc *d_wave, *d_block;
-  PDLP_HIP(s, s->alloc(&d_perm, sc.perm.size()));
-  PDLP_HIP(s, s->alloc(&d_wave, sc.wave.size()));
-  PDLP_HIP(s, s->alloc(&d_block, sc.block.size()));
-  if (!sc.perm.empty())
-    PDLP_HIP(s, hipMemcpy(d_perm, sc.perm.data(), sc.perm.size() * 4, hipMemcpyHostToDevice));
-  if (!sc.wave.empty())
-    PDLP_HIP(s, hipMemcpy(d_wave, sc.wave.data(), sc.wave.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
-  if (!sc.block.empty())
-    PDLP_HIP(s, hipMemcpy(d_block, sc.block.data(), sc.block.size() * sizeof(RowDesc), hipMemcpyHostToDevice));
-  int32_t *nch, *base;
-  PDLP_HIP(s, s->alloc(&nch, sc.split_nchunks.size()));
-  PDLP_HIP(s, s->alloc(&base, sc.split_base.size()));
-  if (!sc.split_nchunks.empty()) {
-    PDLP_HIP(s, hipMemcpy(nch, sc.split_nchunks.data(), sc.split_nchunks.size() * 4, hipMemcpyHostToDevice));
-    PDLP_HIP(s, hipMemcpy(base, sc.split_base.data(), sc.split_base.size() * 4, hipMemcpyHostToDevice));
-  }
+template <class T>
+int upload_vec(pdlp_solver* s, const std::vector<T>& h, const T** out) {
+  T* d;
+  PDLP_HIP(s, s->alloc(&d, h.size()));
+  if (!h.empty()) PDLP_HIP(s, hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = d;
+  return 0;
+}
+
+int upload_tasks(pdlp_solver* s, const Schedule& sc, CsrDev& A) {
+  int rc;
+  const RowDesc *w, *b;
+  const int32_t *nch, *base;
+  if ((rc = upload_vec(s, sc.wave, &w)) || (rc = upload_vec(s, sc.block, &b)) ||
+      (rc = upload_vec(s, sc.split_nchunks, &nch)) || (rc = upload_vec(s, sc.split_base, &base)))
+    return rc;
   double* part;
   unsigned* cnt;
   PDLP_HIP(s, s->alloc(&part, size_t(sc.total_chunks)));
   PDLP_HIP(s, s->alloc(&cnt, sc.split_row.size()));
   PDLP_HIP(s, hipMemset(cnt, 0, std::max<size_t>(sc.split_row.size(), 1) * sizeof(unsigned)));
-  A.nrows = int32_t(nrows);
   A.nwave = int32_t(sc.wave.size());
   A.nblock = int32_t(sc.block.size());
-  A.perm = d_perm;
-  A.wave = d_wave;
-  A.block = d_block;
+  A.wave = w;
+  A.block = b;
   A.split_nchunks = nch;
   A.split_base = base;
   A.nsplit = int32_t(sc.split_row.size());
@@ -172,13 +170,91 @@ int upload_schedule(pdlp_solver* s, const Schedule& sc, int64_t nrows, CsrDev& A
   return 0;
 }
 
+// Uploads one CSR copy (nrows x ncols) in the plain row layout or, when it pays, in XCD
+// column panels; *vdev receives the device values (the scaling kernels rewrite them) and
+// *prow_part the panel-row partial buffer (panel mode only).
+int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp, const int32_t* ci,
+                const double* v, CsrDev& A, double** vdev, double** prow_part) {
+  int rc;
+  const int64_t nnz = rp[nrows];
+  const int mode = s->opts.xcd_panels;
+  PanelLayout PL;
+  bool panel = false;
+  if (nnz > 0 && (mode == 1 || (mode < 0 && ncols * 8 > (int64_t(4) << 20))))
+    panel = build_panels(rp, ci, nrows, ncols, kWaves * 2, mode == 1 ? 1e300 : 0.25, PL);
+  A.nrows_orig = int32_t(nrows);
+  if (panel) {
+    const int64_t nprow = int64_t(PL.prow_row.size());
+    std::vector<int32_t> ciP(static_cast<size_t>(nnz));
+    std::vector<double> vP(static_cast<size_t>(nnz));
+    for (int64_t k = 0; k < nnz; ++k) {
+      ciP[size_t(k)] = ci[PL.src[size_t(k)]];
+      vP[size_t(k)] = v[PL.src[size_t(k)]];
+    }
+    std::vector<int64_t>().swap(PL.src);
+    if ((rc = upload_vec(s, PL.prow_ptr, &A.rp)) || (rc = upload_vec(s, ciP, &A.ci))) return rc;
+    const double* dv;
+    if ((rc = upload_vec(s, vP, &dv))) return rc;
+    *vdev = const_cast<double*>(dv);
+    A.v = dv;
+    if ((rc = upload_vec(s, PL.prow_row, &A.prow_row)) || (rc = upload_vec(s, PL.slot_ptr, &A.slot_ptr)) ||
+        (rc = upload_vec(s, PL.slot_idx, &A.slot_idx)) ||
+        (rc = upload_vec(s, PL.wave_begin, &A.wave_begin)) ||
+        (rc = upload_vec(s, PL.block_begin, &A.block_begin)))
+      return rc;
+    if ((rc = upload_tasks(s, PL.sched, A))) return rc;
+    A.perm = nullptr;
+    A.nrows = int32_t(nprow);
+    A.npanel = PL.P;
+    PDLP_HIP(s, s->alloc(prow_part, size_t(nprow)));
+    return 0;
+  }
+  Schedule sc = build_schedule(rp, nrows);
+  std::vector<int64_t> hrp(rp, rp + nrows + 1);
+  std::vector<int32_t> hci(ci, ci + nnz);
+  std::vector<double> hv(v, v + nnz);
+  const double* dv;
+  if ((rc = upload_vec(s, hrp, &A.rp)) || (rc = upload_vec(s, hci, &A.ci)) || (rc = upload_vec(s, hv, &dv)))
+    return rc;
+  *vdev = const_cast<double*>(dv);
+  A.v = dv;
+  if ((rc = upload_vec(s, sc.perm, &A.perm))) return rc;
+  const std::vector<int32_t> wb = {0, int32_t(sc.wave.size())}, bb = {0, int32_t(sc.block.size())};
+  if ((rc = upload_vec(s, wb, &A.wave_begin)) || (rc = upload_vec(s, bb, &A.block_begin))) return rc;
+  if ((rc = upload_tasks(s, sc, A))) return rc;
+  A.prow_row = nullptr;
+  A.slot_ptr = nullptr;
+  A.slot_idx = nullptr;
+  A.nrows = int32_t(nrows);
+  A.npanel = 1;
+  return 0;
+}
+
+// Grid of a CSR pass: a multiple of npanel, enough workgroups for the busiest panel.
 int grid_for(const CsrDev& A, int maxG) {
-  const int by_wave = (A.nwave + kWaves - 1) / kWaves;
-  return std::max(1, std::min(std::max(by_wave, A.nblock), maxG));
+  if (A.npanel <= 1) {
+    const int by_wave = (A.nwave + kWaves - 1) / kWaves;
+    return std::max(1, std::min(std::max(by_wave, A.nblock), maxG));
+  }
+  return A.npanel * std::max(1, maxG / A.npanel);
+}
+
+int grid_rows(int64_t nrows, int maxG) {
+  return int(std::max<int64_t>(1, std::min<int64_t>((nrows + kBlock - 1) / kBlock, maxG)));
 }
 
 int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double* in1, int in_par,
                 double* out0, double* out1, int out_par, int pred, int count_as) {
+  if (A.npanel > 1) {
+    double* part = (&A == &s->K) ? s->partPK : s->partPT;
+    k_panel_rows<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, part,
+                                                               pred, kProd);
+    PDLP_LAUNCH(s);
+    k_spmv_combine<<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(
+        A, s->st, part, out0, out1, out_par, pred, count_as, s->tickets + kTkSpmv);
+    PDLP_LAUNCH(s);
+    return 0;
+  }
   k_spmv<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out0, out1,
                                                        out_par, pred, count_as,
                                                        s->tickets + kTkSpmv);
@@ -203,13 +279,30 @@ int enqueue_block(pdlp_solver* s, int par) {
   const pdlp_options& o = s->opts;
   unsigned* tk = s->tickets;
   Bufs& B = s->B;
-  const int nslotA = s->gA + s->KT.nsplit;
+  const bool panT = s->KT.npanel > 1, panK = s->K.npanel > 1;
+  const int nslotA = panT ? s->gAc : s->gA + s->KT.nsplit;
   for (int i = 0; i < o.check_every; ++i) {
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i], s->stream));
-    k_primal<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA, tk + kTkPrimal);
+    if (panT) {
+      k_panel_rows<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B.Y[0], B.Y[1], 1, s->partPT,
+                                                    kPredAttemptKty, kProd);
+      PDLP_LAUNCH(s);
+      k_primal_combine<<<s->gAc, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partPT, s->partA,
+                                                         tk + kTkPrimal);
+    } else {
+      k_primal<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA, tk + kTkPrimal);
+    }
     PDLP_LAUNCH(s);
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 1], s->stream));
-    k_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partA, nslotA, s->partB, tk + kTkDual);
+    if (panK) {
+      k_panel_rows<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B.X[1], B.X[0], 1, s->partPK,
+                                                    kPredAttempt, kProd);
+      PDLP_LAUNCH(s);
+      k_dual_combine<<<s->gBc, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partPK, s->partA, nslotA,
+                                                       s->partB, tk + kTkDual);
+    } else {
+      k_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partA, nslotA, s->partB, tk + kTkDual);
+    }
     PDLP_LAUNCH(s);
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 2], s->stream));
     if (o.trace_iters > 0) {
@@ -278,10 +371,20 @@ int precondition(pdlp_solver* s) {
   const int passes = s->opts.ruiz_iters + (s->opts.pock_chambolle ? 1 : 0);
   for (int p = 0; p < passes; ++p) {
     const int inf_norm = (p < s->opts.ruiz_iters) ? 1 : 0;
-    k_row_norms<<<gK, kBlock, 0, s->stream>>>(s->K, rn, inf_norm);
-    PDLP_LAUNCH(s);
-    k_row_norms<<<gT, kBlock, 0, s->stream>>>(s->KT, cn, inf_norm);
-    PDLP_LAUNCH(s);
+    for (int which = 0; which < 2; ++which) {
+      const CsrDev& A = which ? s->KT : s->K;
+      double* out = which ? cn : rn;
+      if (A.npanel > 1) {
+        double* part = which ? s->partPT : s->partPK;
+        k_panel_rows<<<which ? gT : gK, kBlock, 0, s->stream>>>(A, s->st, nullptr, nullptr, 0, part,
+                                                                kPredAlways, inf_norm ? kAbsMax : kAbsSum);
+        PDLP_LAUNCH(s);
+        k_norm_combine<<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(A, part, out, inf_norm);
+      } else {
+        k_row_norms<<<which ? gT : gK, kBlock, 0, s->stream>>>(A, out, inf_norm);
+      }
+      PDLP_LAUNCH(s);
+    }
     if (s->m > 0) {
       k_scale_factors<<<gm, kBlock, 0, s->stream>>>(rn, rf, D1, int(s->m));
       PDLP_LAUNCH(s);
@@ -349,8 +452,6 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   std::vector<int32_t> ciT;
   std::vector<double> vT;
   transpose_csr(m, n, rp, ci, v, rpT, ciT, vT);
-  const Schedule schK = build_schedule(rp, m);
-  const Schedule schT = build_schedule(rpT.data(), n);
 
   int dev = 0;
   PDLP_HIP(s, hipGetDevice(&dev));
@@ -358,31 +459,9 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   PDLP_HIP(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   s->maxG = std::max(1, ncu * 8);
 
-  // the two CSR copies
-  int64_t *d_rp, *d_rpT;
-  int32_t *d_ci, *d_ciT;
-  PDLP_HIP(s, s->alloc(&d_rp, size_t(m) + 1));
-  PDLP_HIP(s, s->alloc(&d_ci, size_t(nnz)));
-  PDLP_HIP(s, s->alloc(&s->vK, size_t(nnz)));
-  PDLP_HIP(s, s->alloc(&d_rpT, size_t(n) + 1));
-  PDLP_HIP(s, s->alloc(&d_ciT, size_t(nnz)));
-  PDLP_HIP(s, s->alloc(&s->vKT, size_t(nnz)));
-  PDLP_HIP(s, hipMemcpy(d_rp, rp, (size_t(m) + 1) * 8, hipMemcpyHostToDevice));
-  PDLP_HIP(s, hipMemcpy(d_rpT, rpT.data(), (size_t(n) + 1) * 8, hipMemcpyHostToDevice));
-  if (nnz > 0) {
-    PDLP_HIP(s, hipMemcpy(d_ci, ci, size_t(nnz) * 4, hipMemcpyHostToDevice));
-    PDLP_HIP(s, hipMemcpy(s->vK, v, size_t(nnz) * 8, hipMemcpyHostToDevice));
-    PDLP_HIP(s, hipMemcpy(d_ciT, ciT.data(), size_t(nnz) * 4, hipMemcpyHostToDevice));
-    PDLP_HIP(s, hipMemcpy(s->vKT, vT.data(), size_t(nnz) * 8, hipMemcpyHostToDevice));
-  }
-  s->K.rp = d_rp;
-  s->K.ci = d_ci;
-  s->K.v = s->vK;
-  s->KT.rp = d_rpT;
-  s->KT.ci = d_ciT;
-  s->KT.v = s->vKT;
-  if ((rc = upload_schedule(s, schK, m, s->K))) return rc;
-  if ((rc = upload_schedule(s, schT, n, s->KT))) return rc;
+  // the two CSR copies (K~ and K~^T), each in the plain or the XCD-panel layout
+  if ((rc = upload_copy(s, m, n, rp, ci, v, s->K, &s->vK, &s->partPK))) return rc;
+  if ((rc = upload_copy(s, n, m, rpT.data(), ciT.data(), vT.data(), s->KT, &s->vKT, &s->partPT))) return rc;
   std::vector<int64_t>().swap(rpT);
   std::vector<int32_t>().swap(ciT);
   std::vector<double>().swap(vT);
@@ -443,9 +522,11 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   // grids and reduction scratch
   s->gA = grid_for(s->KT, s->maxG);
   s->gB = grid_for(s->K, s->maxG);
+  s->gAc = grid_rows(n, s->maxG);
+  s->gBc = grid_rows(m, s->maxG);
   s->gE = int(std::max<int64_t>(1, std::min<int64_t>(int64_t((NM + kBlock - 1) / kBlock), s->maxG)));
-  PDLP_HIP(s, s->alloc(&s->partA, size_t(s->gA + s->KT.nsplit)));
-  PDLP_HIP(s, s->alloc(&s->partB, size_t(s->gB + s->K.nsplit) * 2));
+  PDLP_HIP(s, s->alloc(&s->partA, size_t(std::max(s->gA + s->KT.nsplit, s->gAc))));
+  PDLP_HIP(s, s->alloc(&s->partB, size_t(std::max(s->gB + s->K.nsplit, s->gBc)) * 2));
   PDLP_HIP(s, s->alloc(&s->partX, size_t(s->gE) * 64));
   PDLP_HIP(s, s->alloc(&s->tickets, size_t(kNumTickets)));
   PDLP_HIP(s, hipMemset(s->tickets, 0, kNumTickets * sizeof(unsigned)));
@@ -509,6 +590,7 @@ void pdlp_default_options(pdlp_options* o) {
   o->trace_iters = 0;
   o->trace_capacity = 4096;
   o->time_kernels = 0;
+  o->xcd_panels = -1;
   o->beta_sufficient = 0.1;
   o->beta_necessary = 0.9;
   o->beta_artificial = 0.5;

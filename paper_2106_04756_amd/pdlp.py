@@ -32,7 +32,7 @@ class Options(ctypes.Structure):
                 ("adaptive_restarts", ctypes.c_int32), ("primal_weight_update", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("max_retries", ctypes.c_int32),
                 ("trace_iters", ctypes.c_int32), ("trace_capacity", ctypes.c_int32),
-                ("time_kernels", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("time_kernels", ctypes.c_int32), ("xcd_panels", ctypes.c_int32),
                 ("beta_sufficient", ctypes.c_double), ("beta_necessary", ctypes.c_double),
                 ("beta_artificial", ctypes.c_double), ("theta", ctypes.c_double),
                 ("primal_importance", ctypes.c_double), ("eps_zero", ctypes.c_double)]

@@ -47,9 +47,11 @@ def rel(a, b):
 
 # ------------------------------------------------------------------------------------------
 
-def test_spmv_matches_scipy_on_ragged_shapes():
-    """Unscaled products (no preconditioning) on every schedule path: short rows staged in
-    LDS, wavefront-sized rows, one-workgroup rows, split giant rows, empty rows/columns."""
+@pytest.mark.parametrize("panels", [0, 1])
+def test_spmv_matches_scipy_on_ragged_shapes(panels):
+    """Unscaled products (no preconditioning) on every schedule path: lane-group rows of
+    every width, one-workgroup rows, split giant rows, empty rows/columns; in the plain row
+    layout and in XCD column panels."""
     import torch
     rng = np.random.default_rng(5)
     m, n = 3000, 70000
@@ -63,8 +65,8 @@ def test_spmv_matches_scipy_on_ragged_shapes():
                       shape=(m, n))
     K.sort_indices()
     lp = lpgen.from_csr(K, np.ones(n), np.zeros(m), np.zeros(n), np.full(n, 1.0), n_eq=0)
-    say("spmv ragged", m, n, K.nnz)
-    s = make(lp, ruiz_iters=0, pock_chambolle=0)
+    say("spmv ragged", m, n, K.nnz, "panels", panels)
+    s = make(lp, ruiz_iters=0, pock_chambolle=0, xcd_panels=panels)
     for trial in range(2):
         x = rng.standard_normal(n)
         y = rng.standard_normal(m)
@@ -80,10 +82,11 @@ def test_spmv_matches_scipy_on_ragged_shapes():
         assert np.all(np.abs(outT.cpu().numpy() - refT) <= 1e-13 * scaleT + 1e-300)
 
 
-def test_preconditioning_matches_oracle():
+@pytest.mark.parametrize("panels", [0, 1])
+def test_preconditioning_matches_oracle(panels):
     for lp in (lpgen.config0(), lpgen.large_plain(11, 2000, 4000), lpgen.pagerank_lp(2, 30000)):
-        say("scaling", lp.name, lp.m, lp.n, lp.nnz)
-        s = make(lp)
+        say("scaling", lp.name, lp.m, lp.n, lp.nnz, "panels", panels)
+        s = make(lp, xcd_panels=panels)
         D1, D2 = s.scaling()
         _, _, _, _, _, oD1, oD2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
         assert np.max(np.abs(D1 / oD1 - 1)) < 1e-13
@@ -133,7 +136,7 @@ def test_trajectory_parity_config0():
 EPS = np.finfo(np.float64).eps
 
 
-def _replay_parity(lp, steps=100):
+def _replay_parity(lp, steps=100, **kw):
     """Replayed steps: for k = 0..steps-1 the GPU is put in the oracle's exact state before
     step k+1 (pdlp_set_state) and must land on the oracle's state after it, including the
     restart check at multiples of 40.  This tests every step's arithmetic without the
@@ -149,8 +152,8 @@ def _replay_parity(lp, steps=100):
     Kt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)[0]
     absK = abs(Kt)
     rowlen = np.diff(Kt.indptr).astype(np.float64)
-    say("replay", lp.name, lp.m, lp.n, lp.nnz)
-    s = make(lp)
+    say("replay", lp.name, lp.m, lp.n, lp.nnz, kw)
+    s = make(lp, **kw)
     states = ref.trace.states
     att_by_k = {}
     for a in ref.trace.attempts:
@@ -192,6 +195,15 @@ def test_replayed_step_parity(maker):
     _replay_parity(maker())
 
 
+@pytest.mark.parametrize("maker", [
+    lpgen.config0,
+    lambda: lpgen.large_plain(21, 400, 900),
+    lambda: lpgen.pagerank_lp(2, 20000),
+])
+def test_replayed_step_parity_xcd_panels(maker):
+    _replay_parity(maker(), xcd_panels=1)
+
+
 def test_solve_config0_to_1e8():
     lp = lpgen.config0()
     say("solve config0")
@@ -229,11 +241,12 @@ def test_solve_pagerank_matches_stationary_vector():
     assert np.abs(x - pi).sum() < 1e-6
 
 
-def test_two_runs_are_bitwise_equal_and_resume_is_seamless():
+@pytest.mark.parametrize("panels", [0, 1])
+def test_two_runs_are_bitwise_equal_and_resume_is_seamless(panels):
     lp = lpgen.large_plain(31, 3000, 7000)
-    say("determinism", lp.nnz)
-    a = make(lp)
-    b = make(lp)
+    say("determinism", lp.nnz, "panels", panels)
+    a = make(lp, xcd_panels=panels)
+    b = make(lp, xcd_panels=panels)
     a.solve(1e-30, 300)
     b.solve(1e-30, 120)
     b.solve(1e-30, 300)          # resume from k = 120
