@@ -152,6 +152,23 @@ def main():
         "step_gbs_algorithmic": step_gbs,
         "kernel_avg_ms": {"k_primal": avg[0], "k_dual": avg[1]},
     }
+    # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
+    tiny = lpgen.config0()
+    st0 = P.Solver.from_lp(tiny)
+    st0.solve(1e-8, 1)          # first launches / module load outside the timing
+    st0.close()
+    st0 = P.Solver.from_lp(tiny)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc0 = st0.solve(1e-8, 100000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    i0 = st0.info()
+    out["tiny_lp_solve"] = {"workload": tiny.name, "status": P.STATUS_NAMES[rc0], "iterations": i0["iterations"],
+                            "seconds": t1 - t0, "iters_per_s": i0["iterations"] / (t1 - t0),
+                            "kkt": i0["kkt"][3]}
+    st0.close()
+    log(f"tiny LP: {i0['iterations']} iterations to KKT {i0['kkt'][3]:.2e} in {t1 - t0:.3f}s")
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
         s.close()

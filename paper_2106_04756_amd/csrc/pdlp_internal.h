@@ -13,6 +13,7 @@ constexpr int kWaveMaxLen = kElemsPerLane * 64;   // longer rows are reduced by 
 constexpr int kRounds = 4;             // rows per lane group in one wavefront task
 constexpr int kVectorMax = 16384;      // longest row one workgroup reduces alone
 constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
+constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per XCD of an MI355X)
 
 enum DescKind : int32_t { kWaveRows = 0, kVector = 1, kSplit = 2 };
 

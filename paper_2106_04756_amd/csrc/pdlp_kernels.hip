@@ -367,8 +367,19 @@ __device__ void combine_rows(const CsrDev& A, const double* __restrict__ part,
     if (stored) {
       s = stored[r];
     } else {
-      const int64_t j1 = A.slot_ptr[r + 1];
-      for (int64_t j = A.slot_ptr[r]; j < j1; ++j) s = comb<MODE>(s, part[A.slot_idx[j]]);
+      // a row has at most kMaxPanels panel rows: load all slot indices, then all partials,
+      // with the indices clamped into the row's slot range (+0.0 past it, bit-identical sum)
+      const int64_t j0 = A.slot_ptr[r], j1 = A.slot_ptr[r + 1];
+      if (j1 > j0) {
+        int32_t k[kMaxPanels];
+        double v[kMaxPanels];
+#pragma unroll
+        for (int q = 0; q < kMaxPanels; ++q) k[q] = A.slot_idx[(j0 + q < j1) ? j0 + q : j1 - 1];
+#pragma unroll
+        for (int q = 0; q < kMaxPanels; ++q) v[q] = part[k[q]];
+#pragma unroll
+        for (int q = 0; q < kMaxPanels; ++q) s = comb<MODE>(s, (j0 + q < j1) ? v[q] : 0.0);
+      }
     }
     double c[Epi::N];
     epi.row(r, s, c);
