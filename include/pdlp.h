@@ -74,6 +74,12 @@ typedef struct pdlp_options {
   double theta;                  /* primal-weight smoothing of Algorithm 3: 0.5               */
   double primal_importance;      /* multiplies the initial primal weight: 1                   */
   double eps_zero;               /* "small nonzero tolerance" of Section 3.3: 1e-10           */
+  int32_t step_policy;           /* 0 adaptive (Algorithm 2, default); 1 constant
+                                    eta = 0.9 / ||K~||_2 (the baseline PDHG of Section 2)       */
+  int32_t restart_to_current;    /* 1 (default): candidate by GetRestartCandidate; 0: always
+                                    the average (Appendix C "adaptive restart (theory)")      */
+  int32_t power_iters;           /* power iterations for ||K~||_2 (constant policy): 200     */
+  int32_t reserved1;
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

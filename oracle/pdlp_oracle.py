@@ -48,6 +48,8 @@ class Options:
     pc_alpha: float = 1.0                # alpha = 1
     step_policy: str = "adaptive"        # Algorithm 2; "constant" = eta 0.9/||K||_2 (Section 2 baseline)
     restarts: bool = True                # Section 3.2 adaptive restarts
+    restart_to_current: bool = True      # False: the candidate is always the average
+                                         # (Appendix C "adaptive restart (theory)")
     beta_sufficient: float = 0.1         # reading R4: the printed 0.9 / 0.1 are transposed
     beta_necessary: float = 0.9
     beta_artificial: float = 0.5
@@ -352,10 +354,11 @@ def next_step_size(eta_bar, eta, k) -> float:
     return min((1.0 - k1 ** -0.3) * eta_bar, (1.0 + k1 ** -0.6) * eta)
 
 
-def power_iteration_norm(K, iters, seed=0) -> float:
-    """||K||_2 estimated by power iteration on K^T K (Section 2, baseline PDHG)."""
+def power_iteration_norm(K, iters) -> float:
+    """||K||_2 estimated by power iteration on K^T K (Section 2, baseline PDHG), started
+    from the all-ones vector (a deterministic start both implementations share)."""
     K = sp.csr_matrix(K)
-    v = np.random.default_rng(seed).standard_normal(K.shape[1])
+    v = np.ones(K.shape[1])
     v /= np.linalg.norm(v)
     sigma = 0.0
     for _ in range(iters):
@@ -494,7 +497,8 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
             gy_avg = qt - Kt @ xbar
             mu_cur = normalized_gap(x, y, xa, ya, omega, gx_cur, gy_cur, lt, ut, m1)
             mu_avg = normalized_gap(xbar, ybar, xa, ya, omega, gx_avg, gy_avg, lt, ut, m1)
-            use_avg = not (mu_cur < mu_avg)          # GetRestartCandidate, tie -> average
+            # GetRestartCandidate, tie -> average; "theory" mode always takes the average
+            use_avg = (not (mu_cur < mu_avg)) or not opts.restart_to_current
         else:
             mu_cur = mu_avg = math.nan
             use_avg = False

@@ -108,6 +108,9 @@ struct DevState {
   int32_t trace_iters;
   int32_t trace_cap;
   int32_t restarts_on, pw_on;
+  int32_t constant_step;  // constant step policy: eta never changes, every attempt accepted
+  int32_t to_current;     // GetRestartCandidate may pick the current iterate
+  double pow_norm2;       // power iteration: squared norm of the last K^T K v
   double beta_suff, beta_nec, beta_art, theta, eps_zero;
 };
 

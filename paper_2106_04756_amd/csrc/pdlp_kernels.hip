@@ -367,19 +367,8 @@ __device__ void combine_rows(const CsrDev& A, const double* __restrict__ part,
     if (stored) {
       s = stored[r];
     } else {
-      // a row has at most kMaxPanels panel rows: load all slot indices, then all partials,
-      // with the indices clamped into the row's slot range (+0.0 past it, bit-identical sum)
-      const int64_t j0 = A.slot_ptr[r], j1 = A.slot_ptr[r + 1];
-      if (j1 > j0) {
-        int32_t k[kMaxPanels];
-        double v[kMaxPanels];
-#pragma unroll
-        for (int q = 0; q < kMaxPanels; ++q) k[q] = A.slot_idx[(j0 + q < j1) ? j0 + q : j1 - 1];
-#pragma unroll
-        for (int q = 0; q < kMaxPanels; ++q) v[q] = part[k[q]];
-#pragma unroll
-        for (int q = 0; q < kMaxPanels; ++q) s = comb<MODE>(s, (j0 + q < j1) ? v[q] : 0.0);
-      }
+      const int64_t j1 = A.slot_ptr[r + 1];
+      for (int64_t j = A.slot_ptr[r]; j < j1; ++j) s = comb<MODE>(s, part[A.slot_idx[j]]);
     }
     double c[Epi::N];
     epi.row(r, s, c);
@@ -480,9 +469,13 @@ __device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA,
   // Algorithm 2: the largest step Eq. (5) allows, and the next proposal
   const double num = omega * dx2 + dy2 / omega;
   const double den = 2.0 * fabs(cross);
-  const double eta_bar = (den > 0.0) ? num / den : INFINITY;
+  double eta_bar = (den > 0.0) ? num / den : INFINITY;
   const double k2 = double(W.k + 2);   // (k + 1) with a 1-based step counter
-  const double eta_next = fmin((1.0 - pow(k2, -0.3)) * eta_bar, (1.0 + pow(k2, -0.6)) * eta);
+  double eta_next = fmin((1.0 - pow(k2, -0.3)) * eta_bar, (1.0 + pow(k2, -0.6)) * eta);
+  if (W.constant_step) {               // baseline PDHG: a fixed step, always accepted
+    eta_bar = INFINITY;
+    eta_next = eta;
+  }
   const bool ok = isfinite(dx2) && isfinite(dy2) && isfinite(cross) && isfinite(eta_next);
   const bool accepted = ok && (eta <= eta_bar);
   if (W.trace_cap > 0) {
@@ -1029,7 +1022,7 @@ __global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int 
   if (mode == 0) {
     W.mu_cur = mu[0];
     W.mu_avg = mu[1];
-    W.use_avg = (mu[0] < mu[1]) ? 0 : 1;    // GetRestartCandidate: a tie picks the average
+    W.use_avg = (W.to_current && mu[0] < mu[1]) ? 0 : 1;   // GetRestartCandidate: a tie picks the average
     W.mu_c = W.use_avg ? mu[1] : mu[0];
   } else {
     W.mu_anchor = mu[0];
@@ -1204,7 +1197,7 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, un
     W.n_outer += 1;
     W.mu_prev = INFINITY;
     W.kty_valid = 1;
-  } else {
+  } else if (W.restarts_on) {
     W.mu_prev = W.mu_c;
   }
   W.restart = 0;
@@ -1241,6 +1234,36 @@ __global__ void k_set_state(DevState* st, pdlp_state v) {
     W.use_avg = 0;
     W.out_avg = 0;
     W.snap_pending = 0;
+  }
+}
+
+// Power iteration for ||K~||_2 (constant step policy): w = K~^T K~ v is in `w`; store
+// ||w||^2 and v <- w / ||w|| for the next round.
+__global__ __launch_bounds__(kBlock) void k_pow_norm(DevState* st, const double* w, int n, double* part,
+                                                     unsigned* ticket) {
+  double a[1] = {0.0};
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) a[0] += w[j] * w[j];
+  block_sum<1>(a);
+  write_slot<1>(part, blockIdx.x, a);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[1];
+  sum_slots<1>(part, gridDim.x, t);
+  if (threadIdx.x == 0) st->pow_norm2 = t[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_pow_scale(const DevState* st, const double* w, double* v, int n) {
+  const double nw = sqrt(st->pow_norm2);
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock)
+    v[j] = (nw > 0.0) ? w[j] / nw : 0.0;
+}
+
+// eta = 0.9 / ||K~||_2 with ||K~||_2 = sqrt(||K~^T K~ v||) of the last power iteration.
+__global__ void k_pow_set_step(DevState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double sigma = sqrt(sqrt(st->pow_norm2));
+    st->eta_hat = (sigma > 0.0) ? 0.9 / sigma : 1.0;
+    st->eta = st->eta_hat;
   }
 }
 

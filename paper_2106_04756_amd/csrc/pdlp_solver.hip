@@ -544,6 +544,8 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   h.trace_iters = s->opts.trace_iters;
   h.trace_cap = cap;
   h.restarts_on = s->opts.adaptive_restarts;
+  h.constant_step = s->opts.step_policy == 1;
+  h.to_current = s->opts.restart_to_current != 0;
   h.pw_on = s->opts.primal_weight_update;
   h.beta_suff = s->opts.beta_sufficient;
   h.beta_nec = s->opts.beta_necessary;
@@ -567,6 +569,28 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
                                           s->opts.primal_importance, s->opts.eps_zero);
   PDLP_LAUNCH(s);
   if ((rc = launch_spmv(s, s->K, B.X[0], nullptr, 0, B.KX[0], nullptr, 0, kPredAlways, 0))) return rc;
+  if (s->opts.step_policy == 1) {
+    // baseline PDHG step 0.9 / ||K~||_2: power iteration on K~^T K~ from the all-ones vector,
+    // using the gap scratch buffers (free until the first check)
+    double* v = B.GA[0];
+    double* t = B.GB[0];
+    double* w = B.GA[1];
+    {
+      std::vector<double> ones(N, 1.0 / std::sqrt(double(n)));
+      PDLP_HIP(s, hipMemcpy(v, ones.data(), N * 8, hipMemcpyHostToDevice));
+    }
+    const int gn = grid_rows(n, s->maxG);
+    for (int it = 0; it < s->opts.power_iters; ++it) {
+      if ((rc = launch_spmv(s, s->K, v, nullptr, 0, t, nullptr, 0, kPredAlways, 0))) return rc;
+      if ((rc = launch_spmv(s, s->KT, t, nullptr, 0, w, nullptr, 0, kPredAlways, 0))) return rc;
+      k_pow_norm<<<gn, kBlock, 0, s->stream>>>(s->st, w, int(n), s->partX, s->tickets + kTkInit);
+      PDLP_LAUNCH(s);
+      k_pow_scale<<<gn, kBlock, 0, s->stream>>>(s->st, w, v, int(n));
+      PDLP_LAUNCH(s);
+    }
+    k_pow_set_step<<<1, 1, 0, s->stream>>>(s->st);
+    PDLP_LAUNCH(s);
+  }
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
 
   s->bytes_A = 8.0 * double(n + 1) + 12.0 * double(nnz) + 8.0 * double(m) + 64.0 * double(n);
@@ -591,6 +615,9 @@ void pdlp_default_options(pdlp_options* o) {
   o->trace_capacity = 4096;
   o->time_kernels = 0;
   o->xcd_panels = -1;
+  o->step_policy = 0;
+  o->restart_to_current = 1;
+  o->power_iters = 200;
   o->beta_sufficient = 0.1;
   o->beta_necessary = 0.9;
   o->beta_artificial = 0.5;
@@ -621,7 +648,7 @@ int pdlp_create(pdlp_solver** out, int64_t m, int64_t n, int64_t n_eq, const dou
   if (o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || o.trace_iters < 0 ||
       o.trace_capacity < 0 || !(o.theta >= 0.0 && o.theta <= 1.0) || !(o.primal_importance > 0.0) ||
       !(o.eps_zero >= 0.0) || !(o.beta_sufficient > 0.0) || !(o.beta_necessary > 0.0) ||
-      !(o.beta_artificial > 0.0)) {
+      !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 1 || o.power_iters < 1) {
     g_create_error = "invalid options";
     delete s;
     return PDLP_ERR_INVALID_ARGUMENT;

@@ -35,7 +35,9 @@ class Options(ctypes.Structure):
                 ("time_kernels", ctypes.c_int32), ("xcd_panels", ctypes.c_int32),
                 ("beta_sufficient", ctypes.c_double), ("beta_necessary", ctypes.c_double),
                 ("beta_artificial", ctypes.c_double), ("theta", ctypes.c_double),
-                ("primal_importance", ctypes.c_double), ("eps_zero", ctypes.c_double)]
+                ("primal_importance", ctypes.c_double), ("eps_zero", ctypes.c_double),
+                ("step_policy", ctypes.c_int32), ("restart_to_current", ctypes.c_int32),
+                ("power_iters", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -136,7 +136,7 @@ def test_trajectory_parity_config0():
 EPS = np.finfo(np.float64).eps
 
 
-def _replay_parity(lp, steps=100, **kw):
+def _replay_parity(lp, steps=100, opts=None, **kw):
     """Replayed steps: for k = 0..steps-1 the GPU is put in the oracle's exact state before
     step k+1 (pdlp_set_state) and must land on the oracle's state after it, including the
     restart check at multiples of 40.  This tests every step's arithmetic without the
@@ -147,8 +147,8 @@ def _replay_parity(lp, steps=100, **kw):
     arithmetic from identical inputs); the proposed step eta_hat within the conditioning of
     the denominator 2 dy^T K dx of Algorithm 2, which the GPU forms as dy^T (K x' - K x):
     its error is bounded by 2 eps sum_i |dy_i| len_i ((|K||x'|)_i + (|K||x|)_i)."""
-    ref = O.solve_lp(lp, tol=1e-30, iter_limit=steps, record_states=steps, trace_iters=steps,
-                     record_trace=True)
+    ref = O.solve_lp(lp, tol=1e-30, iter_limit=steps, opts=opts, record_states=steps,
+                     trace_iters=steps, record_trace=True)
     Kt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)[0]
     absK = abs(Kt)
     rowlen = np.diff(Kt.indptr).astype(np.float64)
@@ -202,6 +202,37 @@ def test_replayed_step_parity(maker):
 ])
 def test_replayed_step_parity_xcd_panels(maker):
     _replay_parity(maker(), xcd_panels=1)
+
+
+# the paper's ablation switches (Appendix C): same option on both sides
+ABLATIONS = {
+    "constant_step": (dict(step_policy="constant"), dict(step_policy=1)),
+    "no_restarts": (dict(restarts=False), dict(adaptive_restarts=0)),
+    "restart_theory": (dict(beta_sufficient=0.37, beta_necessary=0.37, restart_to_current=False),
+                       dict(beta_sufficient=0.37, beta_necessary=0.37, restart_to_current=0)),
+    "fixed_weight": (dict(primal_weight_update=False, primal_importance=0.1),
+                     dict(primal_weight_update=0, primal_importance=0.1)),
+    "no_scaling": (dict(ruiz_iters=0, pock_chambolle=False), dict(ruiz_iters=0, pock_chambolle=0)),
+    "ruiz_only": (dict(pock_chambolle=False), dict(pock_chambolle=0)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ABLATIONS))
+def test_ablation_switches_replay(name):
+    o_kw, g_kw = ABLATIONS[name]
+    _replay_parity(lpgen.large_plain(21, 400, 900), steps=90, opts=O.Options(**o_kw), **g_kw)
+
+
+def test_constant_step_uses_power_iteration_norm():
+    lp = lpgen.config0()
+    say("constant step size")
+    s = make(lp, step_policy=1)
+    Kt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)[0]
+    eta = 0.9 / O.power_iteration_norm(Kt, 200)
+    assert abs(s.get_state()["eta_hat"] - eta) <= 1e-12 * eta
+    # power iteration approaches ||K~||_2 from below
+    sigma_est, sigma = 0.9 / eta, np.linalg.norm(Kt.toarray(), 2)
+    assert 0.99 * sigma <= sigma_est <= sigma * (1 + 1e-12)
 
 
 def test_solve_config0_to_1e8():
