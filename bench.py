@@ -59,6 +59,35 @@ def cpu_baseline(lp, budget_s=20.0):
                        f"scipy CSR products, 1 thread) on the same LP, {el:.1f} s")
 
 
+def bench_batched(P, lpgen, count, iter_limit, plain_sample=16):
+    """LPs/s to KKT 1e-8 of the batched solver (one launch, one workgroup per LP) on the
+    batched workload, against a loop of single-LP solves on an evenly spaced sample."""
+    import numpy as np
+    t = time.time()
+    lps = [lpgen.batched_instance(i) for i in range(count)]
+    log(f"generated {count} batched members in {time.time() - t:.1f}s")
+    b = P.Batch(lps)
+    secs = b.solve(1e-8, iter_limit)
+    _, _, st, it, kkt = b.get()
+    b.close()
+    conv = int((st == P.OPTIMAL).sum())
+    idx = list(range(0, count, max(1, count // plain_sample)))[:plain_sample]
+    t0 = time.perf_counter()
+    pconv = 0
+    for i in idx:
+        s = P.Solver.from_lp(lps[i])
+        pconv += s.solve(1e-8, iter_limit) == P.OPTIMAL
+        s.close()
+    pdt = time.perf_counter() - t0
+    log(f"batched: {conv}/{count} at KKT 1e-8 in {secs:.2f}s; plain loop {pconv}/{len(idx)} in {pdt:.2f}s")
+    return {"workload": f"{count} LPs, m log-uniform in [50,2000], n = U[2,3] m, 3-8 nonzeros per "
+                        f"column, seeds 3000+i", "tol": 1e-8, "iter_limit": iter_limit,
+            "seconds": secs, "converged": conv, "count": count, "lps_per_s": conv / secs,
+            "median_iterations": float(np.median(it)), "max_kkt_converged": float(kkt[st == 0, 3].max()) if conv else None,
+            "plain_loop_lps_per_s": pconv / pdt, "plain_sample": len(idx), "plain_converged": pconv,
+            "speedup_vs_plain": (conv / secs) / (pconv / pdt) if pconv else None}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -79,6 +108,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-iter-limit", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -169,6 +201,8 @@ def main():
                             "kkt": i0["kkt"][3]}
     st0.close()
     log(f"tiny LP: {i0['iterations']} iterations to KKT {i0['kkt'][3]:.2e} in {t1 - t0:.3f}s")
+    if not args.no_batched:
+        out["batched"] = bench_batched(P, lpgen, args.batch_count, args.batch_iter_limit)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
         s.close()

@@ -187,6 +187,46 @@ void pdlp_destroy(pdlp_solver *s);
  * NULL).  Owned by the library, valid until the next call on s. */
 const char *pdlp_last_error(const pdlp_solver *s);
 
+/* ---- batched solve: many independent LPs in one launch ----------------------------------- */
+
+typedef struct pdlp_batch pdlp_batch;
+
+/*
+ * pdlp_batch_create - a batch of `count` independent LPs of the form above, solved later in one
+ * persistent launch with one GPU workgroup per LP; every LP has its own preconditioning, step
+ * size, primal weight, restart state and termination (the method of Section 3 applied to each).
+ *   m, n, n_eq   count sizes each (as in pdlp_create, per member).
+ *   c, l, u      members' n-vectors concatenated in member order (sum of n values).
+ *   q            members' m-vectors concatenated (sum of m values).
+ *   row_ptr      members' CSR row offsets concatenated (sum of m + 1 values; each member's
+ *                offsets start at 0 and index that member's nonzeros).
+ *   col_idx, val members' nonzeros concatenated (member-local column indices).
+ *   opts         as in pdlp_create; step_policy must be 0 (adaptive); traces are not kept.
+ * Inputs are deep-copied; host or device pointers.  Errors as pdlp_create (the message names
+ * the first invalid member).
+ */
+int pdlp_batch_create(pdlp_batch **out, int64_t count, const int64_t *m, const int64_t *n,
+                      const int64_t *n_eq, const double *c, const int64_t *row_ptr,
+                      const int32_t *col_idx, const double *val, const double *q,
+                      const double *l, const double *u, const pdlp_options *opts,
+                      void *hip_stream);
+
+/* pdlp_batch_solve - solve every member to relative KKT error tol or iter_limit accepted
+ * steps (each member separately).  One call per batch; PDLP_ERR_INVALID_STATE on a second. */
+int pdlp_batch_solve(pdlp_batch *b, double tol, int64_t iter_limit);
+
+/* pdlp_batch_get - returned points, unscaled and concatenated like the inputs (x: sum of n,
+ * y: sum of m), and per member the pdlp_status, accepted steps and kkt[4] (4 * count values).
+ * Any pointer may be NULL. */
+int pdlp_batch_get(const pdlp_batch *b, double *x, double *y, int32_t *status,
+                   int64_t *iterations, double *kkt);
+
+/* pdlp_batch_solve_seconds - host wall time of pdlp_batch_solve (launch to completion). */
+double pdlp_batch_solve_seconds(const pdlp_batch *b);
+
+void pdlp_batch_destroy(pdlp_batch *b);
+const char *pdlp_batch_last_error(const pdlp_batch *b);
+
 /* ---- inspection entry points (parity tests and measurement) ---------------------------- */
 
 /*

@@ -1,0 +1,397 @@
+// Batched PDLP: many independent LPs in one persistent launch, one workgroup per LP.
+//
+// Each workgroup runs the whole method on its own LP: preconditioning (Section 3.5), the
+// initial point, and Algorithm 1 with adaptive steps (Algorithm 2), averages, restart checks
+// (Section 3.2), primal-weight updates (Algorithm 3) and the KKT test (Section 4.1), each with
+// its own step size, primal weight, restart state, counters and termination.  The scalar state
+// lives in LDS (a DevState per workgroup) and is changed only by thread 0 between barriers,
+// through the same decision functions the one-LP kernels use; the per-element work uses the
+// same element functions.  Products: one thread per row of K~ or K~^T (the member LPs have
+// short rows), summing in index order.  No atomics; every sum has a fixed order.
+//
+// Included into the solver's translation unit after pdlp_kernels.hip.
+
+namespace pdlp {
+
+struct BatchInst {
+  int32_t m, n, m1, pad;
+  int64_t rp;     // offset of the member's m + 1 row offsets of K (member-local, from 0)
+  int64_t rpT;    // offset of its n + 1 row offsets of K^T
+  int64_t nz;     // offset of its nonzeros (same in both copies)
+  int64_t xo;     // offset of its n-vectors
+  int64_t yo;     // offset of its m-vectors (its (n+m)-vectors start at xo + yo)
+};
+
+struct BatchDev {
+  const BatchInst* inst;
+  const int64_t* rp;
+  const int32_t* ci;
+  double* v;
+  const int64_t* rpT;
+  const int32_t* ciT;
+  double* vT;
+  double *c, *l, *u, *c0, *l0, *u0, *D2, *X0, *X1, *KTy, *Sx, *XB, *KTYB, *XA;
+  double *q, *q0, *D1, *Y0, *Y1, *KX0, *KX1, *Sy, *YB, *KXB, *YA;
+  double *GA0, *GA1, *GB0, *GB1;
+  DevState* out_state;   // final state of every member
+};
+
+__device__ Bufs batch_bufs(const BatchDev& D, const BatchInst& I) {
+  Bufs B;
+  B.n = I.n;
+  B.m = I.m;
+  B.m1 = I.m1;
+  B.pad = 0;
+  const int64_t xo = I.xo, yo = I.yo, zo = I.xo + I.yo;
+  B.c = D.c + xo;
+  B.l = D.l + xo;
+  B.u = D.u + xo;
+  B.q = D.q + yo;
+  B.c0 = D.c0 + xo;
+  B.l0 = D.l0 + xo;
+  B.u0 = D.u0 + xo;
+  B.q0 = D.q0 + yo;
+  B.D1 = D.D1 + yo;
+  B.D2 = D.D2 + xo;
+  B.X[0] = D.X0 + xo;
+  B.X[1] = D.X1 + xo;
+  B.Y[0] = D.Y0 + yo;
+  B.Y[1] = D.Y1 + yo;
+  B.KX[0] = D.KX0 + yo;
+  B.KX[1] = D.KX1 + yo;
+  B.KTy = D.KTy + xo;
+  B.Sx = D.Sx + xo;
+  B.Sy = D.Sy + yo;
+  B.XB = D.XB + xo;
+  B.YB = D.YB + yo;
+  B.KXB = D.KXB + yo;
+  B.KTYB = D.KTYB + xo;
+  B.XA = D.XA + xo;
+  B.YA = D.YA + yo;
+  B.GA[0] = D.GA0 + zo;
+  B.GA[1] = D.GA1 + zo;
+  B.GB[0] = D.GB0 + zo;
+  B.GB[1] = D.GB1 + zo;
+  B.att = nullptr;
+  B.chk = nullptr;
+  B.tx = nullptr;
+  B.ty = nullptr;
+  return B;
+}
+
+// One member's CSR copy: row offsets from 0, nonzeros at a member offset.
+struct LocalCsr {
+  const int64_t* rp;
+  const int32_t* ci;
+  double* v;
+  int32_t nrows;
+};
+
+// Row r of A times x, summed in index order.  The nonzeros are taken 8 at a time with the
+// index clamped into the row and the extra products masked to +0.0, so the loads of a chunk
+// (and then its gathers) are all in flight together; the sum is bit-identical to the plain
+// left-to-right loop.
+__device__ __forceinline__ double local_row_dot(const LocalCsr& A, int r, const double* __restrict__ x) {
+  constexpr int C = 8;
+  double s = 0.0;
+  const int64_t p0 = A.rp[r], p1 = A.rp[r + 1];
+  for (int64_t base = p0; base < p1; base += C) {
+    double v[C], xv[C];
+    int32_t c[C];
+#pragma unroll
+    for (int k = 0; k < C; ++k) {
+      const int64_t e = (base + k < p1) ? base + k : p1 - 1;
+      v[k] = A.v[e];
+      c[k] = A.ci[e];
+    }
+#pragma unroll
+    for (int k = 0; k < C; ++k) xv[k] = x[c[k]];
+#pragma unroll
+    for (int k = 0; k < C; ++k) s = s + ((base + k < p1) ? v[k] * xv[k] : 0.0);
+  }
+  return s;
+}
+
+#define PDLP_BLOCK_LOOP(idx, total) for (int64_t idx = threadIdx.x; idx < (total); idx += kBlock)
+
+// out = A x, one thread per row.
+__device__ void local_spmv(const LocalCsr& A, const double* x, double* out) {
+  PDLP_BLOCK_LOOP(r, A.nrows) out[r] = local_row_dot(A, int(r), x);
+}
+
+__device__ void batch_gap(DevState& S, const Bufs& B, int mode) {
+  PointPtrs pt[2];
+  gap_points_of(S, B, mode, pt);
+  const int ns = (mode == 0) ? 2 : 1;
+  const double sw = sqrt(S.omega);
+  const int64_t NM = int64_t(B.n) + B.m;
+  {
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    PDLP_BLOCK_LOOP(idx, NM) gap_setup_elem(B, pt, ns, sw, idx, acc);
+    block_sum<6>(acc);
+    if (threadIdx.x == 0) gap_setup_decide(S, mode, acc);
+    __syncthreads();
+  }
+  // bisection, one slot at a time, points recomputed from the bracket (few registers)
+  for (int pass = 0; pass < 13; ++pass) {
+    bool any = false;
+    for (int s = 0; s < ns; ++s) {
+      if (S.gap_state[s] != 0) continue;
+      any = true;
+      const uint64_t lo = S.gap_lo[s], hi = S.gap_hi[s];
+      double acc[kGapPts];
+#pragma unroll
+      for (int i = 0; i < kGapPts; ++i) acc[i] = 0.0;
+      const double* GA = s ? B.GA[1] : B.GA[0];
+      const double* GB = s ? B.GB[1] : B.GB[0];
+      PDLP_BLOCK_LOOP(idx, NM) {
+        const double aa = GA[idx], b = GB[idx];
+        if (aa != 0.0) {
+#pragma unroll
+          for (int i = 0; i < kGapPts; ++i) {
+            const double e = fmin(__longlong_as_double((long long)gap_point(lo, hi, i + 1)) * aa, b);
+            acc[i] += e * e;
+          }
+        }
+      }
+      block_sum<kGapPts>(acc);
+      if (threadIdx.x == 0) gap_bisect_decide_slot(S, s, acc);
+      __syncthreads();
+    }
+    if (!any) break;
+  }
+  {
+    double sstar[2];
+    for (int s = 0; s < 2; ++s)
+      sstar[s] = (S.gap_state[s] == 1) ? INFINITY : __longlong_as_double((long long)S.gap_hi[s]);
+    double acc[2] = {0.0, 0.0};
+    PDLP_BLOCK_LOOP(idx, NM) gap_final_elem(B, S, ns, sstar, idx, acc);
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) gap_final_decide(S, mode, acc, nullptr);
+    __syncthreads();
+  }
+}
+
+__device__ void batch_kkt(DevState& S, const Bufs& B, int mode) {
+  const PointPtrs pt = kkt_point_is_average(S, mode) ? average_point(B) : current_point(B, S.parity);
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  PDLP_BLOCK_LOOP(idx, int64_t(B.n) + B.m) kkt_elem(B, pt, idx, a);
+  block_sum<7>(a);
+  if (threadIdx.x == 0) kkt_decide(S, mode, a, nullptr);
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmpl, double tol,
+                                                        int64_t iter_limit, int ruiz_iters,
+                                                        int pock_chambolle, double primal_importance) {
+  __shared__ DevState S;
+  const BatchInst I = D.inst[blockIdx.x];
+  const Bufs B = batch_bufs(D, I);
+  const LocalCsr K{D.rp + I.rp, D.ci + I.nz, D.v + I.nz, I.m};
+  const LocalCsr KT{D.rpT + I.rpT, D.ciT + I.nz, D.vT + I.nz, I.n};
+  const int n = I.n, m = I.m;
+  const int64_t NM = int64_t(n) + m;
+  if (threadIdx.x == 0) {
+    S = tmpl;
+    S.tol = tol;
+    S.iter_limit = iter_limit;
+  }
+  double* D1 = const_cast<double*>(B.D1);
+  double* D2 = const_cast<double*>(B.D2);
+  PDLP_BLOCK_LOOP(i, m) D1[i] = 1.0;
+  PDLP_BLOCK_LOOP(j, n) D2[j] = 1.0;
+  __syncthreads();
+
+  // ---- diagonal preconditioning (Section 3.5): Ruiz passes, then Pock-Chambolle
+  const int passes = ruiz_iters + (pock_chambolle ? 1 : 0);
+  for (int p = 0; p < passes; ++p) {
+    const bool inf_norm = p < ruiz_iters;
+    PDLP_BLOCK_LOOP(i, m) {
+      double r = 0.0;
+      for (int64_t e = K.rp[i]; e < K.rp[i + 1]; ++e) r = inf_norm ? fmax(r, fabs(K.v[e])) : r + fabs(K.v[e]);
+      const double d = (r > 0.0) ? 1.0 / sqrt(r) : 1.0;
+      B.GB[0][i] = d;
+      D1[i] = D1[i] * d;
+    }
+    PDLP_BLOCK_LOOP(j, n) {
+      double r = 0.0;
+      for (int64_t e = KT.rp[j]; e < KT.rp[j + 1]; ++e) r = inf_norm ? fmax(r, fabs(KT.v[e])) : r + fabs(KT.v[e]);
+      const double d = (r > 0.0) ? 1.0 / sqrt(r) : 1.0;
+      B.GB[1][j] = d;
+      D2[j] = D2[j] * d;
+    }
+    __syncthreads();
+    const double* dr = B.GB[0];
+    const double* dc = B.GB[1];
+    PDLP_BLOCK_LOOP(i, m) {
+      for (int64_t e = K.rp[i]; e < K.rp[i + 1]; ++e) K.v[e] = (K.v[e] * dr[i]) * dc[K.ci[e]];
+    }
+    PDLP_BLOCK_LOOP(j, n) {
+      for (int64_t e = KT.rp[j]; e < KT.rp[j + 1]; ++e) KT.v[e] = (KT.v[e] * dr[KT.ci[e]]) * dc[j];
+    }
+    __syncthreads();
+  }
+  PDLP_BLOCK_LOOP(idx, NM) {
+    if (idx < n) {
+      const double d = B.D2[idx];
+      const_cast<double*>(B.c)[idx] = d * B.c0[idx];
+      const_cast<double*>(B.l)[idx] = B.l0[idx] / d;
+      const_cast<double*>(B.u)[idx] = B.u0[idx] / d;
+    } else {
+      const int i = int(idx - n);
+      const_cast<double*>(B.q)[i] = B.D1[i] * B.q0[i];
+    }
+  }
+  __syncthreads();
+
+  // ---- initial point and scalars
+  {
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    double vmax = 0.0;
+    PDLP_BLOCK_LOOP(idx, NM) {
+      if (idx < n) {
+        const int j = int(idx);
+        const double x0 = fmin(fmax(0.0, B.l[j]), B.u[j]);
+        B.X[0][j] = x0;
+        B.X[1][j] = x0;
+        B.XA[j] = x0;
+        B.Sx[j] = 0.0;
+        B.KTy[j] = 0.0;
+        a[0] += B.c0[j] * B.c0[j];
+        a[2] += B.c[j] * B.c[j];
+      } else {
+        const int i = int(idx - n);
+        B.Y[0][i] = 0.0;
+        B.Y[1][i] = 0.0;
+        B.YA[i] = 0.0;
+        B.Sy[i] = 0.0;
+        a[1] += B.q0[i] * B.q0[i];
+        a[3] += B.q[i] * B.q[i];
+      }
+    }
+    const int64_t nnz = K.rp[m];
+    PDLP_BLOCK_LOOP(e, nnz) vmax = fmax(vmax, fabs(K.v[e]));
+    block_sum<4>(a);
+    vmax = block_max(vmax);
+    if (threadIdx.x == 0) {
+      S.c_norm = sqrt(a[0]);
+      S.q_norm = sqrt(a[1]);
+      const double nc = sqrt(a[2]), nq = sqrt(a[3]);
+      S.omega = ((nc > S.eps_zero && nq > S.eps_zero) ? nc / nq : 1.0) * primal_importance;
+      S.eta_hat = (vmax > 0.0) ? 1.0 / vmax : 1.0;
+      S.eta = S.eta_hat;
+    }
+    __syncthreads();
+    local_spmv(K, B.X[0], B.KX[0]);
+    __syncthreads();
+  }
+
+  // ---- termination check before the first step
+  batch_kkt(S, B, 1);
+
+  // ---- Algorithm 1
+  while (!S.done) {
+    if (!S.check_pending && S.k >= S.iter_limit) {
+      if (threadIdx.x == 0) {
+        S.done = 1;
+        S.status = PDLP_ITERATION_LIMIT;
+        S.out_avg = 0;
+      }
+      __syncthreads();
+      break;
+    }
+    if (!S.check_pending) {
+      // one attempt of Algorithm 2
+      const int P = S.parity;
+      const int kty_valid = S.kty_valid;
+      const PrimalEpi pe{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+      double ax[1] = {0.0};
+      double c1[1];
+      PDLP_BLOCK_LOOP(j, n) {
+        const double s = kty_valid ? B.KTy[j] : local_row_dot(KT, int(j), pick(B.Y, P));
+        pe.row(int(j), s, c1);
+        ax[0] += c1[0];
+      }
+      block_sum<1>(ax);     // its barriers also publish x' to the whole workgroup
+      const DualEpi de{B.q, pick(B.Y, P), pick(B.KX, P), pick(B.Y, P ^ 1), pick(B.KX, P ^ 1), B.Sy, S.eta * S.omega, S.w_pending, B.m1};
+      double ay[2] = {0.0, 0.0};
+      double c2[2];
+      PDLP_BLOCK_LOOP(i, m) {
+        de.row(int(i), local_row_dot(K, int(i), pick(B.X, P ^ 1)), c2);
+        ay[0] += c2[0];
+        ay[1] += c2[1];
+      }
+      block_sum<2>(ay);
+      if (threadIdx.x == 0) {
+        if (!kty_valid) S.spmv_KT += 1;
+        attempt_decide(S, ax[0], ay[0], ay[1], nullptr);
+      }
+      __syncthreads();
+      continue;
+    }
+    // ---- restart / termination check
+    {
+      const int P = S.parity;
+      const double w = S.w_pending, se = S.s_eta;
+      PDLP_BLOCK_LOOP(idx, NM) prepare_elem(B, P, w, se, idx);
+      __syncthreads();
+      if (threadIdx.x == 0) S.w_pending = 0.0;
+      if (S.restarts_on) {
+        local_spmv(KT, B.YB, B.KTYB);
+        local_spmv(K, B.XB, B.KXB);
+      }
+      if (!S.kty_valid) local_spmv(KT, pick(B.Y, P), B.KTy);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        if (S.restarts_on) {
+          S.spmv_K += 1;
+          S.spmv_KT += 1;
+        }
+        if (!S.kty_valid) S.spmv_KT += 1;
+        S.kty_valid = 1;
+      }
+      __syncthreads();
+    }
+    if (S.restarts_on) batch_gap(S, B, 0);
+    batch_kkt(S, B, 0);
+    if (S.done) break;
+    if (S.restarts_on && S.restart) batch_gap(S, B, 1);
+    if (S.restart) {
+      const bool avg = S.use_avg != 0;
+      const int P = S.parity;
+      PDLP_BLOCK_LOOP(idx, NM) apply_elem(B, P, avg, idx);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) apply_decide(S);
+    __syncthreads();
+  }
+
+  // ---- KKT error of the returned point when the solve did not end at a passing check
+  if (S.status != PDLP_OPTIMAL) {
+    if (!S.kty_valid) {
+      local_spmv(KT, pick(B.Y, S.parity), B.KTy);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        S.kty_valid = 1;
+        S.spmv_KT += 1;
+      }
+      __syncthreads();
+    }
+    batch_kkt(S, B, 2);
+  }
+  if (threadIdx.x == 0) D.out_state[blockIdx.x] = S;
+}
+
+// x = D2 x~, y = D1 y~ of every member's returned point into packed outputs.
+__global__ __launch_bounds__(kBlock) void k_batch_output(BatchDev D, double* xo, double* yo) {
+  const BatchInst I = D.inst[blockIdx.x];
+  const Bufs B = batch_bufs(D, I);
+  const DevState& S = D.out_state[blockIdx.x];
+  const bool avg = S.out_avg != 0;
+  const double* xs = avg ? B.XB : pick(B.X, S.parity);
+  const double* ys = avg ? B.YB : pick(B.Y, S.parity);
+  PDLP_BLOCK_LOOP(j, I.n) xo[I.xo + j] = B.D2[j] * xs[j];
+  PDLP_BLOCK_LOOP(i, I.m) yo[I.yo + i] = B.D1[i] * ys[i];
+}
+
+}  // namespace pdlp

@@ -377,6 +377,9 @@ __device__ void combine_rows(const CsrDev& A, const double* __restrict__ part,
   }
 }
 
+// Parity-selected buffer without a runtime array index (keeps a local Bufs out of scratch).
+__device__ __forceinline__ double* pick(double* const (&a)[2], int P) { return P ? a[1] : a[0]; }
+
 // ------------------------------------------------------------------------------------------
 // predicates on the device state
 // ------------------------------------------------------------------------------------------
@@ -454,19 +457,11 @@ struct DualEpi {
   }
 };
 
-// Algorithm 2 decision, run by the last workgroup of the dual-step kernel: the largest step
-// Eq. (5) allows, the next proposal, accept or retry, and the bookkeeping of Algorithm 1.
-__device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA, int nslotA,
-                               const double* partB, int nslotB) {
-  const int P = st->parity;
-  double ax[1], ay[2];
-  sum_slots<1>(partA, nslotA, ax);
-  sum_slots<2>(partB, nslotB, ay);
-  if (threadIdx.x != 0) return;
-  DevState& W = *st;
+// Algorithm 2 decision for one attempt: the largest step Eq. (5) allows, the next proposal,
+// accept or retry, and the bookkeeping of Algorithm 1.  One thread.
+__device__ void attempt_decide(DevState& W, double dx2, double dy2, double cross, pdlp_attempt_rec* att) {
+  const int P = W.parity;
   const double eta = W.eta, omega = W.omega;
-  const double dx2 = ax[0], dy2 = ay[0], cross = ay[1];
-  // Algorithm 2: the largest step Eq. (5) allows, and the next proposal
   const double num = omega * dx2 + dy2 / omega;
   const double den = 2.0 * fabs(cross);
   double eta_bar = (den > 0.0) ? num / den : INFINITY;
@@ -478,8 +473,8 @@ __device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA,
   }
   const bool ok = isfinite(dx2) && isfinite(dy2) && isfinite(cross) && isfinite(eta_next);
   const bool accepted = ok && (eta <= eta_bar);
-  if (W.trace_cap > 0) {
-    pdlp_attempt_rec& rec = B.att[W.n_att_log % W.trace_cap];
+  if (att && W.trace_cap > 0) {
+    pdlp_attempt_rec& rec = att[W.n_att_log % W.trace_cap];
     rec.k = W.k;
     rec.eta = eta;
     rec.eta_bar = eta_bar;
@@ -518,16 +513,25 @@ __device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA,
   }
 }
 
+// Run by the last workgroup of the dual-step kernel.
+__device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA, int nslotA,
+                               const double* partB, int nslotB) {
+  double ax[1], ay[2];
+  sum_slots<1>(partA, nslotA, ax);
+  sum_slots<2>(partB, nslotB, ay);
+  if (threadIdx.x == 0) attempt_decide(*st, ax[0], ay[0], ay[1], B.att);
+}
+
 __global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA,
                                                    unsigned* ticket) {
   const DevState& S = *st;
   if (!attempt_runs(S)) return;
   const int P = S.parity;
   const int kty_valid = S.kty_valid;
-  PrimalEpi epi{B.c, B.l, B.u, B.X[P], B.X[P ^ 1], B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  PrimalEpi epi{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
   double acc[1] = {0.0};
   if (kty_valid) csr_rows_stored(AT, B.KTy, epi, acc, partA);
-  else csr_rows<kProd>(AT, B.Y[P], epi, acc, partA);
+  else csr_rows<kProd>(AT, pick(B.Y, P), epi, acc, partA);
   block_sum<1>(acc);
   write_slot<1>(partA, blockIdx.x, acc);
   if (arrive_last(ticket, gridDim.x)) {
@@ -543,9 +547,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B,
   const DevState& S = *st;
   if (!attempt_runs(S)) return;
   const int P = S.parity;
-  DualEpi epi{B.q, B.Y[P], B.KX[P], B.Y[P ^ 1], B.KX[P ^ 1], B.Sy, S.eta * S.omega, S.w_pending, B.m1};
+  DualEpi epi{B.q, pick(B.Y, P), pick(B.KX, P), pick(B.Y, P ^ 1), pick(B.KX, P ^ 1), B.Sy, S.eta * S.omega, S.w_pending, B.m1};
   double acc[2] = {0.0, 0.0};
-  csr_rows<kProd>(A, B.X[P ^ 1], epi, acc, partB);
+  csr_rows<kProd>(A, pick(B.X, P ^ 1), epi, acc, partB);
   block_sum<2>(acc);
   write_slot<2>(partB, blockIdx.x, acc);
   if (!arrive_last(ticket, gridDim.x)) return;
@@ -561,8 +565,8 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(DevState* st, Bufs B, unsig
   const int64_t kk = S.k - 1;
   for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
        idx += int64_t(gridDim.x) * kBlock) {
-    if (idx < B.n) B.tx[kk * B.n + idx] = B.X[P][idx];
-    else B.ty[kk * B.m + (idx - B.n)] = B.Y[P][idx - B.n];
+    if (idx < B.n) B.tx[kk * B.n + idx] = pick(B.X, P)[idx];
+    else B.ty[kk * B.m + (idx - B.n)] = pick(B.Y, P)[idx - B.n];
   }
   if (arrive_last(ticket, gridDim.x)) {
     if (threadIdx.x == 0) {
@@ -631,7 +635,7 @@ __global__ __launch_bounds__(kBlock) void k_primal_combine(CsrDev AT, DevState* 
   if (!attempt_runs(S)) return;
   const int P = S.parity;
   const int kty_valid = S.kty_valid;
-  PrimalEpi epi{B.c, B.l, B.u, B.X[P], B.X[P ^ 1], B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  PrimalEpi epi{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
   double acc[1] = {0.0};
   combine_rows<kProd>(AT, part, kty_valid ? B.KTy : nullptr, epi, acc);
   block_sum<1>(acc);
@@ -650,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_combine(CsrDev A, DevState* st,
   const DevState& S = *st;
   if (!attempt_runs(S)) return;
   const int P = S.parity;
-  DualEpi epi{B.q, B.Y[P], B.KX[P], B.Y[P ^ 1], B.KX[P ^ 1], B.Sy, S.eta * S.omega, S.w_pending, B.m1};
+  DualEpi epi{B.q, pick(B.Y, P), pick(B.KX, P), pick(B.Y, P ^ 1), pick(B.KX, P ^ 1), B.Sy, S.eta * S.omega, S.w_pending, B.m1};
   double acc[2] = {0.0, 0.0};
   combine_rows<kProd>(A, part, nullptr, epi, acc);
   block_sum<2>(acc);
@@ -797,38 +801,11 @@ __global__ __launch_bounds__(kBlock) void k_init(CsrDev A, DevState* st, Bufs B,
 
 // ------------------------------------------------------------------------------------------
 // restart / termination check (Algorithm 1 every check_every accepted steps)
+//
+// Each stage is split into a per-element piece and a scalar decision taken by one thread,
+// so the multi-workgroup kernels below (grid-stride + last-workgroup ticket) and the batched
+// solver (one workgroup per LP) run the very same arithmetic.
 // ------------------------------------------------------------------------------------------
-
-// Add the pending weighted iterate to the sums and form the averages x_bar = S_x / S_eta.
-__global__ __launch_bounds__(kBlock) void k_check_prepare(DevState* st, Bufs B, unsigned* ticket) {
-  const DevState& S = *st;
-  if (!check_runs(S)) return;
-  const int P = S.parity;
-  const double w = S.w_pending, se = S.s_eta;
-  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
-       idx += int64_t(gridDim.x) * kBlock) {
-    if (idx < B.n) {
-      double s = B.Sx[idx];
-      if (w != 0.0) {
-        s = s + w * B.X[P][idx];
-        B.Sx[idx] = s;
-      }
-      B.XB[idx] = s / se;
-    } else {
-      const int i = int(idx - B.n);
-      double s = B.Sy[i];
-      if (w != 0.0) {
-        s = s + w * B.Y[P][i];
-        B.Sy[i] = s;
-      }
-      B.YB[i] = s / se;
-    }
-  }
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) st->w_pending = 0.0;
-    reset_ticket(ticket);
-  }
-}
 
 struct PointPtrs {
   const double* x;
@@ -838,23 +815,38 @@ struct PointPtrs {
 };
 
 __device__ __forceinline__ PointPtrs current_point(const Bufs& B, int P) {
-  return PointPtrs{B.X[P], B.Y[P], B.KTy, B.KX[P]};
+  return PointPtrs{pick(B.X, P), pick(B.Y, P), B.KTy, pick(B.KX, P)};
 }
 __device__ __forceinline__ PointPtrs average_point(const Bufs& B) {
   return PointPtrs{B.XB, B.YB, B.KTYB, B.KXB};
 }
 
-// Normalized duality gap (Section 3.2), set-up pass: for each slot, the trust-region data
-// |a_i| and b_i (distance to the box along sign(a_i)) and the radius.
+// Add the pending weighted iterate to the sums and form the average x_bar = S_x / S_eta.
+__device__ __forceinline__ void prepare_elem(const Bufs& B, int P, double w, double se, int64_t idx) {
+  if (idx < B.n) {
+    double s = B.Sx[idx];
+    if (w != 0.0) {
+      s = s + w * pick(B.X, P)[idx];
+      B.Sx[idx] = s;
+    }
+    B.XB[idx] = s / se;
+  } else {
+    const int i = int(idx - B.n);
+    double s = B.Sy[i];
+    if (w != 0.0) {
+      s = s + w * pick(B.Y, P)[i];
+      B.Sy[i] = s;
+    }
+    B.YB[i] = s / se;
+  }
+}
+
+// Normalized duality gap (Section 3.2), set-up: the trust-region data |a_i| and b_i (the
+// distance to the box along sign(a_i)) of every slot, and the radius sums.
 // mode 0: slot 0 = current iterate, slot 1 = average, both against the anchor.
 // mode 1: slot 0 = the restart candidate against the old anchor (after the weight update).
-__global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int mode, double* part,
-                                                      unsigned* ticket) {
-  const DevState& S = *st;
-  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+__device__ __forceinline__ void gap_points_of(const DevState& S, const Bufs& B, int mode, PointPtrs (&pt)[2]) {
   const int P = S.parity;
-  const int ns = (mode == 0) ? 2 : 1;
-  PointPtrs pt[2];
   if (mode == 0) {
     pt[0] = current_point(B, P);
     pt[1] = average_point(B);
@@ -862,50 +854,45 @@ __global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int 
     pt[0] = S.use_avg ? average_point(B) : current_point(B, P);
     pt[1] = pt[0];
   }
-  const double omega = S.omega;
-  const double sw = sqrt(omega);
-  double acc[6] = {0, 0, 0, 0, 0, 0};   // per slot: sum dx^2, sum dy^2, f(inf)
-  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
-       idx += int64_t(gridDim.x) * kBlock) {
-    for (int s = 0; s < ns; ++s) {
-      double a, lo, hi;
-      if (idx < B.n) {
-        const int j = int(idx);
-        const double xj = pt[s].x[j];
-        const double d = xj - B.XA[j];
-        acc[3 * s] += d * d;
-        a = -(B.c[j] - pt[s].kty[j]) / sw;
-        lo = sw * (B.l[j] - xj);
-        hi = sw * (B.u[j] - xj);
-      } else {
-        const int i = int(idx - B.n);
-        const double yi = pt[s].y[i];
-        const double d = yi - B.YA[i];
-        acc[3 * s + 1] += d * d;
-        a = sw * (B.q[i] - pt[s].kx[i]);
-        lo = (i < B.m1) ? -yi / sw : -INFINITY;
-        hi = INFINITY;
-      }
-      lo = fmin(lo, 0.0);
-      hi = fmax(hi, 0.0);
-      double aa = fabs(a), b = (a > 0.0) ? hi : -lo;
-      if (a == 0.0) {
-        aa = 0.0;
-        b = 0.0;
-      }
-      B.GA[s][idx] = aa;
-      B.GB[s][idx] = b;
-      acc[3 * s + 2] += b * b;
+}
+
+__device__ __forceinline__ void gap_setup_elem(const Bufs& B, const PointPtrs (&pt)[2], int ns,
+                                               double sw, int64_t idx, double (&acc)[6]) {
+  for (int s = 0; s < ns; ++s) {
+    double a, lo, hi;
+    if (idx < B.n) {
+      const int j = int(idx);
+      const double xj = pt[s].x[j];
+      const double d = xj - B.XA[j];
+      acc[3 * s] += d * d;
+      a = -(B.c[j] - pt[s].kty[j]) / sw;
+      lo = sw * (B.l[j] - xj);
+      hi = sw * (B.u[j] - xj);
+    } else {
+      const int i = int(idx - B.n);
+      const double yi = pt[s].y[i];
+      const double d = yi - B.YA[i];
+      acc[3 * s + 1] += d * d;
+      a = sw * (B.q[i] - pt[s].kx[i]);
+      lo = (i < B.m1) ? -yi / sw : -INFINITY;
+      hi = INFINITY;
     }
+    lo = fmin(lo, 0.0);
+    hi = fmax(hi, 0.0);
+    double aa = fabs(a), b = (a > 0.0) ? hi : -lo;
+    if (a == 0.0) {
+      aa = 0.0;
+      b = 0.0;
+    }
+    B.GA[s][idx] = aa;
+    B.GB[s][idx] = b;
+    acc[3 * s + 2] += b * b;
   }
-  block_sum<6>(acc);
-  write_slot<6>(part, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  reset_ticket(ticket);
-  double t[6];
-  sum_slots<6>(part, gridDim.x, t);
-  if (threadIdx.x != 0) return;
-  DevState& W = *st;
+}
+
+__device__ void gap_setup_decide(DevState& W, int mode, const double (&t)[6]) {
+  const int ns = (mode == 0) ? 2 : 1;
+  const double omega = W.omega;
   for (int s = 0; s < ns; ++s) {
     const double r = sqrt(omega * t[3 * s] + t[3 * s + 1] / omega);
     W.gap_r[s] = r;
@@ -925,98 +912,74 @@ __device__ __forceinline__ uint64_t gap_point(uint64_t lo, uint64_t hi, int i) {
   return lo + (d >> 5) * uint64_t(i) + (((d & 31ull) * uint64_t(i)) >> 5);
 }
 
-// One bisection pass over the breakpoints of ||e(s)||^2 = sum min(s|a_i|, b_i)^2: evaluate
-// it at 31 points splitting [lo, hi] (as bit patterns of positive doubles, which order like
-// the values) and keep the sub-interval where it crosses r^2.
-__global__ __launch_bounds__(kBlock) void k_gap_bisect(DevState* st, Bufs B, int mode, double* part,
-                                                       unsigned* ticket) {
-  const DevState& S = *st;
-  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
-  const bool act0 = S.gap_state[0] == 0;
-  const bool act1 = (mode == 0) && S.gap_state[1] == 0;
-  if (!act0 && !act1) return;
-  double sp[2][kGapPts];
+// One bisection pass over the breakpoints of ||e(s)||^2 = sum min(s|a_i|, b_i)^2: it is
+// evaluated at 32 points splitting [lo, hi] (as bit patterns of positive doubles, which order
+// like the values) and the sub-interval where it crosses r^2 is kept.
+__device__ __forceinline__ void gap_bisect_points(const DevState& S, double (&sp)[2][kGapPts]) {
 #pragma unroll
   for (int i = 0; i < kGapPts; ++i) {
     sp[0][i] = __longlong_as_double((long long)gap_point(S.gap_lo[0], S.gap_hi[0], i + 1));
     sp[1][i] = __longlong_as_double((long long)gap_point(S.gap_lo[1], S.gap_hi[1], i + 1));
   }
-  double acc[2 * kGapPts];
+}
+
+__device__ __forceinline__ void gap_bisect_elem(const Bufs& B, bool act0, bool act1,
+                                                const double (&sp)[2][kGapPts], int64_t idx,
+                                                double (&acc)[2 * kGapPts]) {
+  if (act0) {
+    const double aa = B.GA[0][idx], b = B.GB[0][idx];
+    if (aa != 0.0) {
 #pragma unroll
-  for (int i = 0; i < 2 * kGapPts; ++i) acc[i] = 0.0;
-  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
-       idx += int64_t(gridDim.x) * kBlock) {
-    if (act0) {
-      const double aa = B.GA[0][idx], b = B.GB[0][idx];
-      if (aa != 0.0) {
-#pragma unroll
-        for (int i = 0; i < kGapPts; ++i) {
-          const double e = fmin(sp[0][i] * aa, b);
-          acc[i] += e * e;
-        }
-      }
-    }
-    if (act1) {
-      const double aa = B.GA[1][idx], b = B.GB[1][idx];
-      if (aa != 0.0) {
-#pragma unroll
-        for (int i = 0; i < kGapPts; ++i) {
-          const double e = fmin(sp[1][i] * aa, b);
-          acc[kGapPts + i] += e * e;
-        }
+      for (int i = 0; i < kGapPts; ++i) {
+        const double e = fmin(sp[0][i] * aa, b);
+        acc[i] += e * e;
       }
     }
   }
-  block_sum<2 * kGapPts>(acc);
-  write_slot<2 * kGapPts>(part, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  reset_ticket(ticket);
-  double t[2 * kGapPts];
-  sum_slots<2 * kGapPts>(part, gridDim.x, t);
-  if (threadIdx.x != 0) return;
-  DevState& W = *st;
+  if (act1) {
+    const double aa = B.GA[1][idx], b = B.GB[1][idx];
+    if (aa != 0.0) {
+#pragma unroll
+      for (int i = 0; i < kGapPts; ++i) {
+        const double e = fmin(sp[1][i] * aa, b);
+        acc[kGapPts + i] += e * e;
+      }
+    }
+  }
+}
+
+// t[i] holds f at point i + 1 of slot s (point 32 is hi itself; point 0 is lo).
+__device__ void gap_bisect_decide_slot(DevState& W, int s, const double* t) {
+  const double r2 = W.gap_r[s] * W.gap_r[s];
+  const uint64_t lo = W.gap_lo[s], hi = W.gap_hi[s];
+  int i = 0;
+  while (i < kGapPts && t[i] < r2) ++i;
+  if (i == kGapPts) i = kGapPts - 1;
+  const uint64_t nlo = (i == 0) ? lo : gap_point(lo, hi, i);
+  const uint64_t nhi = gap_point(lo, hi, i + 1);
+  W.gap_lo[s] = nlo;
+  W.gap_hi[s] = nhi;
+  if (nhi - nlo <= 1) W.gap_state[s] = 3;
+}
+
+__device__ void gap_bisect_decide(DevState& W, int mode, const double (&t)[2 * kGapPts]) {
   for (int s = 0; s < 2; ++s) {
     if (W.gap_state[s] != 0 || (s == 1 && mode != 0)) continue;
-    const double r2 = W.gap_r[s] * W.gap_r[s];
-    const uint64_t lo = W.gap_lo[s], hi = W.gap_hi[s];
-    // entry i holds f at point i + 1 (point 32 is hi itself); point 0 is lo
-    int i = 0;
-    while (i < kGapPts && t[s * kGapPts + i] < r2) ++i;
-    if (i == kGapPts) i = kGapPts - 1;
-    const uint64_t nlo = (i == 0) ? lo : gap_point(lo, hi, i);
-    const uint64_t nhi = gap_point(lo, hi, i + 1);
-    W.gap_lo[s] = nlo;
-    W.gap_hi[s] = nhi;
-    if (nhi - nlo <= 1) W.gap_state[s] = 3;
+    gap_bisect_decide_slot(W, s, t + s * kGapPts);
   }
 }
 
 // mu = a^T e(s*) / r with s* the upper end of the final bracket (or +inf).
-__global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int mode, double* part,
-                                                      unsigned* ticket) {
-  const DevState& S = *st;
-  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
-  const int ns = (mode == 0) ? 2 : 1;
-  double sstar[2];
-  for (int s = 0; s < 2; ++s)
-    sstar[s] = (S.gap_state[s] == 1) ? INFINITY : __longlong_as_double((long long)S.gap_hi[s]);
-  double acc[2] = {0.0, 0.0};
-  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
-       idx += int64_t(gridDim.x) * kBlock) {
-    for (int s = 0; s < ns; ++s) {
-      if (S.gap_state[s] == 2) continue;
-      const double aa = B.GA[s][idx], b = B.GB[s][idx];
-      if (aa != 0.0) acc[s] += aa * (isinf(sstar[s]) ? b : fmin(sstar[s] * aa, b));
-    }
+__device__ __forceinline__ void gap_final_elem(const Bufs& B, const DevState& S, int ns,
+                                               const double (&sstar)[2], int64_t idx, double (&acc)[2]) {
+  for (int s = 0; s < ns; ++s) {
+    if (S.gap_state[s] == 2) continue;
+    const double aa = B.GA[s][idx], b = B.GB[s][idx];
+    if (aa != 0.0) acc[s] += aa * (isinf(sstar[s]) ? b : fmin(sstar[s] * aa, b));
   }
-  block_sum<2>(acc);
-  write_slot<2>(part, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  reset_ticket(ticket);
-  double t[2];
-  sum_slots<2>(part, gridDim.x, t);
-  if (threadIdx.x != 0) return;
-  DevState& W = *st;
+}
+
+__device__ void gap_final_decide(DevState& W, int mode, const double (&t)[2], pdlp_check_rec* chk) {
   double mu[2];
   for (int s = 0; s < 2; ++s) mu[s] = (W.gap_state[s] == 2) ? 0.0 : t[s] / W.gap_r[s];
   if (mode == 0) {
@@ -1026,67 +989,56 @@ __global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int 
     W.mu_c = W.use_avg ? mu[1] : mu[0];
   } else {
     W.mu_anchor = mu[0];
-    if (W.trace_cap > 0 && W.n_chk_log > 0) B.chk[(W.n_chk_log - 1) % W.trace_cap].mu_anchor = mu[0];
+    if (chk && W.trace_cap > 0 && W.n_chk_log > 0) chk[(W.n_chk_log - 1) % W.trace_cap].mu_anchor = mu[0];
   }
 }
 
 // Relative KKT error (Section 4.1, Eq. (6a)-(6c)) of a point on the user's unscaled problem:
-// x = D2 x~, K x = (K~ x~) / D1, y = D1 y~, K^T y = (K~^T y~) / D2.
+// x = D2 x~, K x = (K~ x~) / D1, y = D1 y~, K^T y = (K~^T y~) / D2.  Sums: pobj, dobj (q
+// part), dobj (bound part), primal residual^2, dual residual^2, |x~ - xa|^2, |y~ - ya|^2.
+__device__ __forceinline__ void kkt_elem(const Bufs& B, const PointPtrs& pt, int64_t idx, double (&a)[7]) {
+  if (idx < B.n) {
+    const int j = int(idx);
+    const double xs = pt.x[j];
+    const double x = B.D2[j] * xs;
+    const double g = B.c0[j] - pt.kty[j] / B.D2[j];
+    const double lj = B.l0[j], uj = B.u0[j];
+    const bool lf = isfinite(lj), uf = isfinite(uj);
+    double lam = g;
+    if (!lf && !uf) lam = 0.0;
+    else if (!lf) lam = fmin(g, 0.0);
+    else if (!uf) lam = fmax(g, 0.0);
+    const double dr = g - lam;
+    a[4] += dr * dr;
+    a[0] += B.c0[j] * x;
+    double bt = 0.0;
+    if (lf) bt += lj * fmax(lam, 0.0);
+    if (uf) bt += uj * fmin(lam, 0.0);
+    a[2] += bt;
+    const double d = xs - B.XA[j];
+    a[5] += d * d;
+  } else {
+    const int i = int(idx - B.n);
+    const double ys = pt.y[i];
+    const double y = B.D1[i] * ys;
+    const double kx = pt.kx[i] / B.D1[i];
+    const double r = (i < B.m1) ? fmax(B.q0[i] - kx, 0.0) : kx - B.q0[i];
+    a[3] += r * r;
+    a[1] += B.q0[i] * y;
+    const double d = ys - B.YA[i];
+    a[6] += d * d;
+  }
+}
+
+__device__ __forceinline__ bool kkt_point_is_average(const DevState& S, int mode) {
+  return (mode == 0) ? (S.use_avg != 0) : (mode == 2 && S.out_avg != 0);
+}
+
 // mode 0: the restart candidate of a check, followed by the restart decision (criteria
 //         (i)-(iii)) and the primal-weight update (Algorithm 3);
 // mode 1: the current point before the first step (termination only);
 // mode 2: the returned point after the solve stopped.
-__global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, double* part,
-                                                unsigned* ticket) {
-  const DevState& S = *st;
-  if (mode == 0 && !check_runs(S)) return;
-  const int P = S.parity;
-  const bool avg = (mode == 0) ? (S.use_avg != 0) : (mode == 2 && S.out_avg != 0);
-  const PointPtrs pt = avg ? average_point(B) : current_point(B, P);
-  // pobj, dobj (q part), dobj (bound part), primal res^2, dual res^2, |dx|^2, |dy|^2
-  double a[7] = {0, 0, 0, 0, 0, 0, 0};
-  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
-       idx += int64_t(gridDim.x) * kBlock) {
-    if (idx < B.n) {
-      const int j = int(idx);
-      const double xs = pt.x[j];
-      const double x = B.D2[j] * xs;
-      const double g = B.c0[j] - pt.kty[j] / B.D2[j];
-      const double lj = B.l0[j], uj = B.u0[j];
-      const bool lf = isfinite(lj), uf = isfinite(uj);
-      double lam = g;
-      if (!lf && !uf) lam = 0.0;
-      else if (!lf) lam = fmin(g, 0.0);
-      else if (!uf) lam = fmax(g, 0.0);
-      const double dr = g - lam;
-      a[4] += dr * dr;
-      a[0] += B.c0[j] * x;
-      double bt = 0.0;
-      if (lf) bt += lj * fmax(lam, 0.0);
-      if (uf) bt += uj * fmin(lam, 0.0);
-      a[2] += bt;
-      const double d = xs - B.XA[j];
-      a[5] += d * d;
-    } else {
-      const int i = int(idx - B.n);
-      const double ys = pt.y[i];
-      const double y = B.D1[i] * ys;
-      const double kx = pt.kx[i] / B.D1[i];
-      const double r = (i < B.m1) ? fmax(B.q0[i] - kx, 0.0) : kx - B.q0[i];
-      a[3] += r * r;
-      a[1] += B.q0[i] * y;
-      const double d = ys - B.YA[i];
-      a[6] += d * d;
-    }
-  }
-  block_sum<7>(a);
-  write_slot<7>(part, blockIdx.x, a);
-  if (!arrive_last(ticket, gridDim.x)) return;
-  reset_ticket(ticket);
-  double t[7];
-  sum_slots<7>(part, gridDim.x, t);
-  if (threadIdx.x != 0) return;
-  DevState& W = *st;
+__device__ void kkt_decide(DevState& W, int mode, const double (&t)[7], pdlp_check_rec* chk) {
   const double pobj = t[0], dobj = t[1] + t[2];
   const double e_gap = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
   const double e_pri = sqrt(t[3]) / (1.0 + W.q_norm);
@@ -1111,8 +1063,8 @@ __global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, 
   }
   W.checks += 1;
   pdlp_check_rec* rec = nullptr;
-  if (W.trace_cap > 0) {
-    rec = &B.chk[W.n_chk_log % W.trace_cap];
+  if (chk && W.trace_cap > 0) {
+    rec = &chk[W.n_chk_log % W.trace_cap];
     rec->k = W.k;
     rec->mu_cur = W.restarts_on ? W.mu_cur : NAN;
     rec->mu_avg = W.restarts_on ? W.mu_avg : NAN;
@@ -1156,41 +1108,31 @@ __global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, 
 }
 
 // Restart (Algorithm 1): z <- z_c, anchor <- z_c, sums cleared; then close the check.
-__global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, unsigned* ticket) {
-  const DevState& S = *st;
-  if (!check_runs(S)) return;
-  const int P = S.parity;
-  if (S.restart) {
-    const bool avg = S.use_avg != 0;
-    for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
-         idx += int64_t(gridDim.x) * kBlock) {
-      if (idx < B.n) {
-        const int j = int(idx);
-        double xc = B.X[P][j];
-        if (avg) {
-          xc = B.XB[j];
-          B.X[P][j] = xc;
-          B.KTy[j] = B.KTYB[j];
-        }
-        B.XA[j] = xc;
-        B.Sx[j] = 0.0;
-      } else {
-        const int i = int(idx - B.n);
-        double yc = B.Y[P][i];
-        if (avg) {
-          yc = B.YB[i];
-          B.Y[P][i] = yc;
-          B.KX[P][i] = B.KXB[i];
-        }
-        B.YA[i] = yc;
-        B.Sy[i] = 0.0;
-      }
+__device__ __forceinline__ void apply_elem(const Bufs& B, int P, bool avg, int64_t idx) {
+  if (idx < B.n) {
+    const int j = int(idx);
+    double xc = pick(B.X, P)[j];
+    if (avg) {
+      xc = B.XB[j];
+      pick(B.X, P)[j] = xc;
+      B.KTy[j] = B.KTYB[j];
     }
+    B.XA[j] = xc;
+    B.Sx[j] = 0.0;
+  } else {
+    const int i = int(idx - B.n);
+    double yc = pick(B.Y, P)[i];
+    if (avg) {
+      yc = B.YB[i];
+      pick(B.Y, P)[i] = yc;
+      pick(B.KX, P)[i] = B.KXB[i];
+    }
+    B.YA[i] = yc;
+    B.Sy[i] = 0.0;
   }
-  if (!arrive_last(ticket, gridDim.x)) return;
-  reset_ticket(ticket);
-  if (threadIdx.x != 0) return;
-  DevState& W = *st;
+}
+
+__device__ void apply_decide(DevState& W) {
   if (W.restart) {
     W.s_eta = 0.0;
     W.t = 0;
@@ -1208,6 +1150,110 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, un
     W.status = PDLP_ITERATION_LIMIT;
     W.out_avg = 0;
   }
+}
+
+#define PDLP_GRID_LOOP(idx, total) \
+  for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < (total); idx += int64_t(gridDim.x) * kBlock)
+
+__global__ __launch_bounds__(kBlock) void k_check_prepare(DevState* st, Bufs B, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!check_runs(S)) return;
+  const int P = S.parity;
+  const double w = S.w_pending, se = S.s_eta;
+  PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) prepare_elem(B, P, w, se, idx);
+  if (arrive_last(ticket, gridDim.x)) {
+    if (threadIdx.x == 0) st->w_pending = 0.0;
+    reset_ticket(ticket);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int mode, double* part,
+                                                      unsigned* ticket) {
+  const DevState& S = *st;
+  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  PointPtrs pt[2];
+  gap_points_of(S, B, mode, pt);
+  const int ns = (mode == 0) ? 2 : 1;
+  const double sw = sqrt(S.omega);
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_setup_elem(B, pt, ns, sw, idx, acc);
+  block_sum<6>(acc);
+  write_slot<6>(part, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[6];
+  sum_slots<6>(part, gridDim.x, t);
+  if (threadIdx.x == 0) gap_setup_decide(*st, mode, t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gap_bisect(DevState* st, Bufs B, int mode, double* part,
+                                                       unsigned* ticket) {
+  const DevState& S = *st;
+  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  const bool act0 = S.gap_state[0] == 0;
+  const bool act1 = (mode == 0) && S.gap_state[1] == 0;
+  if (!act0 && !act1) return;
+  double sp[2][kGapPts];
+  gap_bisect_points(S, sp);
+  double acc[2 * kGapPts];
+#pragma unroll
+  for (int i = 0; i < 2 * kGapPts; ++i) acc[i] = 0.0;
+  PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_bisect_elem(B, act0, act1, sp, idx, acc);
+  block_sum<2 * kGapPts>(acc);
+  write_slot<2 * kGapPts>(part, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[2 * kGapPts];
+  sum_slots<2 * kGapPts>(part, gridDim.x, t);
+  if (threadIdx.x == 0) gap_bisect_decide(*st, mode, t);
+}
+
+__global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int mode, double* part,
+                                                      unsigned* ticket) {
+  const DevState& S = *st;
+  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  const int ns = (mode == 0) ? 2 : 1;
+  double sstar[2];
+  for (int s = 0; s < 2; ++s)
+    sstar[s] = (S.gap_state[s] == 1) ? INFINITY : __longlong_as_double((long long)S.gap_hi[s]);
+  double acc[2] = {0.0, 0.0};
+  PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_final_elem(B, S, ns, sstar, idx, acc);
+  block_sum<2>(acc);
+  write_slot<2>(part, blockIdx.x, acc);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[2];
+  sum_slots<2>(part, gridDim.x, t);
+  if (threadIdx.x == 0) gap_final_decide(*st, mode, t, B.chk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, double* part,
+                                                unsigned* ticket) {
+  const DevState& S = *st;
+  if (mode == 0 && !check_runs(S)) return;
+  const PointPtrs pt = kkt_point_is_average(S, mode) ? average_point(B) : current_point(B, S.parity);
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) kkt_elem(B, pt, idx, a);
+  block_sum<7>(a);
+  write_slot<7>(part, blockIdx.x, a);
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  double t[7];
+  sum_slots<7>(part, gridDim.x, t);
+  if (threadIdx.x == 0) kkt_decide(*st, mode, t, B.chk);
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, unsigned* ticket) {
+  const DevState& S = *st;
+  if (!check_runs(S)) return;
+  const int P = S.parity;
+  if (S.restart) {
+    const bool avg = S.use_avg != 0;
+    PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) apply_elem(B, P, avg, idx);
+  }
+  if (!arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  if (threadIdx.x == 0) apply_decide(*st);
 }
 
 // Resume from a checkpoint: vectors already copied into X[0], Y[0], XA, YA, Sx, Sy.
@@ -1293,8 +1339,8 @@ __global__ __launch_bounds__(kBlock) void k_output(const DevState* st, Bufs B, d
   const DevState& S = *st;
   const int P = S.parity;
   const bool avg = (which == 0) && S.out_avg;
-  const double* xs = avg ? B.XB : B.X[P];
-  const double* ys = avg ? B.YB : B.Y[P];
+  const double* xs = avg ? B.XB : pick(B.X, P);
+  const double* ys = avg ? B.YB : pick(B.Y, P);
   for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m;
        idx += int64_t(gridDim.x) * kBlock) {
     if (idx < B.n) xo[idx] = (which == 0) ? B.D2[idx] * xs[idx] : xs[idx];

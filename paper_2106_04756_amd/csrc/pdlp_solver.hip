@@ -20,6 +20,7 @@
 #include "pdlp_device.h"
 #include "pdlp_internal.h"
 #include "pdlp_kernels.hip"
+#include "pdlp_batch.hip"
 
 using namespace pdlp;
 
@@ -931,6 +932,333 @@ int pdlp_reset_kernel_times(pdlp_solver* s) {
   s->t_ms[0] = s->t_ms[1] = 0.0;
   s->t_cnt[0] = s->t_cnt[1] = 0;
   return 0;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// batched solver
+// ------------------------------------------------------------------------------------------
+
+struct pdlp_batch {
+  hipStream_t stream = nullptr;
+  int64_t count = 0, total_n = 0, total_m = 0;
+  pdlp_options opts{};
+  std::vector<void*> allocs;
+  std::vector<BatchInst> inst;
+  BatchDev D{};
+  DevState tmpl{};
+  double* xout = nullptr;
+  double* yout = nullptr;
+  std::string err;
+  bool solved = false;
+  double create_seconds = 0.0, solve_seconds = 0.0;
+
+  ~pdlp_batch() {
+    if (stream) (void)hipStreamSynchronize(stream);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t alloc(T** p, size_t count_) {
+    const size_t bytes = std::max<size_t>(count_, 1) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+    if (e == hipSuccess) allocs.push_back(*p);
+    return e;
+  }
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+template <class T>
+int batch_fetch(pdlp_batch* b, const T* p, size_t count, std::vector<T>& tmp, const T** out) {
+  if (count == 0) {
+    *out = p;
+    return 0;
+  }
+  if (is_device_ptr(p)) {
+    tmp.resize(count);
+    PDLP_HIP(b, hipMemcpy(tmp.data(), p, count * sizeof(T), hipMemcpyDeviceToHost));
+    *out = tmp.data();
+  } else {
+    *out = p;
+  }
+  return 0;
+}
+
+template <class T>
+int batch_upload(pdlp_batch* b, const T* h, size_t count, T** d) {
+  PDLP_HIP(b, b->alloc(d, count));
+  if (count) PDLP_HIP(b, hipMemcpy(*d, h, count * sizeof(T), hipMemcpyHostToDevice));
+  return 0;
+}
+
+int batch_create_impl(pdlp_batch* b, int64_t count, const int64_t* hm, const int64_t* hn,
+                      const int64_t* hneq, const double* c, const int64_t* row_ptr,
+                      const int32_t* col_idx, const double* val, const double* q, const double* l,
+                      const double* u) {
+  if (count < 1 || !hm || !hn || !hneq || !c || !row_ptr || !l || !u) {
+    b->err = "count must be >= 1 and the size arrays and c, row_ptr, l, u non-null";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  std::vector<int64_t> vm, vn, vneq;
+  const int64_t *pm, *pn, *pneq;
+  int rc;
+  if ((rc = batch_fetch(b, hm, size_t(count), vm, &pm)) || (rc = batch_fetch(b, hn, size_t(count), vn, &pn)) ||
+      (rc = batch_fetch(b, hneq, size_t(count), vneq, &pneq)))
+    return rc;
+  b->inst.resize(size_t(count));
+  int64_t rp_total = 0, rpT_total = 0, tn = 0, tm = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    if (pn[k] < 1 || pm[k] < 0 || pneq[k] < 0 || pneq[k] > pm[k] || pm[k] >= (int64_t(1) << 31) ||
+        pn[k] >= (int64_t(1) << 31)) {
+      b->err = "invalid sizes of member " + std::to_string(k);
+      return PDLP_ERR_INVALID_ARGUMENT;
+    }
+    BatchInst& I = b->inst[size_t(k)];
+    I.m = int32_t(pm[k]);
+    I.n = int32_t(pn[k]);
+    I.m1 = int32_t(pm[k] - pneq[k]);
+    I.pad = 0;
+    I.rp = rp_total;
+    I.rpT = rpT_total;
+    I.xo = tn;
+    I.yo = tm;
+    rp_total += pm[k] + 1;
+    rpT_total += pn[k] + 1;
+    tn += pn[k];
+    tm += pm[k];
+  }
+  if (tm > 0 && !q) {
+    b->err = "q is NULL";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  b->count = count;
+  b->total_n = tn;
+  b->total_m = tm;
+  std::vector<int64_t> vrp;
+  const int64_t* rp;
+  if ((rc = batch_fetch(b, row_ptr, size_t(rp_total), vrp, &rp))) return rc;
+  int64_t nz_total = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    BatchInst& I = b->inst[size_t(k)];
+    I.nz = nz_total;
+    const int64_t nnz_k = rp[I.rp + I.m];
+    if (rp[I.rp] != 0 || nnz_k < 0) {
+      b->err = "row offsets of member " + std::to_string(k) + " must start at 0";
+      return PDLP_ERR_INVALID_ARGUMENT;
+    }
+    nz_total += nnz_k;
+  }
+  if (nz_total > 0 && (!col_idx || !val)) {
+    b->err = "null col_idx or val";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  std::vector<int32_t> vci;
+  std::vector<double> vv, vc, vq, vl, vu;
+  const int32_t* ci;
+  const double *v, *hc, *hq, *hl, *hu;
+  if ((rc = batch_fetch(b, col_idx, size_t(nz_total), vci, &ci)) ||
+      (rc = batch_fetch(b, val, size_t(nz_total), vv, &v)) || (rc = batch_fetch(b, c, size_t(tn), vc, &hc)) ||
+      (rc = batch_fetch(b, q, size_t(tm), vq, &hq)) || (rc = batch_fetch(b, l, size_t(tn), vl, &hl)) ||
+      (rc = batch_fetch(b, u, size_t(tn), vu, &hu)))
+    return rc;
+  // validate every member and build its transposed copy
+  std::vector<int64_t> rpT(static_cast<size_t>(rpT_total));
+  std::vector<int32_t> ciT(static_cast<size_t>(nz_total));
+  std::vector<double> vT(static_cast<size_t>(nz_total));
+  for (int64_t k = 0; k < count; ++k) {
+    const BatchInst& I = b->inst[size_t(k)];
+    const int64_t* rpk = rp + I.rp;
+    const std::string bad = validate_lp(I.m, I.n, I.m - I.m1, hc + I.xo, rpk, ci + I.nz, v + I.nz,
+                                        hq + I.yo, hl + I.xo, hu + I.xo);
+    if (!bad.empty()) {
+      b->err = "member " + std::to_string(k) + ": " + bad;
+      return PDLP_ERR_INVALID_ARGUMENT;
+    }
+    std::vector<int64_t> trp;
+    std::vector<int32_t> tci;
+    std::vector<double> tv;
+    transpose_csr(I.m, I.n, rpk, ci + I.nz, v + I.nz, trp, tci, tv);
+    std::copy(trp.begin(), trp.end(), rpT.begin() + I.rpT);
+    std::copy(tci.begin(), tci.end(), ciT.begin() + I.nz);
+    std::copy(tv.begin(), tv.end(), vT.begin() + I.nz);
+  }
+  BatchDev& D = b->D;
+  BatchInst* dinst;
+  int64_t* drp;
+  int64_t* drpT;
+  int32_t* dci;
+  int32_t* dciT;
+  if ((rc = batch_upload(b, b->inst.data(), b->inst.size(), &dinst)) ||
+      (rc = batch_upload(b, rp, size_t(rp_total), &drp)) || (rc = batch_upload(b, rpT.data(), rpT.size(), &drpT)) ||
+      (rc = batch_upload(b, ci, size_t(nz_total), &dci)) || (rc = batch_upload(b, ciT.data(), ciT.size(), &dciT)) ||
+      (rc = batch_upload(b, v, size_t(nz_total), &D.v)) || (rc = batch_upload(b, vT.data(), vT.size(), &D.vT)) ||
+      (rc = batch_upload(b, hc, size_t(tn), &D.c0)) || (rc = batch_upload(b, hl, size_t(tn), &D.l0)) ||
+      (rc = batch_upload(b, hu, size_t(tn), &D.u0)) || (rc = batch_upload(b, hq, size_t(tm), &D.q0)))
+    return rc;
+  D.inst = dinst;
+  D.rp = drp;
+  D.rpT = drpT;
+  D.ci = dci;
+  D.ciT = dciT;
+  for (double** p : {&D.c, &D.l, &D.u, &D.D2, &D.X0, &D.X1, &D.KTy, &D.Sx, &D.XB, &D.KTYB, &D.XA})
+    PDLP_HIP(b, b->alloc(p, size_t(tn)));
+  for (double** p : {&D.q, &D.D1, &D.Y0, &D.Y1, &D.KX0, &D.KX1, &D.Sy, &D.YB, &D.KXB, &D.YA})
+    PDLP_HIP(b, b->alloc(p, size_t(tm)));
+  for (double** p : {&D.GA0, &D.GA1, &D.GB0, &D.GB1}) PDLP_HIP(b, b->alloc(p, size_t(tn + tm)));
+  PDLP_HIP(b, b->alloc(&D.out_state, size_t(count)));
+  PDLP_HIP(b, b->alloc(&b->xout, size_t(tn)));
+  PDLP_HIP(b, b->alloc(&b->yout, size_t(tm)));
+  // per-member state template (no traces in batched mode)
+  DevState& h = b->tmpl;
+  h = DevState{};
+  h.mu_prev = INFINITY;
+  h.mu_anchor = INFINITY;
+  h.kty_valid = 1;
+  h.status = PDLP_NOT_SOLVED;
+  h.check_every = b->opts.check_every;
+  h.max_retries = b->opts.max_retries;
+  h.trace_iters = 0;
+  h.trace_cap = 0;
+  h.restarts_on = b->opts.adaptive_restarts;
+  h.pw_on = b->opts.primal_weight_update;
+  h.constant_step = 0;
+  h.to_current = b->opts.restart_to_current != 0;
+  h.beta_suff = b->opts.beta_sufficient;
+  h.beta_nec = b->opts.beta_necessary;
+  h.beta_art = b->opts.beta_artificial;
+  h.theta = b->opts.theta;
+  h.eps_zero = b->opts.eps_zero;
+  return 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pdlp_batch_create(pdlp_batch** out, int64_t count, const int64_t* m, const int64_t* n,
+                      const int64_t* n_eq, const double* c, const int64_t* row_ptr,
+                      const int32_t* col_idx, const double* val, const double* q, const double* l,
+                      const double* u, const pdlp_options* opts, void* hip_stream) {
+  if (!out) {
+    g_batch_error = "out is NULL";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  *out = nullptr;
+  const double t0 = now_s();
+  pdlp_batch* b = nullptr;
+  try {
+    b = new pdlp_batch();
+  } catch (...) {
+    g_batch_error = "host allocation failed";
+    return PDLP_ERR_OUT_OF_MEMORY;
+  }
+  if (opts) b->opts = *opts;
+  else pdlp_default_options(&b->opts);
+  const pdlp_options& o = b->opts;
+  if (o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || !(o.theta >= 0.0 && o.theta <= 1.0) ||
+      !(o.primal_importance > 0.0) || !(o.eps_zero >= 0.0) || o.step_policy != 0) {
+    g_batch_error = "invalid options (the batched solver uses the adaptive step policy)";
+    delete b;
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  int rc;
+  try {
+    rc = batch_create_impl(b, count, m, n, n_eq, c, row_ptr, col_idx, val, q, l, u);
+  } catch (const std::bad_alloc&) {
+    b->err = "host allocation failed";
+    rc = PDLP_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    b->err = "unexpected host exception";
+    rc = PDLP_ERR_DEVICE;
+  }
+  if (rc != 0) {
+    g_batch_error = b->err;
+    delete b;
+    return rc;
+  }
+  b->create_seconds = now_s() - t0;
+  *out = b;
+  return 0;
+}
+
+int pdlp_batch_solve(pdlp_batch* b, double tol, int64_t iter_limit) {
+  if (!b) return PDLP_ERR_INVALID_ARGUMENT;
+  if (!(tol >= 0.0) || iter_limit < 0) {
+    b->err = "tol must be >= 0 and iter_limit >= 0";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  if (b->solved) {
+    b->err = "a batch is solved once (create a new batch to solve again)";
+    return PDLP_ERR_INVALID_STATE;
+  }
+  const double t0 = now_s();
+  k_batch_solve<<<unsigned(b->count), kBlock, 0, b->stream>>>(b->D, b->tmpl, tol, iter_limit,
+                                                             b->opts.ruiz_iters, b->opts.pock_chambolle,
+                                                             b->opts.primal_importance);
+  PDLP_LAUNCH(b);
+  PDLP_HIP(b, hipStreamSynchronize(b->stream));
+  b->solved = true;
+  b->solve_seconds = now_s() - t0;
+  return 0;
+}
+
+int pdlp_batch_get(const pdlp_batch* cb, double* x, double* y, int32_t* status, int64_t* iterations,
+                   double* kkt) {
+  if (!cb) return PDLP_ERR_INVALID_ARGUMENT;
+  pdlp_batch* b = const_cast<pdlp_batch*>(cb);
+  if (!b->solved) {
+    b->err = "pdlp_batch_get before pdlp_batch_solve";
+    return PDLP_ERR_INVALID_STATE;
+  }
+  if (x || y) {
+    k_batch_output<<<unsigned(b->count), kBlock, 0, b->stream>>>(b->D, b->xout, b->yout);
+    PDLP_LAUNCH(b);
+    PDLP_HIP(b, hipStreamSynchronize(b->stream));
+    auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+      if (!dst || bytes == 0) return 0;
+      const hipMemcpyKind kind = is_device_ptr(dst) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+      PDLP_HIP(b, hipMemcpy(dst, src, bytes, kind));
+      return 0;
+    };
+    int rc;
+    if ((rc = put(x, b->xout, size_t(b->total_n) * 8)) || (rc = put(y, b->yout, size_t(b->total_m) * 8))) return rc;
+  }
+  if (status || iterations || kkt) {
+    std::vector<DevState> h(static_cast<size_t>(b->count));
+    PDLP_HIP(b, hipMemcpy(h.data(), b->D.out_state, h.size() * sizeof(DevState), hipMemcpyDeviceToHost));
+    std::vector<int32_t> st(h.size());
+    std::vector<int64_t> it(h.size());
+    std::vector<double> kk(4 * h.size());
+    for (size_t k = 0; k < h.size(); ++k) {
+      st[k] = h[k].status;
+      it[k] = h[k].k;
+      for (int q = 0; q < 4; ++q) kk[4 * k + q] = h[k].kkt[q];
+    }
+    auto put = [&](void* dst, const void* src, size_t bytes) -> int {
+      if (!dst) return 0;
+      if (is_device_ptr(dst)) PDLP_HIP(b, hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice));
+      else std::memcpy(dst, src, bytes);
+      return 0;
+    };
+    int rc;
+    if ((rc = put(status, st.data(), st.size() * 4)) || (rc = put(iterations, it.data(), it.size() * 8)) ||
+        (rc = put(kkt, kk.data(), kk.size() * 8)))
+      return rc;
+  }
+  return 0;
+}
+
+double pdlp_batch_solve_seconds(const pdlp_batch* b) { return b ? b->solve_seconds : -1.0; }
+
+void pdlp_batch_destroy(pdlp_batch* b) { delete b; }
+
+const char* pdlp_batch_last_error(const pdlp_batch* b) {
+  if (!b) return g_batch_error.c_str();
+  return b->err.c_str();
 }
 
 }  // extern "C"

@@ -24,7 +24,8 @@ EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pd
             "pdlp_destroy", "pdlp_last_error", "pdlp_get_state", "pdlp_set_state",
             "pdlp_get_scaling", "pdlp_get_iterate",
             "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
-            "pdlp_build_schedule"]
+            "pdlp_build_schedule", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
+            "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error"]
 
 
 class Options(ctypes.Structure):
@@ -120,6 +121,19 @@ def lib() -> ctypes.CDLL:
         L.pdlp_reset_kernel_times.restype = ctypes.c_int
         L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P, P]
         L.pdlp_build_schedule.restype = ctypes.c_int
+        L.pdlp_batch_create.argtypes = [ctypes.POINTER(P), I64, P, P, P, P, P, P, P, P, P, P,
+                                        ctypes.POINTER(Options), P]
+        L.pdlp_batch_create.restype = ctypes.c_int
+        L.pdlp_batch_solve.argtypes = [P, ctypes.c_double, I64]
+        L.pdlp_batch_solve.restype = ctypes.c_int
+        L.pdlp_batch_get.argtypes = [P, P, P, P, P, P]
+        L.pdlp_batch_get.restype = ctypes.c_int
+        L.pdlp_batch_solve_seconds.argtypes = [P]
+        L.pdlp_batch_solve_seconds.restype = ctypes.c_double
+        L.pdlp_batch_destroy.argtypes = [P]
+        L.pdlp_batch_destroy.restype = None
+        L.pdlp_batch_last_error.argtypes = [P]
+        L.pdlp_batch_last_error.restype = ctypes.c_char_p
         _lib = L
     return _lib
 
@@ -332,3 +346,66 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+class Batch:
+    """Many independent LPs solved in one persistent launch (one workgroup per LP).
+    See pdlp_batch_create in include/pdlp.h."""
+
+    def __init__(self, lps, options: Options | None = None, stream=None, **option_overrides):
+        L = lib()
+        if options is None:
+            options = default_options(**option_overrides)
+        self.options = options
+        self.count = len(lps)
+        self.m = np.array([lp.m for lp in lps], dtype=np.int64)
+        self.n = np.array([lp.n for lp in lps], dtype=np.int64)
+        self.n_eq = np.array([lp.n_eq for lp in lps], dtype=np.int64)
+        cat = lambda key, dt: np.ascontiguousarray(np.concatenate([np.asarray(getattr(lp, key)) for lp in lps]), dtype=dt)
+        arrs = [self.m, self.n, self.n_eq, cat("c", np.float64), cat("row_ptr", np.int64),
+                cat("col_idx", np.int32), cat("val", np.float64), cat("q", np.float64),
+                cat("l", np.float64), cat("u", np.float64)]
+        self._keep = arrs
+        self._stream = stream if stream is not None else _default_stream()
+        h = ctypes.c_void_p()
+        rc = L.pdlp_batch_create(ctypes.byref(h), self.count, *[a.ctypes.data for a in arrs],
+                                 ctypes.byref(options), self._stream)
+        if rc != 0:
+            raise PdlpError(rc, L.pdlp_batch_last_error(None).decode())
+        self._h = h
+        self.xoff = np.concatenate([[0], np.cumsum(self.n)])
+        self.yoff = np.concatenate([[0], np.cumsum(self.m)])
+
+    def _check(self, rc):
+        if rc < 0:
+            raise PdlpError(rc, lib().pdlp_batch_last_error(self._h).decode())
+        return rc
+
+    def solve(self, tol: float = 1e-8, iter_limit: int = 100000) -> float:
+        """Solve every member; returns the wall time of the launch in seconds."""
+        self._check(lib().pdlp_batch_solve(self._h, float(tol), int(iter_limit)))
+        return lib().pdlp_batch_solve_seconds(self._h)
+
+    def get(self):
+        """(list of x, list of y, status[count], iterations[count], kkt[count, 4])."""
+        x = np.empty(int(self.xoff[-1]))
+        y = np.empty(max(int(self.yoff[-1]), 1))
+        st = np.empty(self.count, dtype=np.int32)
+        it = np.empty(self.count, dtype=np.int64)
+        kkt = np.empty((self.count, 4))
+        self._check(lib().pdlp_batch_get(self._h, x.ctypes.data, y.ctypes.data, st.ctypes.data,
+                                         it.ctypes.data, kkt.ctypes.data))
+        xs = [x[self.xoff[k]:self.xoff[k + 1]] for k in range(self.count)]
+        ys = [y[self.yoff[k]:self.yoff[k + 1]] for k in range(self.count)]
+        return xs, ys, st, it, kkt
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pdlp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -339,3 +339,45 @@ def test_get_before_solve_and_device_outputs():
     s2.solve(1e-8, 200)
     x2, y2, _ = s2.get()
     assert np.array_equal(x, x2) and np.array_equal(y, y2)
+
+
+# ------------------------------------------------------------------------------------------
+# batched solve (one workgroup per LP)
+# ------------------------------------------------------------------------------------------
+
+def test_batched_solve_matches_oracle_and_single_solver():
+    members = [lpgen.batched_instance(i) for i in (2, 3, 5, 7)] + [lpgen.config0(1)] + \
+              [lpgen.add_empty_row_and_column(lpgen.tiny_plain(3, 60, 150, 20, 4))]
+    say("batch", [lp.m for lp in members])
+    b = P.Batch(members)
+    b.solve(1e-8, 100000)
+    xs, ys, st, it, kkt = b.get()
+    for k, lp in enumerate(members):
+        ref = O.solve_lp(lp, tol=1e-8, iter_limit=100000)
+        assert st[k] == ref.status == O.OPTIMAL, (k, st[k], ref.status)
+        kk = O.kkt(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, xs[k], ys[k])
+        assert kk["kkt"] <= 1e-8, (k, kk)
+        assert abs(kk["kkt"] - kkt[k, 3]) <= 1e-10
+        assert abs(kk["pobj"] - ref.kkt["pobj"]) <= 1e-6 * (1 + abs(ref.kkt["pobj"]))
+        assert 0.5 * ref.k <= it[k] <= 2 * ref.k, (k, it[k], ref.k)
+
+
+def test_batched_first_steps_match_oracle():
+    """Iteration limit 40: every member's returned point (the current iterate) after one
+    check equals the oracle's at the iterate tolerance."""
+    members = [lpgen.batched_instance(i) for i in range(8)]
+    b = P.Batch(members)
+    b.solve(1e-30, 40)
+    xs, ys, st, it, _ = b.get()
+    for k, lp in enumerate(members):
+        ref = O.solve_lp(lp, tol=1e-30, iter_limit=40)
+        assert st[k] == P.ITERATION_LIMIT and it[k] == 40
+        assert rel(xs[k], ref.x) <= 1e-11 and rel(ys[k], ref.y) <= 1e-11, k
+
+
+def test_batched_rejects_bad_member():
+    lps = [lpgen.batched_instance(0), lpgen.config0()]
+    lps[1].l = lps[1].l.copy()
+    lps[1].l[3] = 20.0
+    with pytest.raises(P.PdlpError, match="member 1"):
+        P.Batch(lps)
