@@ -544,3 +544,92 @@ def solve_lp(lp, tol=1e-8, iter_limit=100000, opts=None, trace_iters=0, record_t
     """solve() on a workloads.lpgen.LP."""
     return solve(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, tol, iter_limit, opts,
                  trace_iters, record_trace, record_states)
+
+
+# ------------------------------------------------------------------------------------------
+# Unrolled PDHG and its adjoint (differentiation through a fixed number of steps of Eq. (3))
+# ------------------------------------------------------------------------------------------
+
+def unroll_forward(Kt, ct, qt, lt, ut, m1, eta, omega, T):
+    """T steps of Eq. (3) with fixed tau = eta/omega, sigma = eta*omega on the preconditioned
+    problem, from x0 = proj_X(0), y0 = 0 (Section 4.1 initialisation).  The dual step uses
+    K~(2x' - x) as printed.  Returns the lists of iterates x_0..x_T, y_0..y_T."""
+    Kt = sp.csr_matrix(Kt)
+    KT = Kt.T.tocsr()
+    tau, sigma = eta / omega, eta * omega
+    x = np.clip(np.zeros(Kt.shape[1]), lt, ut)
+    y = np.zeros(Kt.shape[0])
+    xs, ys = [x], [y]
+    for _ in range(T):
+        xn = np.clip(x - tau * (ct - KT @ y), lt, ut)
+        yn = y + sigma * (qt - Kt @ (2.0 * xn - x))
+        yn[:m1] = np.maximum(yn[:m1], 0.0)
+        x, y = xn, yn
+        xs.append(x)
+        ys.append(y)
+    return xs, ys
+
+
+def unroll_backward(Kt, lt, ut, m1, eta, omega, xs, ys, gx_T, gy_T=None):
+    """Reverse mode of unroll_forward: given dL/dx_T (and dL/dy_T, default 0), returns
+    (dL/dc~, dL/dq~).
+
+    Step t maps (x_t, y_t) to x_{t+1} = clip(u), u = x_t - tau (c~ - K~^T y_t), and
+    y_{t+1} = proj_Y(v), v = y_t + sigma (q~ - K~ (2 x_{t+1} - x_t)).  The Jacobian of the
+    clip is 1 where l < x_{t+1} < u and 0 elsewhere; that of proj_Y is 1 on the equality rows
+    and where y_{t+1} > 0.  Going backwards with adjoints (xb, yb) of (x_{t+1}, y_{t+1}):
+      vb  = mask_y * yb                      ;  qb += sigma vb
+      xb' = xb - 2 sigma K~^T vb              (x_{t+1} also enters v)
+      ub  = mask_x * xb'                     ;  cb -= tau ub
+      xb <- ub + sigma K~^T vb                (adjoint of x_t)
+      yb <- vb + tau K~ ub                    (adjoint of y_t)"""
+    Kt = sp.csr_matrix(Kt)
+    KT = Kt.T.tocsr()
+    tau, sigma = eta / omega, eta * omega
+    m = Kt.shape[0]
+    xb = np.array(gx_T, dtype=np.float64)
+    yb = np.zeros(m) if gy_T is None else np.array(gy_T, dtype=np.float64)
+    cb = np.zeros(Kt.shape[1])
+    qb = np.zeros(m)
+    T = len(xs) - 1
+    for t in range(T - 1, -1, -1):
+        x1, y1 = xs[t + 1], ys[t + 1]
+        mask_y = np.ones(m)
+        mask_y[:m1] = (y1[:m1] > 0.0).astype(np.float64)
+        vb = mask_y * yb
+        qb += sigma * vb
+        g = KT @ vb
+        mask_x = ((x1 > lt) & (x1 < ut)).astype(np.float64)
+        ub = mask_x * (xb - 2.0 * sigma * g)
+        cb -= tau * ub
+        xb = ub + sigma * g
+        yb = vb + tau * (Kt @ ub)
+    return cb, qb
+
+
+def unroll_user(K, c, q, l, u, m1, x_tgt, T, eta=None, omega=None, gy_T=None):
+    """The unrolled map in the user's variables and its gradient, for the loss
+    ||x_T - x_tgt||^2 (+ <gy_T, y_T> when gy_T is given).
+
+    D1, D2 come from K alone (Section 3.5), so they, eta and omega are constants of the map:
+    c~ = D2 c, q~ = D1 q, x_T = D2 x~_T, y_T = D1 y~_T, hence dL/dc = D2 dL/dc~,
+    dL/dq = D1 dL/dq~ and dL/dx~_T = D2 dL/dx_T.  eta defaults to 0.9 / ||K~||_2 (power
+    iteration), omega to the initial primal weight of Section 3.3 computed from the LP's own
+    c~, q~.  Returns dict(x_T, y_T, loss, gc, gq, eta, omega)."""
+    Kt, ct, qt, lt, ut, D1, D2 = precondition(K, c, q, l, u)
+    if eta is None:
+        eta = 0.9 / power_iteration_norm(Kt, 200)
+    if omega is None:
+        omega = initial_primal_weight(ct, qt, 1e-10)
+    xs, ys = unroll_forward(Kt, ct, qt, lt, ut, m1, eta, omega, T)
+    x_T = D2 * xs[-1]
+    y_T = D1 * ys[-1]
+    r = x_T - x_tgt
+    loss = float(r @ r)
+    gy_s = None
+    if gy_T is not None:
+        loss += float(np.asarray(gy_T) @ y_T)
+        gy_s = D1 * np.asarray(gy_T)
+    cb, qb = unroll_backward(Kt, lt, ut, m1, eta, omega, xs, ys, D2 * (2.0 * r), gy_s)
+    return dict(x_T=x_T, y_T=y_T, loss=loss, gc=D2 * cb, gq=D1 * qb, eta=eta, omega=omega)
+

@@ -412,3 +412,83 @@ def test_pagerank_solution_is_the_stationary_vector():
         pi = 0.85 * (S @ pi) + 0.15 / N
     assert np.abs(r.x - pi).sum() < 1e-6
     assert abs(r.kkt["pobj"]) == 0.0
+
+
+# ------------------------------------------------------------------------------------------
+# unrolled PDHG adjoint: reverse mode vs central finite differences of the forward map
+# ------------------------------------------------------------------------------------------
+
+def test_unroll_adjoint_matches_finite_differences():
+    lp = lpgen.tiny_plain(9, 60, 120, 24, 4)
+    Kt, ct, qt, lt, ut, D1, D2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
+    eta = 0.9 / O.power_iteration_norm(Kt, 200)
+    omega = O.initial_primal_weight(ct, qt, 1e-10)
+    T = 30
+    rng = np.random.default_rng(0)
+    x_tgt = rng.uniform(0, 5, lp.n)
+
+    def loss(c_t, q_t):
+        xs, _ = O.unroll_forward(Kt, c_t, q_t, lt, ut, lp.m1, eta, omega, T)
+        return float(np.sum((xs[-1] - x_tgt) ** 2))
+
+    xs, ys = O.unroll_forward(Kt, ct, qt, lt, ut, lp.m1, eta, omega, T)
+    gc, gq = O.unroll_backward(Kt, lt, ut, lp.m1, eta, omega, xs, ys, 2.0 * (xs[-1] - x_tgt))
+    h = 1e-6
+    for j in rng.choice(lp.n, 12, replace=False):
+        e = np.zeros(lp.n)
+        e[j] = h
+        fd = (loss(ct + e, qt) - loss(ct - e, qt)) / (2 * h)
+        assert abs(fd - gc[j]) <= 1e-6 * (1 + abs(fd)), (j, fd, gc[j])
+    for i in rng.choice(lp.m, 12, replace=False):
+        e = np.zeros(lp.m)
+        e[i] = h
+        fd = (loss(ct, qt + e) - loss(ct, qt - e)) / (2 * h)
+        assert abs(fd - gq[i]) <= 1e-6 * (1 + abs(fd)), (i, fd, gq[i])
+
+
+def test_unroll_one_step_closed_form():
+    # T = 1 from x0 = proj(0), y0 = 0: x1 = clip(x0 - tau c~), so with x~ the only path,
+    # dL/dc~ = -tau * mask * dL/dx~_1 and dL/dq~ = 0 for a loss on x_1 alone.
+    lp = lpgen.tiny_plain(5, 30, 70, 12, 4)
+    Kt, ct, qt, lt, ut, D1, D2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
+    eta, omega = 0.3, 1.7
+    xs, ys = O.unroll_forward(Kt, ct, qt, lt, ut, lp.m1, eta, omega, 1)
+    x0 = np.clip(np.zeros(lp.n), lt, ut)
+    assert np.array_equal(xs[1], np.clip(x0 - (eta / omega) * ct, lt, ut))
+    g = np.random.default_rng(1).standard_normal(lp.n)
+    gc, gq = O.unroll_backward(Kt, lt, ut, lp.m1, eta, omega, xs, ys, g)
+    inside = (xs[1] > lt) & (xs[1] < ut)
+    assert np.allclose(gc, -(eta / omega) * inside * g, rtol=0, atol=1e-15)
+    assert np.all(gq == 0.0)
+
+
+def test_unroll_user_units_gradient_matches_finite_differences():
+    # the full map (c, q) -> ||x_T - x_tgt||^2 + <gy, y_T> in the user's units, on an LP with
+    # free, one-sided and boxed columns; D1, D2 depend on K only, eta and omega are held fixed.
+    lp = lpgen.tiny_plain(11, 40, 90, 16, 4)
+    rng = np.random.default_rng(2)
+    l = lp.l.copy()
+    u = lp.u.copy()
+    l[:20] = -np.inf
+    u[:20] = np.inf                 # free
+    u[20:40] = np.inf               # [0, inf)
+    x_tgt = rng.uniform(0, 5, lp.n)
+    gy = rng.standard_normal(lp.m)
+    K = lp.K()
+    base = O.unroll_user(K, lp.c, lp.q, l, u, lp.m1, x_tgt, 25, gy_T=gy)
+    eta, omega = base["eta"], base["omega"]
+
+    def loss(c, q):
+        return O.unroll_user(K, c, q, l, u, lp.m1, x_tgt, 25, eta, omega, gy_T=gy)["loss"]
+
+    h = 1e-6
+    for j in rng.choice(lp.n, 10, replace=False):
+        e = np.zeros(lp.n)
+        e[j] = h
+        fd = (loss(lp.c + e, lp.q) - loss(lp.c - e, lp.q)) / (2 * h)
+        assert abs(fd - base["gc"][j]) <= 1e-6 * (1 + abs(fd)), (j, fd, base["gc"][j])
+    for i in rng.choice(lp.m, 10, replace=False):
+        e = np.zeros(lp.m)
+        e[i] = h
+        fd = (loss(lp.c, lp.q + e) - loss(lp.c, lp.q - e)) / (2 * h)
+        assert abs(fd - base["gq"][i]) <= 1e-6 * (1 + abs(fd)), (i, fd, base["gq"][i])
