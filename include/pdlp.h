@@ -227,6 +227,61 @@ double pdlp_batch_solve_seconds(const pdlp_batch *b);
 void pdlp_batch_destroy(pdlp_batch *b);
 const char *pdlp_batch_last_error(const pdlp_batch *b);
 
+/* ---- unrolled PDHG and its adjoint (differentiating through a fixed number of steps) ------- */
+
+/* Scalars of the last unrolled forward / backward pass (pdlp_unroll_get_info). */
+typedef struct pdlp_unroll_info {
+  int64_t steps;                 /* T of the last pdlp_unroll_forward                          */
+  int64_t segment;               /* steps per checkpoint segment                               */
+  int64_t checkpoints;           /* ceil(T / segment) stored iterates                          */
+  int64_t recomputed_steps;      /* forward steps the last backward pass recomputed            */
+  double eta;                    /* frozen step size used (preconditioned problem)             */
+  double omega;                  /* frozen primal weight used                                  */
+  double forward_seconds;        /* host wall time of the last forward / backward call         */
+  double backward_seconds;
+  double device_bytes;           /* device memory held by the unroll buffers                   */
+  int32_t ready;                 /* 1 if a forward pass can be differentiated                  */
+  int32_t pad;
+} pdlp_unroll_info;
+
+/*
+ * pdlp_unroll_forward - T = steps iterations of Eq. (3) on the solver's preconditioned LP with
+ * new objective c and right-hand side q, a fixed step eta and primal weight omega
+ * (tau = eta / omega, sigma = eta * omega) and the solver's frozen D1, D2: no restarts, no
+ * step-size rule, no rejections.  Starts at x0 = proj_[l,u](0), y0 = 0 (Section 4.1's start).
+ * This is the map that a network with an LP "optimization layer" differentiates, the use of
+ * GPU PDLP that the introduction (Section 1) mentions; the paper itself gives no derivative.
+ *   c, q      n and m values in the user's units (c~ = D2 c, q~ = D1 q); NULL = the LP's own.
+ *   steps     T >= 0.
+ *   segment   steps between stored checkpoints of (x, y, K~ x): 0 = one segment (no
+ *             recomputation in the backward pass, most memory), else at most ceil(T/segment)
+ *             checkpoints of n + 2m values plus segment * (n + m) bytes of projection masks.
+ *   eta       <= 0: 0.9 / ||K~||_2 from power iteration (the baseline step of Section 2).
+ *   omega     <= 0: the initial primal weight of Section 3.3 from the LP's own c~, q~.
+ *   x_T, y_T  outputs (n, m values, user's units x = D2 x~, y = D1 y~); NULL skips.
+ * The solver keeps what pdlp_unroll_backward needs until the next forward call.  The unroll
+ * uses its own buffers: it neither reads nor changes the state of pdlp_solve.
+ * Errors: PDLP_ERR_INVALID_ARGUMENT (negative steps or segment, non-finite eta or omega),
+ * PDLP_ERR_OUT_OF_MEMORY, PDLP_ERR_DEVICE.
+ */
+int pdlp_unroll_forward(pdlp_solver *s, const double *c, const double *q, int64_t steps,
+                        int64_t segment, double eta, double omega, double *x_T, double *y_T);
+
+/*
+ * pdlp_unroll_backward - reverse mode of the last pdlp_unroll_forward: given gx_T = dL/dx_T
+ * (n values) and gy_T = dL/dy_T (m values; either may be NULL = 0), writes gc = dL/dc (n) and
+ * gq = dL/dq (m) in the user's units.  eta, omega, D1, D2, l and u are held constant.  Where a
+ * projection is active the derivative of the clamp is taken as 0 (strictly inside the bounds,
+ * and y > 0 on ">=" rows, it is 1).  Segments other than the last are recomputed from their
+ * checkpoints; the result is identical to storing every step.  May be called several times.
+ * Errors: PDLP_ERR_INVALID_STATE without a forward pass; as pdlp_unroll_forward otherwise.
+ */
+int pdlp_unroll_backward(pdlp_solver *s, const double *gx_T, const double *gy_T, double *gc,
+                         double *gq);
+
+/* pdlp_unroll_get_info - see pdlp_unroll_info. */
+int pdlp_unroll_get_info(const pdlp_solver *s, pdlp_unroll_info *info);
+
 /* ---- inspection entry points (parity tests and measurement) ---------------------------- */
 
 /*

@@ -21,6 +21,7 @@
 #include "pdlp_internal.h"
 #include "pdlp_kernels.hip"
 #include "pdlp_batch.hip"
+#include "pdlp_unroll.hip"
 
 using namespace pdlp;
 
@@ -81,10 +82,35 @@ struct pdlp_solver {
   double create_seconds = 0.0, solve_seconds = 0.0;
   int last_status = PDLP_NOT_SOLVED;
   double bytes_A = 0.0, bytes_B = 0.0;
+  double omega0 = 0.0;                 // initial primal weight (frozen omega of the unroll)
+  double eta_pow = 0.0;                // 0.9 / ||K~||_2 once computed (frozen eta of the unroll)
+
+  // Unrolled PDHG: buffers sized for the last forward call, the checkpoints of its segments
+  // and the projection masks of one segment.
+  struct Unroll {
+    std::vector<void*> allocs;
+    int64_t T = 0, S = 1, nseg = 0, cap_seg = -1, cap_S = -1;
+    double eta = 0.0, omega = 0.0;
+    double* ct = nullptr;      // c~, q~ of the forward call
+    double* qt = nullptr;
+    double* gin = nullptr;     // staging of the caller's c, q (forward) or gx, gy (backward)
+    double* z = nullptr;       // x (n) | y (m) | K~ x (m) of the running step
+    double* ck = nullptr;      // nseg checkpoints with the layout of z
+    double* xb = nullptr;      // adjoints
+    double* ub = nullptr;
+    double* vb = nullptr;
+    double* cb = nullptr;      // cb (n) | qb (m), contiguous
+    double* out = nullptr;     // n + m outputs in the user's units
+    uint8_t* mask = nullptr;   // S steps x (n + m) bytes
+    bool ready = false, masks_last = false;
+    double fwd_s = 0.0, bwd_s = 0.0, bytes = 0.0;
+    int64_t recomputed = 0;
+  } U;
 
   ~pdlp_solver() {
     if (stream) (void)hipStreamSynchronize(stream);
     for (void* p : allocs) (void)hipFree(p);
+    for (void* p : U.allocs) (void)hipFree(p);
     if (h_st) (void)hipHostFree(h_st);
     for (int b = 0; b < 2; ++b) {
       if (blk_ev[b]) (void)hipEventDestroy(blk_ev[b]);
@@ -260,6 +286,27 @@ int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double
                                                        out_par, pred, count_as,
                                                        s->tickets + kTkSpmv);
   PDLP_LAUNCH(s);
+  return 0;
+}
+
+// Power iteration on K~^T K~ from the all-ones vector (v, w: n values, t: m values); leaves
+// ||K~^T K~ v||^2 of the last round in the device state, so ||K~||_2 ~ its fourth root.
+int power_iterate(pdlp_solver* s, double* v, double* t, double* w) {
+  int rc;
+  const int64_t n = s->n;
+  {
+    std::vector<double> ones(static_cast<size_t>(n), 1.0 / std::sqrt(double(n)));
+    PDLP_HIP(s, hipMemcpy(v, ones.data(), size_t(n) * 8, hipMemcpyHostToDevice));
+  }
+  const int gn = grid_rows(n, s->maxG);
+  for (int it = 0; it < s->opts.power_iters; ++it) {
+    if ((rc = launch_spmv(s, s->K, v, nullptr, 0, t, nullptr, 0, kPredAlways, 0))) return rc;
+    if ((rc = launch_spmv(s, s->KT, t, nullptr, 0, w, nullptr, 0, kPredAlways, 0))) return rc;
+    k_pow_norm<<<gn, kBlock, 0, s->stream>>>(s->st, w, int(n), s->partX, s->tickets + kTkInit);
+    PDLP_LAUNCH(s);
+    k_pow_scale<<<gn, kBlock, 0, s->stream>>>(s->st, w, v, int(n));
+    PDLP_LAUNCH(s);
+  }
   return 0;
 }
 
@@ -571,31 +618,229 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   PDLP_LAUNCH(s);
   if ((rc = launch_spmv(s, s->K, B.X[0], nullptr, 0, B.KX[0], nullptr, 0, kPredAlways, 0))) return rc;
   if (s->opts.step_policy == 1) {
-    // baseline PDHG step 0.9 / ||K~||_2: power iteration on K~^T K~ from the all-ones vector,
-    // using the gap scratch buffers (free until the first check)
-    double* v = B.GA[0];
-    double* t = B.GB[0];
-    double* w = B.GA[1];
-    {
-      std::vector<double> ones(N, 1.0 / std::sqrt(double(n)));
-      PDLP_HIP(s, hipMemcpy(v, ones.data(), N * 8, hipMemcpyHostToDevice));
-    }
-    const int gn = grid_rows(n, s->maxG);
-    for (int it = 0; it < s->opts.power_iters; ++it) {
-      if ((rc = launch_spmv(s, s->K, v, nullptr, 0, t, nullptr, 0, kPredAlways, 0))) return rc;
-      if ((rc = launch_spmv(s, s->KT, t, nullptr, 0, w, nullptr, 0, kPredAlways, 0))) return rc;
-      k_pow_norm<<<gn, kBlock, 0, s->stream>>>(s->st, w, int(n), s->partX, s->tickets + kTkInit);
-      PDLP_LAUNCH(s);
-      k_pow_scale<<<gn, kBlock, 0, s->stream>>>(s->st, w, v, int(n));
-      PDLP_LAUNCH(s);
-    }
+    // baseline PDHG step 0.9 / ||K~||_2, using the gap scratch buffers (free until the first check)
+    if ((rc = power_iterate(s, B.GA[0], B.GB[0], B.GA[1]))) return rc;
     k_pow_set_step<<<1, 1, 0, s->stream>>>(s->st);
     PDLP_LAUNCH(s);
   }
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
+  PDLP_HIP(s, hipMemcpy(&s->omega0, &s->st->omega, sizeof(double), hipMemcpyDeviceToHost));
+  if (s->opts.step_policy == 1) PDLP_HIP(s, hipMemcpy(&s->eta_pow, &s->st->eta, sizeof(double), hipMemcpyDeviceToHost));
 
   s->bytes_A = 8.0 * double(n + 1) + 12.0 * double(nnz) + 8.0 * double(m) + 64.0 * double(n);
   s->bytes_B = 8.0 * double(m + 1) + 12.0 * double(nnz) + 8.0 * double(n) + 56.0 * double(m);
+  return 0;
+}
+
+// ------------------------------------------------------------------------------------------
+// unrolled PDHG with frozen eta, omega, D1, D2 and its adjoint
+// ------------------------------------------------------------------------------------------
+
+template <class T>
+int unroll_alloc(pdlp_solver* s, T** p, size_t count) {
+  const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), bytes);
+  if (e != hipSuccess) {
+    s->err = std::string("hipMalloc (unroll buffers): ") + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? PDLP_ERR_OUT_OF_MEMORY : PDLP_ERR_DEVICE;
+  }
+  s->U.allocs.push_back(*p);
+  s->U.bytes += double(bytes);
+  return 0;
+}
+
+// Buffers for nseg checkpoints and segments of S steps; kept while large enough.
+int unroll_reserve(pdlp_solver* s, int64_t nseg, int64_t S) {
+  auto& U = s->U;
+  const size_t N = size_t(s->n), M = size_t(s->m);
+  int rc;
+  if (U.cap_seg < 0) {
+    if ((rc = unroll_alloc(s, &U.ct, N)) || (rc = unroll_alloc(s, &U.qt, M)) ||
+        (rc = unroll_alloc(s, &U.gin, N + M)) || (rc = unroll_alloc(s, &U.z, N + 2 * M)) ||
+        (rc = unroll_alloc(s, &U.xb, N)) || (rc = unroll_alloc(s, &U.ub, N)) ||
+        (rc = unroll_alloc(s, &U.vb, M)) || (rc = unroll_alloc(s, &U.cb, N + M)) ||
+        (rc = unroll_alloc(s, &U.out, N + M)))
+      return rc;
+    U.cap_seg = 0;
+    U.cap_S = 0;
+  }
+  if (nseg > U.cap_seg) {
+    if (U.ck) {
+      PDLP_HIP(s, hipStreamSynchronize(s->stream));
+      PDLP_HIP(s, hipFree(U.ck));
+      U.allocs.erase(std::find(U.allocs.begin(), U.allocs.end(), static_cast<void*>(U.ck)));
+      U.bytes -= double(std::max<int64_t>(U.cap_seg, 1)) * double(N + 2 * M) * 8.0;
+      U.ck = nullptr;
+    }
+    if ((rc = unroll_alloc(s, &U.ck, size_t(nseg) * (N + 2 * M)))) return rc;
+    U.cap_seg = nseg;
+  }
+  if (S > U.cap_S) {
+    if (U.mask) {
+      PDLP_HIP(s, hipStreamSynchronize(s->stream));
+      PDLP_HIP(s, hipFree(U.mask));
+      U.allocs.erase(std::find(U.allocs.begin(), U.allocs.end(), static_cast<void*>(U.mask)));
+      U.bytes -= double(std::max<int64_t>(U.cap_S, 1)) * double(N + M);
+      U.mask = nullptr;
+    }
+    if ((rc = unroll_alloc(s, &U.mask, size_t(S) * (N + M)))) return rc;
+    U.cap_S = S;
+  }
+  return 0;
+}
+
+// One fused CSR pass: out rows of A from the product with `in`, then epi.row per row.
+template <class Epi>
+int launch_fused(pdlp_solver* s, const CsrDev& A, const double* in, const Epi& epi) {
+  if (A.npanel > 1) {
+    double* part = (&A == &s->K) ? s->partPK : s->partPT;
+    k_panel_rows<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in, nullptr, 0, part,
+                                                               kPredAlways, kProd);
+    PDLP_LAUNCH(s);
+    k_unroll_combine<Epi><<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(A, part, epi);
+    PDLP_LAUNCH(s);
+    return 0;
+  }
+  k_unroll_rows<Epi><<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, in, epi);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
+int unroll_copy(pdlp_solver* s, const double* src, double* dst, int64_t len) {
+  const int g = int(std::max<int64_t>(1, std::min<int64_t>((len + kBlock - 1) / kBlock, s->maxG)));
+  k_unroll_copy<<<g, kBlock, 0, s->stream>>>(src, dst, len);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
+// Forward step t -> t + 1 on U.z, recording the projection masks into `slot` (n + m bytes).
+int unroll_fwd_step(pdlp_solver* s, uint8_t* slot) {
+  auto& U = s->U;
+  int rc;
+  double* x = U.z;
+  double* y = U.z + s->n;
+  double* kx = U.z + s->n + s->m;
+  const UFwdPrimal ep{U.ct, s->B.l, s->B.u, x, slot, U.eta / U.omega};
+  if ((rc = launch_fused(s, s->KT, y, ep))) return rc;
+  const UFwdDual ed{U.qt, y, kx, slot + s->n, U.eta * U.omega, s->B.m1};
+  return launch_fused(s, s->K, x, ed);
+}
+
+// Stage a caller's vector (host or device, len values) in device memory.
+int stage_in(pdlp_solver* s, const double* src, double* dst, int64_t len) {
+  if (len == 0) return 0;
+  const hipMemcpyKind kind = is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  PDLP_HIP(s, hipMemcpyAsync(dst, src, size_t(len) * 8, kind, s->stream));
+  return 0;
+}
+
+int unroll_forward_impl(pdlp_solver* s, const double* c, const double* q, int64_t T, int64_t segment,
+                        double eta, double omega, double* x_T, double* y_T) {
+  auto& U = s->U;
+  int rc;
+  if (T < 0 || segment < 0 || !(std::isfinite(eta) && std::isfinite(omega))) {
+    s->err = "unroll: need steps >= 0, segment >= 0 and finite eta, omega";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  const int64_t n = s->n, m = s->m;
+  const int64_t S = std::max<int64_t>(1, segment == 0 ? T : std::min(segment, std::max<int64_t>(T, 1)));
+  const int64_t nseg = (T + S - 1) / S;
+  const double t0 = now_s();
+  U.ready = false;
+  if ((rc = unroll_reserve(s, std::max<int64_t>(nseg, 1), S))) return rc;
+  if (eta <= 0.0) {
+    if (s->eta_pow <= 0.0) {
+      if ((rc = power_iterate(s, U.xb, U.vb, U.ub))) return rc;
+      double pn2 = 0.0;
+      PDLP_HIP(s, hipMemcpyAsync(&pn2, &s->st->pow_norm2, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+      PDLP_HIP(s, hipStreamSynchronize(s->stream));
+      const double sig = std::sqrt(std::sqrt(pn2));
+      s->eta_pow = sig > 0.0 ? 0.9 / sig : 1.0;
+    }
+    eta = s->eta_pow;
+  }
+  if (omega <= 0.0) omega = s->omega0;
+  U.eta = eta;
+  U.omega = omega;
+  U.T = T;
+  U.S = S;
+  U.nseg = nseg;
+  // c~ = D2 c, q~ = D1 q (the LP's own c, q when null), z0 = (proj_X(0), 0, K~ proj_X(0))
+  if ((rc = stage_in(s, c ? c : s->B.c0, U.gin, n))) return rc;
+  if ((rc = stage_in(s, q ? q : s->B.q0, U.gin + n, m))) return rc;
+  const int gE = s->gE;
+  k_unroll_start<<<gE, kBlock, 0, s->stream>>>(U.gin, U.gin + n, s->B.D1, s->B.D2, s->B.l, s->B.u, U.ct,
+                                               U.qt, U.z, U.z + n, int(n), int(m));
+  PDLP_LAUNCH(s);
+  if ((rc = launch_spmv(s, s->K, U.z, nullptr, 0, U.z + n + m, nullptr, 0, kPredAlways, 0))) return rc;
+  const int64_t zlen = n + 2 * m;
+  for (int64_t t = 0; t < T; ++t) {
+    if (t % S == 0 && (rc = unroll_copy(s, U.z, U.ck + (t / S) * zlen, zlen))) return rc;
+    if ((rc = unroll_fwd_step(s, U.mask + (t % S) * (n + m)))) return rc;
+  }
+  k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.z, s->B.D2, int(n), U.z + n, s->B.D1, int(m), U.out);
+  PDLP_LAUNCH(s);
+  if ((rc = write_output(s, x_T, U.out, size_t(n) * 8))) return rc;
+  if ((rc = write_output(s, y_T, U.out + n, size_t(m) * 8))) return rc;
+  PDLP_HIP(s, hipStreamSynchronize(s->stream));
+  U.ready = true;
+  U.masks_last = true;
+  U.fwd_s = now_s() - t0;
+  return 0;
+}
+
+int unroll_backward_impl(pdlp_solver* s, const double* gx, const double* gy, double* gc, double* gq) {
+  auto& U = s->U;
+  int rc;
+  if (!U.ready) {
+    s->err = "unroll backward: no forward pass to differentiate";
+    return PDLP_ERR_INVALID_STATE;
+  }
+  const int64_t n = s->n, m = s->m, nm = n + m, zlen = n + 2 * m;
+  const double t0 = now_s();
+  const double tau = U.eta / U.omega, sigma = U.eta * U.omega;
+  const int gE = s->gE;
+  if (gx && (rc = stage_in(s, gx, U.gin, n))) return rc;
+  if (gy && (rc = stage_in(s, gy, U.gin + n, m))) return rc;
+  U.recomputed = 0;
+  if (U.nseg == 0) {
+    // x_0 = proj_X(0) does not depend on (c, q)
+    k_unroll_seed<<<gE, kBlock, 0, s->stream>>>(nullptr, nullptr, s->B.D1, s->B.D2, U.mask, U.xb, U.vb,
+                                                U.cb, U.cb + n, int(n), int(m), s->B.m1);
+    PDLP_LAUNCH(s);
+  }
+  for (int64_t seg = U.nseg - 1; seg >= 0; --seg) {
+    const int64_t ta = seg * U.S, tb = std::min(U.T, ta + U.S);
+    const bool last = seg == U.nseg - 1;
+    if (!(last && U.masks_last)) {
+      if ((rc = unroll_copy(s, U.ck + seg * zlen, U.z, zlen))) return rc;
+      for (int64_t t = ta; t < tb; ++t)
+        if ((rc = unroll_fwd_step(s, U.mask + (t - ta) * nm))) return rc;
+      U.recomputed += tb - ta;
+    }
+    if (last) {
+      k_unroll_seed<<<gE, kBlock, 0, s->stream>>>(gx ? U.gin : nullptr, gy ? U.gin + n : nullptr, s->B.D1,
+                                                  s->B.D2, U.mask + (tb - 1 - ta) * nm + n, U.xb, U.vb, U.cb,
+                                                  U.cb + n, int(n), int(m), s->B.m1);
+      PDLP_LAUNCH(s);
+    }
+    for (int64_t t = tb - 1; t >= ta; --t) {
+      const uint8_t* slot = U.mask + (t - ta) * nm;
+      const UBwdPrimal ep{slot, U.xb, U.ub, U.cb, tau, sigma};
+      if ((rc = launch_fused(s, s->KT, U.vb, ep))) return rc;
+      const uint8_t* my_prev = (t > ta) ? slot - nm + n : nullptr;
+      const double* y_prev = (t == ta && t > 0) ? U.ck + seg * zlen + n : nullptr;
+      const UBwdDual ed{U.vb, U.cb + n, my_prev, y_prev, tau, sigma, s->B.m1};
+      if ((rc = launch_fused(s, s->K, U.ub, ed))) return rc;
+    }
+  }
+  U.masks_last = U.nseg == 1;
+  k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.cb, s->B.D2, int(n), U.cb + n, s->B.D1, int(m), U.out);
+  PDLP_LAUNCH(s);
+  if ((rc = write_output(s, gc, U.out, size_t(n) * 8))) return rc;
+  if ((rc = write_output(s, gq, U.out + n, size_t(m) * 8))) return rc;
+  PDLP_HIP(s, hipStreamSynchronize(s->stream));
+  U.bwd_s = now_s() - t0;
   return 0;
 }
 
@@ -931,6 +1176,51 @@ int pdlp_reset_kernel_times(pdlp_solver* s) {
   if (!s) return PDLP_ERR_INVALID_ARGUMENT;
   s->t_ms[0] = s->t_ms[1] = 0.0;
   s->t_cnt[0] = s->t_cnt[1] = 0;
+  return 0;
+}
+
+int pdlp_unroll_forward(pdlp_solver* s, const double* c, const double* q, int64_t steps,
+                        int64_t segment, double eta, double omega, double* x_T, double* y_T) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  try {
+    return unroll_forward_impl(s, c, q, steps, segment, eta, omega, x_T, y_T);
+  } catch (const std::bad_alloc&) {
+    s->err = "host out of memory";
+    return PDLP_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    s->err = "unexpected host exception";
+    return PDLP_ERR_DEVICE;
+  }
+}
+
+int pdlp_unroll_backward(pdlp_solver* s, const double* gx_T, const double* gy_T, double* gc,
+                         double* gq) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  try {
+    return unroll_backward_impl(s, gx_T, gy_T, gc, gq);
+  } catch (const std::bad_alloc&) {
+    s->err = "host out of memory";
+    return PDLP_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    s->err = "unexpected host exception";
+    return PDLP_ERR_DEVICE;
+  }
+}
+
+int pdlp_unroll_get_info(const pdlp_solver* s, pdlp_unroll_info* info) {
+  if (!s || !info) return PDLP_ERR_INVALID_ARGUMENT;
+  const auto& U = s->U;
+  info->steps = U.T;
+  info->segment = U.S;
+  info->checkpoints = U.nseg;
+  info->recomputed_steps = U.recomputed;
+  info->eta = U.eta;
+  info->omega = U.omega;
+  info->forward_seconds = U.fwd_s;
+  info->backward_seconds = U.bwd_s;
+  info->device_bytes = U.bytes;
+  info->ready = U.ready ? 1 : 0;
+  info->pad = 0;
   return 0;
 }
 

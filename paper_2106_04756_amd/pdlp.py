@@ -25,7 +25,8 @@ EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pd
             "pdlp_get_scaling", "pdlp_get_iterate",
             "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
             "pdlp_build_schedule", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
-            "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error"]
+            "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error",
+            "pdlp_unroll_forward", "pdlp_unroll_backward", "pdlp_unroll_get_info"]
 
 
 class Options(ctypes.Structure):
@@ -68,6 +69,14 @@ class CheckRec(ctypes.Structure):
                 ("kkt", ctypes.c_double), ("omega_after", ctypes.c_double),
                 ("mu_anchor", ctypes.c_double), ("use_avg", ctypes.c_int32),
                 ("mask", ctypes.c_int32), ("terminated", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class UnrollInfo(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int64), ("segment", ctypes.c_int64),
+                ("checkpoints", ctypes.c_int64), ("recomputed_steps", ctypes.c_int64),
+                ("eta", ctypes.c_double), ("omega", ctypes.c_double),
+                ("forward_seconds", ctypes.c_double), ("backward_seconds", ctypes.c_double),
+                ("device_bytes", ctypes.c_double), ("ready", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 _lib = None
@@ -134,6 +143,12 @@ def lib() -> ctypes.CDLL:
         L.pdlp_batch_destroy.restype = None
         L.pdlp_batch_last_error.argtypes = [P]
         L.pdlp_batch_last_error.restype = ctypes.c_char_p
+        L.pdlp_unroll_forward.argtypes = [P, P, P, I64, I64, ctypes.c_double, ctypes.c_double, P, P]
+        L.pdlp_unroll_forward.restype = ctypes.c_int
+        L.pdlp_unroll_backward.argtypes = [P, P, P, P, P]
+        L.pdlp_unroll_backward.restype = ctypes.c_int
+        L.pdlp_unroll_get_info.argtypes = [P, ctypes.POINTER(UnrollInfo)]
+        L.pdlp_unroll_get_info.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -320,6 +335,41 @@ class Solver:
         px, kx = _ptr(x, np.float64)
         po, ko = _ptr(out, np.float64)
         self._check(lib().pdlp_spmv(self._h, 1 if transpose else 0, px, po))
+
+    # ---- unrolled PDHG (frozen eta, omega, D1, D2) and its adjoint ----
+
+    def unroll_forward(self, c=None, q=None, steps=500, segment=50, eta=0.0, omega=0.0,
+                       x_out=None, y_out=None):
+        """x_T, y_T after `steps` fixed PDHG steps with objective c and right-hand side q (user
+        units; None = the LP's own).  Outputs go to x_out / y_out (NumPy or torch, host or
+        device) when given, else to new NumPy arrays, which are returned."""
+        pc, kc = _ptr(c, np.float64)
+        pq, kq = _ptr(q, np.float64)
+        xo = np.empty(self.n) if x_out is None else x_out
+        yo = np.empty(self.m) if y_out is None else y_out
+        px, kx = _ptr(xo, np.float64)
+        py, ky = _ptr(yo, np.float64)
+        self._check(lib().pdlp_unroll_forward(self._h, pc, pq, int(steps), int(segment), float(eta),
+                                              float(omega), px, py if self.m else None))
+        self.unroll_id = getattr(self, "unroll_id", 0) + 1
+        return xo, yo
+
+    def unroll_backward(self, gx=None, gy=None, gc_out=None, gq_out=None):
+        """(dL/dc, dL/dq) of the last unroll_forward given dL/dx_T, dL/dy_T (None = 0)."""
+        pgx, kgx = _ptr(gx, np.float64)
+        pgy, kgy = _ptr(gy, np.float64)
+        gc = np.empty(self.n) if gc_out is None else gc_out
+        gq = np.empty(self.m) if gq_out is None else gq_out
+        pc, kc = _ptr(gc, np.float64)
+        pq, kq = _ptr(gq, np.float64)
+        self._check(lib().pdlp_unroll_backward(self._h, pgx, pgy if self.m else None, pc,
+                                               pq if self.m else None))
+        return gc, gq
+
+    def unroll_info(self) -> dict:
+        u = UnrollInfo()
+        self._check(lib().pdlp_unroll_get_info(self._h, ctypes.byref(u)))
+        return {k: getattr(u, k) for k, _ in UnrollInfo._fields_ if k != "pad"}
 
     def kernel_times(self):
         t = np.zeros(2)
