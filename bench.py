@@ -1,7 +1,8 @@
 """PDHG throughput of the gfx950 PDLP solver on the large plain LP (m=1e6, n=2e6, Zipf(1.5)
 column counts, nnz ~1.35e8), one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--calibrate-copy]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
+                    [--no-unroll] [--calibrate-copy]
 
 A step is one accepted PDHG iteration of Algorithm 1 on the whole LP: the K~^T product fused
 with the primal step, the K~ product fused with the dual step and the step-size rule, and
@@ -88,6 +89,46 @@ def bench_batched(P, lpgen, count, iter_limit, plain_sample=16):
             "speedup_vs_plain": (conv / secs) / (pconv / pdt) if pconv else None}
 
 
+def bench_unroll(P, lpgen, T=500, segment=50, reps=5):
+    """Unrolled PDHG on the unroll LP (m=2e4, n=5e4, 6 nonzeros per column): wall time of the
+    forward pass (T fixed steps) and of the adjoint (with checkpoint recomputation), median of
+    reps, and the same with every step's masks kept (segment 0: no recomputation); the
+    oracle's NumPy forward + reverse pass timed once beside it (1 thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    lp, x_tgt = lpgen.config4()
+    s = P.Solver.from_lp(lp)
+    res = {}
+    for seg in (segment, 0):
+        f, b = [], []
+        for r in range(reps + 1):
+            x, _ = s.unroll_forward(lp.c, lp.q, T, seg)
+            s.unroll_backward(2.0 * (x - x_tgt))
+            inf = s.unroll_info()
+            if r:
+                f.append(inf["forward_seconds"])
+                b.append(inf["backward_seconds"])
+        fm, bm = float(np.median(f)), float(np.median(b))
+        res[seg] = dict(forward_ms=fm * 1e3, backward_ms=bm * 1e3, forward_steps_per_s=T / fm,
+                        fwd_plus_adjoint_over_fwd=(fm + bm) / fm,
+                        recomputed_steps=inf["recomputed_steps"], device_bytes=inf["device_bytes"])
+    eta, omega = inf["eta"], inf["omega"]
+    s.close()
+    from oracle import pdlp_oracle as O
+    Kt, ct, qt, lt, ut, D1, D2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        xs, ys = O.unroll_forward(Kt, ct, qt, lt, ut, lp.m1, eta, omega, T)
+        t1 = time.perf_counter()
+        O.unroll_backward(Kt, lt, ut, lp.m1, eta, omega, xs, ys, D2 * 2.0 * (D2 * xs[-1] - x_tgt))
+        t2 = time.perf_counter()
+    log(f"unroll T={T}: forward {res[segment]['forward_ms']:.2f} ms, adjoint {res[segment]['backward_ms']:.2f} ms "
+        f"(segment {segment}); oracle {1e3 * (t1 - t0):.0f} + {1e3 * (t2 - t1):.0f} ms")
+    return {"workload": f"{lp.name}, T={T}", "segment": segment, "checkpointed": res[segment],
+            "all_masks_kept": res[0], "oracle_forward_ms": 1e3 * (t1 - t0),
+            "oracle_adjoint_ms": 1e3 * (t2 - t1), "oracle_cores": 1}
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -109,6 +150,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-unroll", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-iter-limit", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -139,7 +181,8 @@ def main():
     st = s.solve(1e-8, W)
     log(f"warmup {W} steps: status {P.STATUS_NAMES[st]}")
     s.reset_kernel_times()
-    k0 = s.info()["iterations"]
+    i0 = s.info()
+    k0 = i0["iterations"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     st = s.solve(1e-8, W + K)
@@ -151,15 +194,30 @@ def main():
     log(f"timed {steps} steps in {dt:.3f}s: status {P.STATUS_NAMES[st]}, attempts {info['attempts']}, "
         f"restarts {info['restarts']}, kkt {info['kkt'][3]:.3e}")
 
+    # Algorithmic bytes of the timed step kernels.  The primal step skips its K~^T y product
+    # when y is unchanged since that product was last formed (after a rejected attempt, and
+    # after a check, which forms it), and a slot whose attempt does not run (a check pending)
+    # does nothing; so count the products from the solver's counters: each check forms two
+    # K~^T products (of the average and of the current y) and one K~ product.
     times, counts = s.kernel_times()
     m, n, nnz = lp.m, lp.n, lp.nnz
-    bytes_primal = 8.0 * (n + 1) + 12.0 * nnz + 8.0 * m + 64.0 * n
-    bytes_dual = 8.0 * (m + 1) + 12.0 * nnz + 8.0 * n + 56.0 * m
-    avg = [times[i] / counts[i] if counts[i] else float("nan") for i in range(2)]
-    dom = 0 if avg[0] >= avg[1] else 1
-    name = ["k_primal (K~^T product + primal step)", "k_dual (K~ product + dual step + step rule)"][dom]
-    bpl = [bytes_primal, bytes_dual][dom]
-    achieved = bpl / (avg[dom] * 1e-3) / 1e9
+    d_att = info["attempts"] - i0["attempts"]
+    d_chk = info["checks"] - i0["checks"]
+    prim_products = (info["spmv_KT"] - i0["spmv_KT"]) - 2 * d_chk
+    dual_products = (info["spmv_K"] - i0["spmv_K"]) - d_chk
+    bytes_primal = 8.0 * (n + 1) + 12.0 * nnz + 8.0 * m + 64.0 * n     # K~^T y, then 8 n-vectors
+    bytes_primal_epi = 64.0 * n                                         # the same without the product
+    bytes_dual = 8.0 * (m + 1) + 12.0 * nnz + 8.0 * n + 56.0 * m        # K~ x', then 7 m-vectors
+    total_bytes = [prim_products * bytes_primal + (d_att - prim_products) * bytes_primal_epi,
+                   dual_products * bytes_dual]
+    dom = 0 if times[0] >= times[1] else 1
+    name = ["primal step: K~^T y product fused with the primal update (k_panel_rows<1> + k_primal_combine "
+            "in XCD-panel mode, else k_primal)",
+            "dual step: K~ x' product fused with the dual update and the step rule (k_panel_rows<0> + "
+            "k_dual_combine in XCD-panel mode, else k_dual)"][dom]
+    avg_ms = times[dom] / counts[dom]
+    bpl = total_bytes[dom] / counts[dom]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
     step_gbs = info["step_bytes"] * steps / dt / 1e9
     out = {
         "metric": "PDHG iters/s",
@@ -179,10 +237,11 @@ def main():
                    "tol": 1e-8, "steps_taken": steps},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "avg_launch_ms": avg[dom], "launches": int(counts[dom]),
+                     "avg_launch_ms": avg_ms, "launches": int(counts[dom]),
+                     "products": int([prim_products, dual_products][dom]), "attempts": int(d_att),
                      "algorithmic_bytes_per_launch": bpl},
         "step_gbs_algorithmic": step_gbs,
-        "kernel_avg_ms": {"k_primal": avg[0], "k_dual": avg[1]},
+        "step_avg_ms": {"primal": times[0] / counts[0], "dual": times[1] / counts[1]},
     }
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
     tiny = lpgen.config0()
@@ -203,6 +262,8 @@ def main():
     log(f"tiny LP: {i0['iterations']} iterations to KKT {i0['kkt'][3]:.2e} in {t1 - t0:.3f}s")
     if not args.no_batched:
         out["batched"] = bench_batched(P, lpgen, args.batch_count, args.batch_iter_limit)
+    if not args.no_unroll:
+        out["unroll"] = bench_unroll(P, lpgen)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
         s.close()

@@ -43,9 +43,15 @@ Schedule build_schedule(const int64_t* rp, int64_t nrows) {
       for (int32_t c = 0; c < nch; ++c) s.block.push_back(RowDesc{int32_t(i), c, kSplit, id});
     }
   }
+  // Rows per lane group in one wavefront task: kRounds when the matrix has enough rows to
+  // give every wavefront of a full grid several tasks; fewer (down to 1) on small matrices,
+  // which shortens each wavefront's serial chain and spreads the rows over more workgroups.
+  int64_t tasks1 = 0;
+  for (int p = 0; p <= 6; ++p) tasks1 += (int64_t(bins[size_t(p)].size()) + (64 >> p) - 1) / (64 >> p);
+  const int rounds = int(std::min<int64_t>(kRounds, std::max<int64_t>(1, (tasks1 + kFillWaves - 1) / kFillWaves)));
   for (int p = 0; p <= 6; ++p) {
     const std::vector<int32_t>& b = bins[size_t(p)];
-    const int32_t per_task = int32_t((64 >> p) * kRounds);
+    const int32_t per_task = int32_t((64 >> p) * rounds);
     for (size_t off = 0; off < b.size(); off += size_t(per_task)) {
       const int32_t cnt = int32_t(std::min<size_t>(size_t(per_task), b.size() - off));
       s.wave.push_back(RowDesc{int32_t(s.perm.size() + off), cnt, int32_t(kWaveRows | (p << 8)), 0});

@@ -10,7 +10,8 @@ constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kElemsPerLane = 8;       // a row of length len gets L = min pow2 with len <= 8 L lanes
 constexpr int kWaveMaxLen = kElemsPerLane * 64;   // longer rows are reduced by a whole workgroup
-constexpr int kRounds = 4;             // rows per lane group in one wavefront task
+constexpr int kRounds = 4;             // rows per lane group in one wavefront task (at most)
+constexpr int kFillWaves = 8192;       // wavefronts of a full grid: 256 CUs x 8 workgroups x 4
 constexpr int kVectorMax = 16384;      // longest row one workgroup reduces alone
 constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
 constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per XCD of an MI355X)

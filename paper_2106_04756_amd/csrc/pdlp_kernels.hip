@@ -615,6 +615,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, DevState* st, const d
 // XCD column-panel mode: first pass per panel row, second pass per row in panel order
 // ------------------------------------------------------------------------------------------
 
+// COPY = 0 for passes over K~, 1 over K~^T (the same code; two symbols so that a kernel trace
+// tells the two products apart).
+template <int COPY>
 __global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, const double* in0,
                                                        const double* in1, int in_parity, double* out,
                                                        int pred, int mode) {

@@ -257,6 +257,15 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
   return 0;
 }
 
+// First pass of a panel-mode product over A (K~ or K~^T).
+void launch_panel_rows(pdlp_solver* s, const CsrDev& A, int grid, const double* in0, const double* in1,
+                       int in_par, double* out, int pred, int mode) {
+  if (&A == &s->KT)
+    k_panel_rows<1><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+  else
+    k_panel_rows<0><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+}
+
 // Grid of a CSR pass: a multiple of npanel, enough workgroups for the busiest panel.
 int grid_for(const CsrDev& A, int maxG) {
   if (A.npanel <= 1) {
@@ -274,7 +283,7 @@ int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double
                 double* out0, double* out1, int out_par, int pred, int count_as) {
   if (A.npanel > 1) {
     double* part = (&A == &s->K) ? s->partPK : s->partPT;
-    k_panel_rows<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, part,
+    launch_panel_rows(s, A, grid_for(A, s->maxG), in0, in1, in_par, part,
                                                                pred, kProd);
     PDLP_LAUNCH(s);
     k_spmv_combine<<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(
@@ -332,7 +341,7 @@ int enqueue_block(pdlp_solver* s, int par) {
   for (int i = 0; i < o.check_every; ++i) {
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i], s->stream));
     if (panT) {
-      k_panel_rows<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B.Y[0], B.Y[1], 1, s->partPT,
+      k_panel_rows<1><<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B.Y[0], B.Y[1], 1, s->partPT,
                                                     kPredAttemptKty, kProd);
       PDLP_LAUNCH(s);
       k_primal_combine<<<s->gAc, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partPT, s->partA,
@@ -343,7 +352,7 @@ int enqueue_block(pdlp_solver* s, int par) {
     PDLP_LAUNCH(s);
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 1], s->stream));
     if (panK) {
-      k_panel_rows<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B.X[1], B.X[0], 1, s->partPK,
+      k_panel_rows<0><<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B.X[1], B.X[0], 1, s->partPK,
                                                     kPredAttempt, kProd);
       PDLP_LAUNCH(s);
       k_dual_combine<<<s->gBc, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partPK, s->partA, nslotA,
@@ -424,7 +433,7 @@ int precondition(pdlp_solver* s) {
       double* out = which ? cn : rn;
       if (A.npanel > 1) {
         double* part = which ? s->partPT : s->partPK;
-        k_panel_rows<<<which ? gT : gK, kBlock, 0, s->stream>>>(A, s->st, nullptr, nullptr, 0, part,
+        launch_panel_rows(s, A, which ? gT : gK, nullptr, nullptr, 0, part,
                                                                 kPredAlways, inf_norm ? kAbsMax : kAbsSum);
         PDLP_LAUNCH(s);
         k_norm_combine<<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(A, part, out, inf_norm);
@@ -694,7 +703,7 @@ template <class Epi>
 int launch_fused(pdlp_solver* s, const CsrDev& A, const double* in, const Epi& epi) {
   if (A.npanel > 1) {
     double* part = (&A == &s->K) ? s->partPK : s->partPT;
-    k_panel_rows<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in, nullptr, 0, part,
+    launch_panel_rows(s, A, grid_for(A, s->maxG), in, nullptr, 0, part,
                                                                kPredAlways, kProd);
     PDLP_LAUNCH(s);
     k_unroll_combine<Epi><<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(A, part, epi);

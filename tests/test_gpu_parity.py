@@ -114,7 +114,11 @@ def _trajectory_parity(lp, iters=100, opts=None, **kw):
     assert len(ga) == len(oa)
     for g, o in zip(ga, oa):
         assert g[0] == o[0] and g[3] == o[3]
-        assert abs(g[1] - o[1]) <= 1e-11 * o[1]
+        # the step tried is the previous proposal of Algorithm 2, min((1 - (k+1)^-0.3) eta_bar,
+        # (1 + (k+1)^-0.6) eta): eta_bar's denominator 2 |dy^T K dx| cancels, so it carries the
+        # last-bit differences of the dot products (summed in another order on the GPU) with a
+        # gain of ~1e2 along a free-running trajectory; the iterates themselves stay at 1e-11
+        assert abs(g[1] - o[1]) <= 1e-10 * o[1]
         if math.isfinite(o[2]):
             assert abs(g[2] - o[2]) <= 1e-9 * o[2]
     gc, oc = tr["checks"], ref.trace.checks

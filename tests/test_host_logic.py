@@ -154,3 +154,12 @@ def test_create_rejects_bad_sizes_and_options():
         P.Solver(lp.m, 0, lp.n_eq, lp.c, lp.row_ptr, lp.col_idx, lp.val, lp.q, lp.l, lp.u)
     with pytest.raises(P.PdlpError, match="options"):
         _create(lp, check_every=0)
+
+
+def test_schedule_rounds_follow_matrix_size():
+    # small matrices: one row per lane group per task (more, shorter tasks); large ones: up to
+    # four rounds per task once every wavefront of a full grid has several tasks
+    for nrows, want in ((1000, 64), (8192 * 64, 64), (8192 * 64 * 3, 192), (2_000_000, 256)):
+        rp = np.arange(nrows + 1, dtype=np.int64)           # rows of one nonzero: 64 per round
+        desc, _, _ = P.schedule(rp)
+        assert desc[:, 1].max() == want, (nrows, desc[:, 1].max())
