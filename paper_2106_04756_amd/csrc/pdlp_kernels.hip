@@ -519,11 +519,13 @@ __device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA,
   double ax[1], ay[2];
   sum_slots<1>(partA, nslotA, ax);
   sum_slots<2>(partB, nslotB, ay);
-  if (threadIdx.x == 0) attempt_decide(*st, ax[0], ay[0], ay[1], B.att);
+  if (threadIdx.x == 0) {
+    if (!st->kty_valid) st->spmv_KT += 1;     // the primal step formed K~^T y
+    attempt_decide(*st, ax[0], ay[0], ay[1], B.att);
+  }
 }
 
-__global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA,
-                                                   unsigned* ticket) {
+__global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA) {
   const DevState& S = *st;
   if (!attempt_runs(S)) return;
   const int P = S.parity;
@@ -534,12 +536,6 @@ __global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs
   else csr_rows<kProd>(AT, pick(B.Y, P), epi, acc, partA);
   block_sum<1>(acc);
   write_slot<1>(partA, blockIdx.x, acc);
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) {
-      if (!kty_valid) st->spmv_KT += 1;
-    }
-    reset_ticket(ticket);
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B, const double* partA,
@@ -552,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(CsrDev A, DevState* st, Bufs B,
   csr_rows<kProd>(A, pick(B.X, P ^ 1), epi, acc, partB);
   block_sum<2>(acc);
   write_slot<2>(partB, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
   finish_attempt(st, B, partA, nslotA, partB, int(gridDim.x) + A.nsplit);
 }
@@ -590,6 +586,15 @@ struct StoreEpi {
   }
 };
 
+// Bookkeeping after a plain product: counters, and K~^T y of the current y is now valid.
+__device__ void spmv_tail(DevState* st, int pred, int count_as) {
+  if (threadIdx.x == 0) {
+    if (count_as == 1) st->spmv_K += 1;
+    if (count_as == 2) st->spmv_KT += 1;
+    if (pred == kPredCheckKty || pred == kPredKty) st->kty_valid = 1;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, DevState* st, const double* in0,
                                                  const double* in1, int in_parity, double* out0,
                                                  double* out1, int out_parity, int pred,
@@ -601,14 +606,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, DevState* st, const d
   StoreEpi epi{out};
   double acc[1] = {0.0};
   csr_rows<kProd>(A, in, epi, acc, nullptr);
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) {
-      if (count_as == 1) st->spmv_K += 1;
-      if (count_as == 2) st->spmv_KT += 1;
-      if (pred == kPredCheckKty || pred == kPredKty) st->kty_valid = 1;
-    }
-    reset_ticket(ticket);
-  }
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  spmv_tail(st, pred, count_as);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -632,8 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, c
 }
 
 __global__ __launch_bounds__(kBlock) void k_primal_combine(CsrDev AT, DevState* st, Bufs B,
-                                                           const double* part, double* partA,
-                                                           unsigned* ticket) {
+                                                           const double* part, double* partA) {
   const DevState& S = *st;
   if (!attempt_runs(S)) return;
   const int P = S.parity;
@@ -643,12 +642,6 @@ __global__ __launch_bounds__(kBlock) void k_primal_combine(CsrDev AT, DevState* 
   combine_rows<kProd>(AT, part, kty_valid ? B.KTy : nullptr, epi, acc);
   block_sum<1>(acc);
   write_slot<1>(partA, blockIdx.x, acc);
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) {
-      if (!kty_valid) st->spmv_KT += 1;
-    }
-    reset_ticket(ticket);
-  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_dual_combine(CsrDev A, DevState* st, Bufs B,
@@ -662,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_dual_combine(CsrDev A, DevState* st,
   combine_rows<kProd>(A, part, nullptr, epi, acc);
   block_sum<2>(acc);
   write_slot<2>(partB, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
   finish_attempt(st, B, partA, nslotA, partB, int(gridDim.x));
 }
@@ -676,14 +669,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_combine(CsrDev A, DevState* st,
   StoreEpi epi{out};
   double acc[1] = {0.0};
   combine_rows<kProd>(A, part, nullptr, epi, acc);
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) {
-      if (count_as == 1) st->spmv_K += 1;
-      if (count_as == 2) st->spmv_KT += 1;
-      if (pred == kPredCheckKty || pred == kPredKty) st->kty_valid = 1;
-    }
-    reset_ticket(ticket);
-  }
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  spmv_tail(st, pred, count_as);
 }
 
 __global__ __launch_bounds__(kBlock) void k_norm_combine(CsrDev A, const double* part, double* out,
@@ -1158,22 +1146,63 @@ __device__ void apply_decide(DevState& W) {
 #define PDLP_GRID_LOOP(idx, total) \
   for (int64_t idx = blockIdx.x * int64_t(kBlock) + threadIdx.x; idx < (total); idx += int64_t(gridDim.x) * kBlock)
 
+// Each check kernel below is an element pass over all n + m coordinates that writes one slot
+// per workgroup, then a tail (sums of the slots, the scalar decision) taken either by the last
+// workgroup to arrive at `ticket` (small grids) or, with ticket = nullptr, by the
+// one-workgroup kernel k_tail launched after it (large grids: there the agent-scope fences
+// of the arrival cost more than a launch).  Both run the same tail function on the same slots.
+
+__device__ __forceinline__ bool gap_active(const DevState& S, int mode) {
+  return check_runs(S) && (mode == 0 || S.restart);
+}
+__device__ __forceinline__ bool gap_bisect_active(const DevState& S, int mode, bool& act0, bool& act1) {
+  act0 = S.gap_state[0] == 0;
+  act1 = (mode == 0) && S.gap_state[1] == 0;
+  return gap_active(S, mode) && (act0 || act1);
+}
+
+__device__ void prepare_tail(DevState* st) {
+  if (threadIdx.x == 0) st->w_pending = 0.0;
+}
+__device__ void gap_setup_tail(DevState* st, int mode, const double* part, int nslot) {
+  double t[6];
+  sum_slots<6>(part, nslot, t);
+  if (threadIdx.x == 0) gap_setup_decide(*st, mode, t);
+}
+__device__ void gap_bisect_tail(DevState* st, int mode, const double* part, int nslot) {
+  double t[2 * kGapPts];
+  sum_slots<2 * kGapPts>(part, nslot, t);
+  if (threadIdx.x == 0) gap_bisect_decide(*st, mode, t);
+}
+__device__ void gap_final_tail(DevState* st, const Bufs& B, int mode, const double* part, int nslot) {
+  double t[2];
+  sum_slots<2>(part, nslot, t);
+  if (threadIdx.x == 0) gap_final_decide(*st, mode, t, B.chk);
+}
+__device__ void kkt_tail(DevState* st, const Bufs& B, int mode, const double* part, int nslot) {
+  double t[7];
+  sum_slots<7>(part, nslot, t);
+  if (threadIdx.x == 0) kkt_decide(*st, mode, t, B.chk);
+}
+__device__ void apply_tail(DevState* st) {
+  if (threadIdx.x == 0) apply_decide(*st);
+}
+
 __global__ __launch_bounds__(kBlock) void k_check_prepare(DevState* st, Bufs B, unsigned* ticket) {
   const DevState& S = *st;
   if (!check_runs(S)) return;
   const int P = S.parity;
   const double w = S.w_pending, se = S.s_eta;
   PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) prepare_elem(B, P, w, se, idx);
-  if (arrive_last(ticket, gridDim.x)) {
-    if (threadIdx.x == 0) st->w_pending = 0.0;
-    reset_ticket(ticket);
-  }
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
+  reset_ticket(ticket);
+  prepare_tail(st);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int mode, double* part,
                                                       unsigned* ticket) {
   const DevState& S = *st;
-  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  if (!gap_active(S, mode)) return;
   PointPtrs pt[2];
   gap_points_of(S, B, mode, pt);
   const int ns = (mode == 0) ? 2 : 1;
@@ -1182,20 +1211,16 @@ __global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int 
   PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_setup_elem(B, pt, ns, sw, idx, acc);
   block_sum<6>(acc);
   write_slot<6>(part, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
-  double t[6];
-  sum_slots<6>(part, gridDim.x, t);
-  if (threadIdx.x == 0) gap_setup_decide(*st, mode, t);
+  gap_setup_tail(st, mode, part, gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gap_bisect(DevState* st, Bufs B, int mode, double* part,
                                                        unsigned* ticket) {
   const DevState& S = *st;
-  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
-  const bool act0 = S.gap_state[0] == 0;
-  const bool act1 = (mode == 0) && S.gap_state[1] == 0;
-  if (!act0 && !act1) return;
+  bool act0, act1;
+  if (!gap_bisect_active(S, mode, act0, act1)) return;
   double sp[2][kGapPts];
   gap_bisect_points(S, sp);
   double acc[2 * kGapPts];
@@ -1204,17 +1229,15 @@ __global__ __launch_bounds__(kBlock) void k_gap_bisect(DevState* st, Bufs B, int
   PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_bisect_elem(B, act0, act1, sp, idx, acc);
   block_sum<2 * kGapPts>(acc);
   write_slot<2 * kGapPts>(part, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
-  double t[2 * kGapPts];
-  sum_slots<2 * kGapPts>(part, gridDim.x, t);
-  if (threadIdx.x == 0) gap_bisect_decide(*st, mode, t);
+  gap_bisect_tail(st, mode, part, gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int mode, double* part,
                                                       unsigned* ticket) {
   const DevState& S = *st;
-  if (!(check_runs(S) && (mode == 0 || S.restart))) return;
+  if (!gap_active(S, mode)) return;
   const int ns = (mode == 0) ? 2 : 1;
   double sstar[2];
   for (int s = 0; s < 2; ++s)
@@ -1223,11 +1246,9 @@ __global__ __launch_bounds__(kBlock) void k_gap_final(DevState* st, Bufs B, int 
   PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_final_elem(B, S, ns, sstar, idx, acc);
   block_sum<2>(acc);
   write_slot<2>(part, blockIdx.x, acc);
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
-  double t[2];
-  sum_slots<2>(part, gridDim.x, t);
-  if (threadIdx.x == 0) gap_final_decide(*st, mode, t, B.chk);
+  gap_final_tail(st, B, mode, part, gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, double* part,
@@ -1239,11 +1260,9 @@ __global__ __launch_bounds__(kBlock) void k_kkt(DevState* st, Bufs B, int mode, 
   PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) kkt_elem(B, pt, idx, a);
   block_sum<7>(a);
   write_slot<7>(part, blockIdx.x, a);
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
-  double t[7];
-  sum_slots<7>(part, gridDim.x, t);
-  if (threadIdx.x == 0) kkt_decide(*st, mode, t, B.chk);
+  kkt_tail(st, B, mode, part, gridDim.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, unsigned* ticket) {
@@ -1254,9 +1273,53 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, un
     const bool avg = S.use_avg != 0;
     PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) apply_elem(B, P, avg, idx);
   }
-  if (!arrive_last(ticket, gridDim.x)) return;
+  if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
-  if (threadIdx.x == 0) apply_decide(*st);
+  apply_tail(st);
+}
+
+enum TailKind : int {
+  kTailAttempt = 0, kTailSpmv, kTailPrepare, kTailGapSetup, kTailGapBisect, kTailGapFinal, kTailKkt,
+  kTailApply
+};
+
+// The tail of a kernel launched without a ticket, in one workgroup after it; it re-evaluates
+// the kernel's own entry predicate on the unchanged state, so it runs exactly when the
+// kernel's element pass ran.  part/nslot: that kernel's slots (partB for the attempt, whose
+// primal slots are partA/nslotA).
+__global__ __launch_bounds__(kBlock) void k_tail(DevState* st, Bufs B, int kind, int mode, const double* part,
+                                                 int nslot, const double* partA, int nslotA, int pred,
+                                                 int count_as) {
+  const DevState& S = *st;
+  bool a0, a1;
+  switch (kind) {
+    case kTailAttempt:
+      if (attempt_runs(S)) finish_attempt(st, B, partA, nslotA, part, nslot);
+      break;
+    case kTailSpmv:
+      if (pred_ok(S, pred)) spmv_tail(st, pred, count_as);
+      break;
+    case kTailPrepare:
+      if (check_runs(S)) prepare_tail(st);
+      break;
+    case kTailGapSetup:
+      if (gap_active(S, mode)) gap_setup_tail(st, mode, part, nslot);
+      break;
+    case kTailGapBisect:
+      if (gap_bisect_active(S, mode, a0, a1)) gap_bisect_tail(st, mode, part, nslot);
+      break;
+    case kTailGapFinal:
+      if (gap_active(S, mode)) gap_final_tail(st, B, mode, part, nslot);
+      break;
+    case kTailKkt:
+      if (!(mode == 0 && !check_runs(S))) kkt_tail(st, B, mode, part, nslot);
+      break;
+    case kTailApply:
+      if (check_runs(S)) apply_tail(st);
+      break;
+    default:
+      break;
+  }
 }
 
 // Resume from a checkpoint: vectors already copied into X[0], Y[0], XA, YA, Sx, Sy.

@@ -279,23 +279,39 @@ int grid_rows(int64_t nrows, int maxG) {
   return int(std::max<int64_t>(1, std::min<int64_t>((nrows + kBlock - 1) / kBlock, maxG)));
 }
 
+// Grids up to this size end with the last-arrival ticket; larger ones hand their tail to k_tail
+// (each arrival costs an agent-scope release, which writes back the XCD's L2).
+constexpr int kFuseMaxGrid = 64;
+
+unsigned* ticket_for(pdlp_solver* s, int grid, int which) {
+  return grid <= kFuseMaxGrid ? s->tickets + which : nullptr;
+}
+
+int launch_tail(pdlp_solver* s, int grid, int kind, int mode, const double* part, int nslot,
+                const double* partA = nullptr, int nslotA = 0, int pred = 0, int count_as = 0) {
+  if (grid <= kFuseMaxGrid) return 0;
+  k_tail<<<1, kBlock, 0, s->stream>>>(s->st, s->B, kind, mode, part, nslot, partA, nslotA, pred, count_as);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
 int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double* in1, int in_par,
                 double* out0, double* out1, int out_par, int pred, int count_as) {
   if (A.npanel > 1) {
     double* part = (&A == &s->K) ? s->partPK : s->partPT;
-    launch_panel_rows(s, A, grid_for(A, s->maxG), in0, in1, in_par, part,
-                                                               pred, kProd);
+    launch_panel_rows(s, A, grid_for(A, s->maxG), in0, in1, in_par, part, pred, kProd);
     PDLP_LAUNCH(s);
-    k_spmv_combine<<<grid_rows(A.nrows_orig, s->maxG), kBlock, 0, s->stream>>>(
-        A, s->st, part, out0, out1, out_par, pred, count_as, s->tickets + kTkSpmv);
+    const int g = grid_rows(A.nrows_orig, s->maxG);
+    k_spmv_combine<<<g, kBlock, 0, s->stream>>>(A, s->st, part, out0, out1, out_par, pred, count_as,
+                                                ticket_for(s, g, kTkSpmv));
     PDLP_LAUNCH(s);
-    return 0;
+    return launch_tail(s, g, kTailSpmv, 0, nullptr, 0, nullptr, 0, pred, count_as);
   }
-  k_spmv<<<grid_for(A, s->maxG), kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out0, out1,
-                                                       out_par, pred, count_as,
-                                                       s->tickets + kTkSpmv);
+  const int g = grid_for(A, s->maxG);
+  k_spmv<<<g, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out0, out1, out_par, pred, count_as,
+                                      ticket_for(s, g, kTkSpmv));
   PDLP_LAUNCH(s);
-  return 0;
+  return launch_tail(s, g, kTailSpmv, 0, nullptr, 0, nullptr, 0, pred, count_as);
 }
 
 // Power iteration on K~^T K~ from the all-ones vector (v, w: n values, t: m values); leaves
@@ -320,16 +336,26 @@ int power_iterate(pdlp_solver* s, double* v, double* t, double* w) {
 }
 
 int enqueue_gap(pdlp_solver* s, int mode) {
-  unsigned* tk = s->tickets;
-  k_gap_setup<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, tk + kTkGapSetup);
+  int rc;
+  const int g = s->gE;
+  k_gap_setup<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapSetup));
   PDLP_LAUNCH(s);
+  if ((rc = launch_tail(s, g, kTailGapSetup, mode, s->partX, g))) return rc;
   for (int p = 0; p < kBisectPasses; ++p) {
-    k_gap_bisect<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, tk + kTkGapBisect);
+    k_gap_bisect<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapBisect));
     PDLP_LAUNCH(s);
+    if ((rc = launch_tail(s, g, kTailGapBisect, mode, s->partX, g))) return rc;
   }
-  k_gap_final<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, tk + kTkGapFinal);
+  k_gap_final<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapFinal));
   PDLP_LAUNCH(s);
-  return 0;
+  return launch_tail(s, g, kTailGapFinal, mode, s->partX, g);
+}
+
+int enqueue_kkt(pdlp_solver* s, int mode) {
+  const int g = s->gE;
+  k_kkt<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkKkt));
+  PDLP_LAUNCH(s);
+  return launch_tail(s, g, kTailKkt, mode, s->partX, g);
 }
 
 int enqueue_block(pdlp_solver* s, int par) {
@@ -338,16 +364,19 @@ int enqueue_block(pdlp_solver* s, int par) {
   Bufs& B = s->B;
   const bool panT = s->KT.npanel > 1, panK = s->K.npanel > 1;
   const int nslotA = panT ? s->gAc : s->gA + s->KT.nsplit;
+  const int gDual = panK ? s->gBc : s->gB;
+  const int nslotB = panK ? s->gBc : s->gB + s->K.nsplit;
+  unsigned* tkDual = ticket_for(s, gDual, kTkDual);
+  int rc;
   for (int i = 0; i < o.check_every; ++i) {
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i], s->stream));
     if (panT) {
       k_panel_rows<1><<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B.Y[0], B.Y[1], 1, s->partPT,
                                                     kPredAttemptKty, kProd);
       PDLP_LAUNCH(s);
-      k_primal_combine<<<s->gAc, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partPT, s->partA,
-                                                         tk + kTkPrimal);
+      k_primal_combine<<<s->gAc, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partPT, s->partA);
     } else {
-      k_primal<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA, tk + kTkPrimal);
+      k_primal<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA);
     }
     PDLP_LAUNCH(s);
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 1], s->stream));
@@ -356,11 +385,12 @@ int enqueue_block(pdlp_solver* s, int par) {
                                                     kPredAttempt, kProd);
       PDLP_LAUNCH(s);
       k_dual_combine<<<s->gBc, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partPK, s->partA, nslotA,
-                                                       s->partB, tk + kTkDual);
+                                                       s->partB, tkDual);
     } else {
-      k_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partA, nslotA, s->partB, tk + kTkDual);
+      k_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partA, nslotA, s->partB, tkDual);
     }
     PDLP_LAUNCH(s);
+    if ((rc = launch_tail(s, gDual, kTailAttempt, 0, s->partB, nslotB, s->partA, nslotA))) return rc;
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 2], s->stream));
     if (o.trace_iters > 0) {
       k_snapshot<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkSnap);
@@ -368,20 +398,21 @@ int enqueue_block(pdlp_solver* s, int par) {
     }
   }
   // restart / termination check
-  int rc;
+  const int gE = s->gE;
   if (o.adaptive_restarts) {
-    k_check_prepare<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkPrep);
+    k_check_prepare<<<gE, kBlock, 0, s->stream>>>(s->st, B, ticket_for(s, gE, kTkPrep));
     PDLP_LAUNCH(s);
+    if ((rc = launch_tail(s, gE, kTailPrepare, 0, nullptr, 0))) return rc;
     if ((rc = launch_spmv(s, s->KT, B.YB, nullptr, 0, B.KTYB, nullptr, 0, kPredCheck, 2))) return rc;
     if ((rc = launch_spmv(s, s->K, B.XB, nullptr, 0, B.KXB, nullptr, 0, kPredCheck, 1))) return rc;
   }
   if ((rc = launch_spmv(s, s->KT, B.Y[0], B.Y[1], 1, B.KTy, nullptr, 0, kPredCheckKty, 2))) return rc;
   if (o.adaptive_restarts && (rc = enqueue_gap(s, 0))) return rc;
-  k_kkt<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, 0, s->partX, tk + kTkKkt);
-  PDLP_LAUNCH(s);
+  if ((rc = enqueue_kkt(s, 0))) return rc;
   if (o.adaptive_restarts && (rc = enqueue_gap(s, 1))) return rc;
-  k_check_apply<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkApply);
+  k_check_apply<<<gE, kBlock, 0, s->stream>>>(s->st, B, ticket_for(s, gE, kTkApply));
   PDLP_LAUNCH(s);
+  if ((rc = launch_tail(s, gE, kTailApply, 0, nullptr, 0))) return rc;
   PDLP_HIP(s, hipMemcpyAsync(&s->h_st[par], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
   PDLP_HIP(s, hipEventRecord(s->blk_ev[par], s->stream));
   return 0;
@@ -940,8 +971,7 @@ int pdlp_solve(pdlp_solver* s, double tol, int64_t iter_limit) {
   k_set_solve_params<<<1, 1, 0, s->stream>>>(s->st, tol, iter_limit);
   PDLP_LAUNCH(s);
   if (!s->initial_checked) {
-    k_kkt<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, 1, s->partX, s->tickets + kTkKkt);
-    PDLP_LAUNCH(s);
+    if ((rc = enqueue_kkt(s, 1))) return rc;
     s->initial_checked = true;
   }
   DevState h;
@@ -964,8 +994,7 @@ int pdlp_solve(pdlp_solver* s, double tol, int64_t iter_limit) {
   if (h.status != PDLP_OPTIMAL) {
     // KKT error of the returned (current) point, which needs K~^T y of the current y
     if ((rc = launch_spmv(s, s->KT, s->B.Y[0], s->B.Y[1], 1, s->B.KTy, nullptr, 0, kPredKty, 2))) return rc;
-    k_kkt<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, 2, s->partX, s->tickets + kTkKkt);
-    PDLP_LAUNCH(s);
+    if ((rc = enqueue_kkt(s, 2))) return rc;
     if ((rc = read_state(s, &h))) return rc;
   }
   s->solved = true;
