@@ -337,9 +337,10 @@ int pdlp_reset_kernel_times(pdlp_solver *s);
 /*
  * pdlp_build_schedule - host-only (no GPU needed): the work schedule the CSR products use
  * for a matrix with nrows rows and offsets row_ptr.  Rows of at most 512 nonzeros are
- * grouped by the lane count L = 2^p (the smallest with length <= 8 L) and listed in *perm
- * (nrows entries at most, may be NULL); a wavefront task {a, b, 0 | p << 8, 0} covers rows
- * perm[a .. a + b).  Longer rows get workgroup tasks {row, 0, 1, 0}; rows above 16384
+ * grouped by the lane count L = 2^p (the smallest with length <= 8 L), ordered by length
+ * within a group, and listed in *perm (nrows entries at most, may be NULL); a wavefront task
+ * {a, b, 0 | p << 8, E} covers rows perm[a .. a + b), E (1..8) entries per lane, E L >= the
+ * longest of those rows.  Longer rows get workgroup tasks {row, 0, 1, 0}; rows above 16384
  * nonzeros are cut into chunks {row, chunk, 2, split id}.  Writes up to cap tasks of four
  * int32 (wavefront tasks first) to desc and sets *ndesc (all tasks) and *nsplit.
  */

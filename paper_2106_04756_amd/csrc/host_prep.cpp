@@ -22,6 +22,12 @@ int lanes_log2_for(int64_t len) {
   return p;
 }
 
+// entries per lane for rows of at most maxlen nonzeros on 2^p lanes: ceil(maxlen / 2^p), >= 1
+int32_t entries_per_lane(int64_t maxlen, int p) {
+  const int64_t L = int64_t(1) << p;
+  return int32_t(std::max<int64_t>(1, std::min<int64_t>(kElemsPerLane, (maxlen + L - 1) / L)));
+}
+
 }  // namespace
 
 Schedule build_schedule(const int64_t* rp, int64_t nrows) {
@@ -50,11 +56,22 @@ Schedule build_schedule(const int64_t* rp, int64_t nrows) {
   for (int p = 0; p <= 6; ++p) tasks1 += (int64_t(bins[size_t(p)].size()) + (64 >> p) - 1) / (64 >> p);
   const int rounds = int(std::min<int64_t>(kRounds, std::max<int64_t>(1, (tasks1 + kFillWaves - 1) / kFillWaves)));
   for (int p = 0; p <= 6; ++p) {
-    const std::vector<int32_t>& b = bins[size_t(p)];
+    std::vector<int32_t>& b = bins[size_t(p)];
+    // rows of one lane class ordered by length, so a task's rows need about the same number of
+    // entries per lane
+    std::stable_sort(b.begin(), b.end(), [&](int32_t x, int32_t y) {
+      return rp[x + 1] - rp[x] < rp[y + 1] - rp[y];
+    });
     const int32_t per_task = int32_t((64 >> p) * rounds);
     for (size_t off = 0; off < b.size(); off += size_t(per_task)) {
       const int32_t cnt = int32_t(std::min<size_t>(size_t(per_task), b.size() - off));
-      s.wave.push_back(RowDesc{int32_t(s.perm.size() + off), cnt, int32_t(kWaveRows | (p << 8)), 0});
+      int64_t maxlen = 0;
+      for (int32_t i = 0; i < cnt; ++i) {
+        const int32_t r = b[off + size_t(i)];
+        maxlen = std::max(maxlen, rp[r + 1] - rp[r]);
+      }
+      s.wave.push_back(RowDesc{int32_t(s.perm.size() + off), cnt, int32_t(kWaveRows | (p << 8)),
+                               entries_per_lane(maxlen, p)});
     }
     s.perm.insert(s.perm.end(), b.begin(), b.end());
   }
@@ -63,12 +80,15 @@ Schedule build_schedule(const int64_t* rp, int64_t nrows) {
 
 namespace {
 
-// Appends wavefront tasks for the panel rows [k0, k1) (all of one lane class `lg`).
-void push_wave_tasks(Schedule& s, int64_t k0, int64_t k1, int lg) {
+// Appends wavefront tasks for the panel rows [k0, k1) (all of one lane class `lg`, ordered by
+// length) with offsets prow_ptr.
+void push_wave_tasks(Schedule& s, const std::vector<int64_t>& prow_ptr, int64_t k0, int64_t k1, int lg) {
   const int64_t per_task = int64_t((64 >> lg) * kRounds);
   for (int64_t off = k0; off < k1; off += per_task) {
     const int32_t cnt = int32_t(std::min<int64_t>(per_task, k1 - off));
-    s.wave.push_back(RowDesc{int32_t(off), cnt, int32_t(kWaveRows | (lg << 8)), 0});
+    int64_t maxlen = 0;
+    for (int64_t k = off; k < off + cnt; ++k) maxlen = std::max(maxlen, prow_ptr[size_t(k) + 1] - prow_ptr[size_t(k)]);
+    s.wave.push_back(RowDesc{int32_t(off), cnt, int32_t(kWaveRows | (lg << 8)), entries_per_lane(maxlen, lg)});
   }
 }
 
@@ -103,7 +123,8 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
     for (int q = 0; q < P; ++q) nprow += seg[size_t(r) * P + q] > 0;
   }
   if (double(nprow) > max_prow_frac * double(std::max<int64_t>(nnz, 1))) return false;
-  // order panel rows: panel, then lane class (wavefront rows by p, then long rows), then row
+  // order panel rows: panel, then lane class (wavefront rows by p, then long rows), then
+  // length (wavefront classes), then row
   L.prow_ptr.reserve(size_t(nprow) + 1);
   L.prow_ptr.push_back(0);
   L.prow_row.reserve(size_t(nprow));
@@ -114,11 +135,19 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
   for (int p = 0; p < P; ++p) {
     for (int cls = 0; cls <= 7; ++cls) {           // 0..6 lane classes, 7 = long rows
       const int64_t k0 = int64_t(L.prow_row.size());
+      std::vector<int32_t> rows_cls;
       for (int64_t r = 0; r < nrows; ++r) {
         const int64_t len = seg[size_t(r) * P + p];
         if (len == 0) continue;
         const int c = (len <= kWaveMaxLen) ? lanes_log2_for(len) : 7;
-        if (c != cls) continue;
+        if (c == cls) rows_cls.push_back(int32_t(r));
+      }
+      if (cls < 7)
+        std::stable_sort(rows_cls.begin(), rows_cls.end(), [&](int32_t x, int32_t y) {
+          return seg[size_t(x) * P + p] < seg[size_t(y) * P + p];
+        });
+      for (const int32_t r : rows_cls) {
+        const int64_t len = seg[size_t(r) * P + p];
         prow_of[size_t(r) * P + p] = int32_t(L.prow_row.size());
         L.prow_row.push_back(int32_t(r));
         L.prow_ptr.push_back(L.prow_ptr.back() + len);
@@ -137,7 +166,7 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
           }
         }
       }
-      if (cls < 7) push_wave_tasks(S, k0, int64_t(L.prow_row.size()), cls);
+      if (cls < 7) push_wave_tasks(S, L.prow_ptr, k0, int64_t(L.prow_row.size()), cls);
     }
     L.wave_begin.push_back(int32_t(S.wave.size()));
     L.block_begin.push_back(int32_t(S.block.size()));

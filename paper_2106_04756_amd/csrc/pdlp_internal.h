@@ -19,7 +19,8 @@ constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per X
 enum DescKind : int32_t { kWaveRows = 0, kVector = 1, kSplit = 2 };
 
 // One unit of SpMV work.
-//  kWaveRows: rows perm[a .. a + b) for one wavefront, 2^(kind_l >> 8) lanes per row
+//  kWaveRows: rows perm[a .. a + b) for one wavefront, 2^(kind_l >> 8) lanes per row,
+//             aux entries per lane (aux * lanes >= every row length of the task)
 //  kVector:   row a, reduced by one workgroup
 //  kSplit:    chunk b of row a (split id aux), reduced by one workgroup, combined by the last
 struct RowDesc {

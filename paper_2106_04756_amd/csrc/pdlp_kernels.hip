@@ -220,6 +220,61 @@ __device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const double* _
   }
 }
 
+// One wavefront task: rows perm[D.a .. D.a + D.b) (panel rows D.a .. in panel mode), each by a
+// group of L = 2^p lanes, E entries per lane (E L >= every row length of the task).
+// Branch-free loads: every lane loads its E entries with the index clamped into the row, so all
+// loads (and then all gathers) are in flight together; entries past the row end are masked to
+// +0.0, which leaves the sum bit-identical for any E.
+template <int MODE, int E, class Epi>
+__device__ __forceinline__ void wave_task(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
+                                          double (&acc)[Epi::N], const RowDesc& D, int lane64) {
+  const int lg = D.kind_l >> 8, L = 1 << lg;
+  const int g = lane64 >> lg, lane = lane64 & (L - 1);
+  const int per_round = 64 >> lg;
+  for (int base = 0; base < D.b; base += per_round) {
+    const int slot = base + g;
+    const bool active = slot < D.b;
+    int r = 0;
+    double s = 0.0;
+    if (active) {
+      r = A.perm ? A.perm[D.a + slot] : D.a + slot;
+      const int64_t q0 = A.rp[r], p1 = A.rp[r + 1];
+      if (p1 > q0) {
+        const int64_t p0 = q0 + lane;
+        double v[E];
+        int32_t c[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          const int64_t e = p0 + int64_t(k) * L;
+          const int64_t ec = (e < p1) ? e : p1 - 1;
+          v[k] = A.v[ec];
+          if constexpr (MODE == kProd) c[k] = A.ci[ec];
+        }
+        if constexpr (MODE == kProd) {
+          double xv[E];
+#pragma unroll
+          for (int k = 0; k < E; ++k) xv[k] = x[c[k]];
+#pragma unroll
+          for (int k = 0; k < E; ++k) {
+            const double t = v[k] * xv[k];
+            s = s + ((p0 + int64_t(k) * L < p1) ? t : 0.0);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < E; ++k) s = comb<MODE>(s, (p0 + int64_t(k) * L < p1) ? fabs(v[k]) : 0.0);
+        }
+      }
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) s = comb<MODE>(s, __shfl_xor(s, off, 64));
+    if (active && lane == 0) {
+      double cc[Epi::N];
+      epi.row(r, s, cc);
+#pragma unroll
+      for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
+    }
+  }
+}
+
 // Visit every row of A once: row value s = sum_j A_rj x_j (kProd) or max/sum |A_rj|, and
 // call epi.row(r, s, contrib).  Rows up to kWaveMaxLen long are handled by wavefronts on
 // their own (no LDS, no workgroup barrier): a group of L = 2^p lanes per row, each lane
@@ -236,54 +291,15 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
   const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[ps.p] + ps.lb * kWaves + (threadIdx.x >> 6));
   for (int t = w0; t < t1; t += nw) {
     const RowDesc D = A.wave[t];
-    const int lg = D.kind_l >> 8, L = 1 << lg;
-    const int g = lane64 >> lg, lane = lane64 & (L - 1);
-    const int per_round = 64 >> lg;
-    for (int base = 0; base < D.b; base += per_round) {
-      const int slot = base + g;
-      const bool active = slot < D.b;
-      int r = 0;
-      double s = 0.0;
-      if (active) {
-        r = A.perm ? A.perm[D.a + slot] : D.a + slot;
-        const int64_t q0 = A.rp[r], p1 = A.rp[r + 1];
-        if (p1 > q0) {
-          // Branch-free loads: every lane loads kElemsPerLane entries with the index clamped
-          // into the row, so all loads (and then all gathers) are in flight together; entries
-          // past the row end are masked to +0.0, which leaves the sum bit-identical.
-          const int64_t p0 = q0 + lane;
-          double v[kElemsPerLane];
-          int32_t c[kElemsPerLane];
-#pragma unroll
-          for (int k = 0; k < kElemsPerLane; ++k) {
-            const int64_t e = p0 + int64_t(k) * L;
-            const int64_t ec = (e < p1) ? e : p1 - 1;
-            v[k] = A.v[ec];
-            if constexpr (MODE == kProd) c[k] = A.ci[ec];
-          }
-          if constexpr (MODE == kProd) {
-            double xv[kElemsPerLane];
-#pragma unroll
-            for (int k = 0; k < kElemsPerLane; ++k) xv[k] = x[c[k]];
-#pragma unroll
-            for (int k = 0; k < kElemsPerLane; ++k) {
-              const double t = v[k] * xv[k];
-              s = s + ((p0 + int64_t(k) * L < p1) ? t : 0.0);
-            }
-          } else {
-#pragma unroll
-            for (int k = 0; k < kElemsPerLane; ++k)
-              s = comb<MODE>(s, (p0 + int64_t(k) * L < p1) ? fabs(v[k]) : 0.0);
-          }
-        }
-      }
-      for (int off = L >> 1; off > 0; off >>= 1) s = comb<MODE>(s, __shfl_xor(s, off, 64));
-      if (active && lane == 0) {
-        double cc[Epi::N];
-        epi.row(r, s, cc);
-#pragma unroll
-        for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
-      }
+    switch (D.aux) {       // entries per lane of this task (uniform across the wavefront)
+      case 1: wave_task<MODE, 1>(A, x, epi, acc, D, lane64); break;
+      case 2: wave_task<MODE, 2>(A, x, epi, acc, D, lane64); break;
+      case 3: wave_task<MODE, 3>(A, x, epi, acc, D, lane64); break;
+      case 4: wave_task<MODE, 4>(A, x, epi, acc, D, lane64); break;
+      case 5: wave_task<MODE, 5>(A, x, epi, acc, D, lane64); break;
+      case 6: wave_task<MODE, 6>(A, x, epi, acc, D, lane64); break;
+      case 7: wave_task<MODE, 7>(A, x, epi, acc, D, lane64); break;
+      default: wave_task<MODE, kElemsPerLane>(A, x, epi, acc, D, lane64); break;
     }
   }
   csr_block_tasks<MODE>(A, x, epi, acc, part);

@@ -68,6 +68,9 @@ def _check_schedule(row_ptr):
             rows = perm[a:a + b]
             perm_used[a:a + b] += 1
             assert np.all(lens[rows] <= ELEMS_PER_LANE * L)
+            # entries per lane: enough for the task's longest row, and no more
+            assert 1 <= aux <= ELEMS_PER_LANE and np.all(lens[rows] <= aux * L)
+            assert aux == 1 or lens[rows].max() > (aux - 1) * L
             if lg > 0:
                 assert np.all(lens[rows] > ELEMS_PER_LANE * L // 2)
             seen[rows] += 1
