@@ -98,22 +98,54 @@ __device__ double block_max(double v) {
 }
 
 // Sum over `nslot` partial slots of N values each (slot-major), value k in a[k] of thread 0.
+// Slots are plain memory: they are read after a kernel boundary (k_tail) or after the acquire
+// fence of arrive_last, which pairs with the release fence every writer passed.  When N
+// divides the workgroup size, thread t sums value k = t mod N of every (kBlock / N)-th slot, so
+// each pass over the slots is one contiguous read; the kBlock / N partial sums of each k are
+// then added in a fixed order.
 template <int N>
 __device__ void sum_slots(const double* part, int nslot, double (&a)[N]) {
+  if constexpr (N >= 8 && kBlock % N == 0) {
+    constexpr int G = kBlock / N;
+    __shared__ double lds[kBlock];
+    const int k = threadIdx.x % N, g = threadIdx.x / N;
+    // eight interleaved partial sums keep eight loads in flight per thread
+    double u8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int sl = g;
+    for (; sl + 7 * G < nslot; sl += 8 * G) {
 #pragma unroll
-  for (int k = 0; k < N; ++k) a[k] = 0.0;
-  for (int s = threadIdx.x; s < nslot; s += kBlock) {
+      for (int q = 0; q < 8; ++q) u8[q] += part[size_t(sl + q * G) * N + k];
+    }
+    for (int q = 0; sl < nslot; sl += G, ++q) u8[q] += part[size_t(sl) * N + k];
+    const double t = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
+    __syncthreads();
+    lds[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) a[k] += ld_agent(&part[size_t(s) * N + k]);
+      for (int kk = 0; kk < N; ++kk) {
+        double u = 0.0;
+        for (int gg = 0; gg < G; ++gg) u += lds[gg * N + kk];
+        a[kk] = u;
+      }
+    }
+    __syncthreads();
+  } else {
+#pragma unroll
+    for (int k = 0; k < N; ++k) a[k] = 0.0;
+    for (int sl = threadIdx.x; sl < nslot; sl += kBlock) {
+#pragma unroll
+      for (int k = 0; k < N; ++k) a[k] += part[size_t(sl) * N + k];
+    }
+    block_sum<N>(a);
   }
-  block_sum<N>(a);
 }
 
 template <int N>
 __device__ __forceinline__ void write_slot(double* part, int slot, const double (&a)[N]) {
   if (threadIdx.x == 0) {
 #pragma unroll
-    for (int k = 0; k < N; ++k) st_agent(&part[size_t(slot) * N + k], a[k]);
+    for (int k = 0; k < N; ++k) part[size_t(slot) * N + k] = a[k];
   }
 }
 

@@ -335,9 +335,13 @@ int power_iterate(pdlp_solver* s, double* v, double* t, double* w) {
   return 0;
 }
 
+// The normalized-gap passes accumulate 2 x 32 sums per workgroup, so they run on a grid of at
+// most kGapGrid workgroups (fewer slots for the tail to add).
+constexpr int kGapGrid = 512;
+
 int enqueue_gap(pdlp_solver* s, int mode) {
   int rc;
-  const int g = s->gE;
+  const int g = std::min(s->gE, kGapGrid);
   k_gap_setup<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapSetup));
   PDLP_LAUNCH(s);
   if ((rc = launch_tail(s, g, kTailGapSetup, mode, s->partX, g))) return rc;
