@@ -27,6 +27,39 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+PROFILE = os.path.join(ROOT, "profiles", "pdlp_step_large_plain_lp.txt")
+
+
+def kernel_sources_digest():
+    """sha256 over the library's HIP/C++ sources and its C header (names and contents)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2106_04756_amd", "csrc", "*")))
+    for f in files + [os.path.join(ROOT, "include", "pdlp.h")]:
+        h.update(os.path.relpath(f, ROOT).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(steps, warmup):
+    """HBM bytes per step slot (primal, dual) that the rocprofv3 byte counters gave for this
+    very source tree and bench configuration, read from the committed profile summary; None
+    when the kernels or the configuration differ from the profiled ones."""
+    try:
+        with open(PROFILE) as fh:
+            for line in fh:
+                if line.startswith("bench-traffic: "):
+                    d = json.loads(line[len("bench-traffic: "):])
+                    if (d["sources_sha256"] == kernel_sources_digest() and d["steps"] == steps
+                            and d["warmup"] == warmup):
+                        return d["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
 def cpu_baseline(lp, budget_s=20.0):
     """The oracle's PDHG attempts (Eq. (3) + Algorithm 2 rule) on the same LP, single thread,
     timed on a bounded sample of iterations."""
@@ -219,6 +252,7 @@ def main():
     bpl = total_bytes[dom] / counts[dom]
     achieved = bpl / (avg_ms * 1e-3) / 1e9
     step_gbs = info["step_bytes"] * steps / dt / 1e9
+    traffic = profiled_traffic(K, W)
     out = {
         "metric": "PDHG iters/s",
         "value": steps / dt,
@@ -236,12 +270,15 @@ def main():
                                f"30% equality rows, mixed bounds), seed {args.seed}",
                    "tol": 1e-8, "steps_taken": steps},
         "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": (traffic or {}).get(["primal", "dual"][dom]),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
                      "avg_launch_ms": avg_ms, "launches": int(counts[dom]),
                      "products": int([prim_products, dual_products][dom]), "attempts": int(d_att),
                      "algorithmic_bytes_per_launch": bpl},
         "step_gbs_algorithmic": step_gbs,
         "step_avg_ms": {"primal": times[0] / counts[0], "dual": times[1] / counts[1]},
+        "algorithmic_bytes_per_slot": {"primal": total_bytes[0] / counts[0], "dual": total_bytes[1] / counts[1]},
     }
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
     tiny = lpgen.config0()
