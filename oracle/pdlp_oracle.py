@@ -46,7 +46,11 @@ class Options:
     ruiz_iters: int = 10                 # Section 3.5: 10 Ruiz passes ...
     pock_chambolle: bool = True          # ... then one Pock-Chambolle pass
     pc_alpha: float = 1.0                # alpha = 1
-    step_policy: str = "adaptive"        # Algorithm 2; "constant" = eta 0.9/||K||_2 (Section 2 baseline)
+    step_policy: str = "adaptive"        # Algorithm 2; "constant" = eta 0.9/||K||_2 (Section 2 baseline);
+                                         # "malitsky_pock" = the line search of Appendix C
+    mp_breaking_factor: float = 1.0      # Malitsky-Pock hyperparameters, the paper's best setting
+    mp_downscaling: float = 0.5
+    mp_interpolation: float = 0.4
     restarts: bool = True                # Section 3.2 adaptive restarts
     restart_to_current: bool = True      # False: the candidate is always the average
                                          # (Appendix C "adaptive restart (theory)")
@@ -375,10 +379,34 @@ def power_iteration_norm(K, iters) -> float:
 # PDLP driver (Algorithm 1)
 # ------------------------------------------------------------------------------------------
 
+def mp_candidate(eta, theta, interpolation):
+    """Malitsky-Pock line search (Appendix C), the first candidate step for iteration k+1:
+    eta^ = eta_k + interpolation (sqrt(1 + theta_k) - 1) eta_k, theta^ = eta_k / eta^, with
+    theta_k = eta_{k-1} / eta_k as the appendix defines it (reading R6: the reciprocal of
+    Malitsky and Pock's own ratio; the printed definition is followed)."""
+    eta_hat = eta + interpolation * (math.sqrt(1.0 + theta) - 1.0) * eta
+    return eta_hat, eta / eta_hat
+
+
+def mp_dual_trial(x, xp, y, eta_hat, theta_hat, omega, K, q, m1):
+    """Candidate dual iterate of the line search: proj_Y(y + omega eta^ (q - K(x' + theta^ (x' - x))))."""
+    yh = y + (omega * eta_hat) * (q - K @ (xp + theta_hat * (xp - x)))
+    yh[:m1] = np.maximum(yh[:m1], 0.0)
+    return yh
+
+
+def mp_accepts(eta_hat, dy, KTdy, breaking_factor) -> bool:
+    """The line-search test eta^ ||K^T (y^ - y)|| <= breaking_factor ||y^ - y|| (reading R7:
+    the step in front of the norm is the candidate eta^ the trial was computed with)."""
+    return eta_hat * float(np.linalg.norm(KTdy)) <= breaking_factor * float(np.linalg.norm(dy))
+
+
 def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None = None,
           trace_iters: int = 0, record_trace: bool = False, record_states: int = 0) -> Result:
     """Algorithm 1 after preconditioning: adaptive steps (Algorithm 2), eta-weighted
     averages, restart candidate, restart criteria, primal weight updates (Algorithm 3).
+    step_policy "constant" takes the fixed step of the baseline PDHG (Section 2) and
+    "malitsky_pock" the line search of Appendix C in place of Algorithm 2.
 
     Evaluation cadence (Section 3): restart/termination checks only when the number of
     accepted steps k is a positive multiple of check_every, plus a termination check before
@@ -429,6 +457,8 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
     Seta = 0.0
     mu_prev = math.inf
     mu_anchor = math.inf
+    mp_theta = 1.0                              # Malitsky-Pock theta_k (1 at the start, R8)
+    kty = KtT @ y                               # K~^T y of the current y
 
     def finish(status, xs, ys):
         kk = unscaled_kkt(xs, ys)
@@ -447,45 +477,85 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
                                   mu_anchor=mu_anchor))
         if k >= iter_limit:
             return finish(ITERATION_LIMIT, x, y)
-        # ---- AdaptiveStepOfPDHG (Algorithm 2) ----
-        eta = eta_hat
-        retries = 0
-        while True:
-            xp, yp = pdhg_step(x, y, eta, omega, ct, Kt, KtT, qt, lt, ut, m1)
-            attempts += 1
-            kkt_passes += 1.0
-            if opts.step_policy == "constant":
-                eta_bar = math.inf
-                eta_next = eta
-            else:
-                eta_bar = step_size_limit(xp - x, yp - y, omega, Kt)
-                eta_next = next_step_size(eta_bar, eta, k + 1)
-            ok = np.isfinite(eta_next) and np.all(np.isfinite(xp)) and np.all(np.isfinite(yp))
-            accepted = bool(ok and eta <= eta_bar)
-            if tr is not None:
-                tr.attempts.append((k, eta, eta_bar, accepted))
-            if not ok:
-                st = OPTIMAL if unscaled_kkt(x, y)["kkt"] <= tol else NUMERICAL_ERROR
-                return finish(st, x, y)
-            if accepted:
-                break
-            eta = eta_next
-            retries += 1
-            if retries >= opts.max_retries:
-                st = OPTIMAL if unscaled_kkt(x, y)["kkt"] <= tol else NUMERICAL_ERROR
-                return finish(st, x, y)
-        x, y = xp, yp
-        Sx += eta * x
-        Sy += eta * y
-        Seta += eta
-        eta_hat = eta_next
-        k += 1
-        t += 1
-        if tr is not None and k <= trace_iters:
-            tr.iterates.append((k, x.copy(), y.copy()))
-
-        if k % opts.check_every != 0:
-            continue
+        if opts.step_policy == "malitsky_pock":
+            # ---- Malitsky-Pock line search (Appendix C) ----
+            xp = np.clip(x - (eta_hat / omega) * (ct - kty), lt, ut)
+            eta, th = mp_candidate(eta_hat, mp_theta, opts.mp_interpolation)
+            retries = 0
+            while True:
+                yp = mp_dual_trial(x, xp, y, eta, th, omega, Kt, qt, m1)
+                kty_p = KtT @ yp
+                attempts += 1
+                kkt_passes += 1.0
+                dy = yp - y
+                kdy = kty_p - kty
+                nk = float(np.linalg.norm(kdy))
+                eta_bar = opts.mp_breaking_factor * float(np.linalg.norm(dy)) / nk if nk > 0.0 else math.inf
+                ok = bool(np.all(np.isfinite(xp)) and np.all(np.isfinite(yp)))
+                accepted = bool(ok and mp_accepts(eta, dy, kdy, opts.mp_breaking_factor))
+                if tr is not None:
+                    tr.attempts.append((k, eta, eta_bar, accepted))
+                if not ok:
+                    st = OPTIMAL if unscaled_kkt(x, y)["kkt"] <= tol else NUMERICAL_ERROR
+                    return finish(st, x, y)
+                if accepted:
+                    break
+                eta = opts.mp_downscaling * eta
+                th = eta_hat / eta
+                retries += 1
+                if retries >= opts.max_retries:
+                    st = OPTIMAL if unscaled_kkt(x, y)["kkt"] <= tol else NUMERICAL_ERROR
+                    return finish(st, x, y)
+            x, y, kty = xp, yp, kty_p
+            Sx += eta * x                       # weight: the accepted step (reading R9)
+            Sy += eta * y
+            Seta += eta
+            eta_hat, mp_theta = eta, th
+            k += 1
+            t += 1
+            if tr is not None and k <= trace_iters:
+                tr.iterates.append((k, x.copy(), y.copy()))
+            if k % opts.check_every != 0:
+                continue
+        else:
+            # ---- AdaptiveStepOfPDHG (Algorithm 2) ----
+            eta = eta_hat
+            retries = 0
+            while True:
+                xp, yp = pdhg_step(x, y, eta, omega, ct, Kt, KtT, qt, lt, ut, m1)
+                attempts += 1
+                kkt_passes += 1.0
+                if opts.step_policy == "constant":
+                    eta_bar = math.inf
+                    eta_next = eta
+                else:
+                    eta_bar = step_size_limit(xp - x, yp - y, omega, Kt)
+                    eta_next = next_step_size(eta_bar, eta, k + 1)
+                ok = np.isfinite(eta_next) and np.all(np.isfinite(xp)) and np.all(np.isfinite(yp))
+                accepted = bool(ok and eta <= eta_bar)
+                if tr is not None:
+                    tr.attempts.append((k, eta, eta_bar, accepted))
+                if not ok:
+                    st = OPTIMAL if unscaled_kkt(x, y)["kkt"] <= tol else NUMERICAL_ERROR
+                    return finish(st, x, y)
+                if accepted:
+                    break
+                eta = eta_next
+                retries += 1
+                if retries >= opts.max_retries:
+                    st = OPTIMAL if unscaled_kkt(x, y)["kkt"] <= tol else NUMERICAL_ERROR
+                    return finish(st, x, y)
+            x, y = xp, yp
+            Sx += eta * x
+            Sy += eta * y
+            Seta += eta
+            eta_hat = eta_next
+            k += 1
+            t += 1
+            if tr is not None and k <= trace_iters:
+                tr.iterates.append((k, x.copy(), y.copy()))
+            if k % opts.check_every != 0:
+                continue
         # ---- restart / termination check (Algorithm 1, Section 3.2) ----
         xbar = Sx / Seta
         ybar = Sy / Seta
@@ -527,6 +597,9 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
             mu_anchor = normalized_gap(xc, yc, xa, ya, omega, gxc, gyc, lt, ut, m1)
             xa, ya = xc.copy(), yc.copy()
             x, y = xc.copy(), yc.copy()
+            if opts.step_policy == "malitsky_pock":
+                kty = KtT @ y
+                mp_theta = 1.0                  # the line search restarts with theta = 1 (R8)
             Sx[:] = 0.0
             Sy[:] = 0.0
             Seta = 0.0

@@ -492,3 +492,59 @@ def test_unroll_user_units_gradient_matches_finite_differences():
         e[i] = h
         fd = (loss(lp.c, lp.q + e) - loss(lp.c, lp.q - e)) / (2 * h)
         assert abs(fd - base["gq"][i]) <= 1e-6 * (1 + abs(fd)), (i, fd, base["gq"][i])
+
+
+# ------------------------------------------------------------------------------------------
+# Malitsky-Pock line search (Appendix C)
+# ------------------------------------------------------------------------------------------
+
+def test_malitsky_pock_without_interpolation_is_fixed_step_pdhg():
+    # interpolation 0 keeps eta^ = eta_k and theta^ = 1, so the trial is the extrapolation
+    # 2x' - x of Eq. (3); with eta <= 1/||K~||_2 the test eta ||K^T dy|| <= ||dy|| always
+    # holds, so the line search accepts every first trial and follows fixed-step PDHG.
+    lp = lpgen.tiny_plain(21, 50, 110, 20, 4)
+    Kt, ct, qt, lt, ut, D1, D2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
+    KT = Kt.T.tocsr()
+    eta = 0.9 / np.linalg.norm(Kt.toarray(), 2)
+    omega = 1.3
+    x = np.clip(np.zeros(lp.n), lt, ut)
+    y = np.zeros(lp.m)
+    xr, yr = x.copy(), y.copy()
+    theta = 1.0
+    for _ in range(60):
+        xp = np.clip(x - (eta / omega) * (ct - KT @ y), lt, ut)
+        eh, th = O.mp_candidate(eta, theta, 0.0)
+        assert eh == eta and th == 1.0
+        yp = O.mp_dual_trial(x, xp, y, eh, th, omega, Kt, qt, lp.m1)
+        assert O.mp_accepts(eh, yp - y, KT @ (yp - y), 1.0)
+        x, y, theta = xp, yp, th
+        xr, yr = O.pdhg_step(xr, yr, eta, omega, ct, Kt, KT, qt, lt, ut, lp.m1)
+        assert np.allclose(x, xr, rtol=1e-12, atol=1e-12) and np.allclose(y, yr, rtol=1e-12, atol=1e-12)
+
+
+def test_malitsky_pock_candidate_range():
+    # eta^ lies in [eta_k, sqrt(1 + theta_k) eta_k], at the ends for interpolation 0 and 1
+    for theta in (0.25, 1.0, 3.0):
+        lo, _ = O.mp_candidate(2.0, theta, 0.0)
+        hi, th = O.mp_candidate(2.0, theta, 1.0)
+        assert lo == 2.0 and abs(hi - 2.0 * math.sqrt(1.0 + theta)) < 1e-15 and abs(th - 2.0 / hi) < 1e-16
+        mid, _ = O.mp_candidate(2.0, theta, 0.4)
+        assert lo < mid < hi
+
+
+def test_malitsky_pock_solves_to_highs_objective():
+    lp = lpgen.config0()
+    opts = O.Options(step_policy="malitsky_pock")
+    r = O.solve_lp(lp, tol=1e-8, iter_limit=60000, opts=opts, record_trace=True)
+    assert r.status == O.OPTIMAL and r.kkt["kkt"] <= 1e-8
+    ref, _, _ = _highs(lp)
+    assert abs(float(lp.c @ r.x) - ref) <= 1e-6 * max(1.0, abs(ref))
+    # every logged trial obeys the acceptance rule it reports
+    rejected = 0
+    for (k, eta, eta_bar, acc) in r.trace.attempts:
+        rejected += not acc
+        if math.isinf(eta_bar):
+            assert acc
+        elif abs(eta - eta_bar) > 1e-12 * eta:
+            assert acc == (eta < eta_bar)
+    assert rejected > 0          # the line search did shrink steps on this LP
