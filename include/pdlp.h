@@ -75,11 +75,17 @@ typedef struct pdlp_options {
   double primal_importance;      /* multiplies the initial primal weight: 1                   */
   double eps_zero;               /* "small nonzero tolerance" of Section 3.3: 1e-10           */
   int32_t step_policy;           /* 0 adaptive (Algorithm 2, default); 1 constant
-                                    eta = 0.9 / ||K~||_2 (the baseline PDHG of Section 2)       */
+                                    eta = 0.9 / ||K~||_2 (the baseline PDHG of Section 2);
+                                    2 the Malitsky-Pock line search of Appendix C             */
   int32_t restart_to_current;    /* 1 (default): candidate by GetRestartCandidate; 0: always
                                     the average (Appendix C "adaptive restart (theory)")      */
   int32_t power_iters;           /* power iterations for ||K~||_2 (constant policy): 200     */
   int32_t reserved1;
+  double mp_breaking_factor;     /* Malitsky-Pock (step_policy 2): a trial step eta^ is kept
+                                    when eta^ ||K~^T (y^ - y)|| <= this * ||y^ - y||: 1       */
+  double mp_downscaling;         /* factor applied to eta^ after a failed trial, in (0,1): 0.5 */
+  double mp_interpolation;       /* first trial eta_k + this (sqrt(1+theta_k) - 1) eta_k,
+                                    in [0,1]: 0.4 (the paper's best setting)                  */
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

@@ -52,6 +52,7 @@ struct Bufs {
   double* Y[2];
   double* KX[2];         // K~ x of X[.]
   double* KTy;           // K~^T y of the current y (valid when DevState.kty_valid)
+  double* KTyH;          // K~^T y^ of the running Malitsky-Pock trial
   double* Sx;            // eta-weighted sums since the last restart
   double* Sy;
   double* XB;            // averages and their products (restart checks)
@@ -75,7 +76,8 @@ enum Pred : int {
   kPredKty = 3,
   kPredCheckRestart = 4,
   kPredAttempt = 5,
-  kPredAttemptKty = 6
+  kPredAttemptKty = 6,
+  kPredMpNew = 7         // an attempt runs and starts a Malitsky-Pock iteration
 };
 
 }  // namespace pdlp

@@ -114,6 +114,14 @@ struct DevState {
   int32_t to_current;     // GetRestartCandidate may pick the current iterate
   double pow_norm2;       // power iteration: squared norm of the last K^T K v
   double beta_suff, beta_nec, beta_art, theta, eps_zero;
+  // Malitsky-Pock line search (step policy 2): eta_hat is the step of the last accepted
+  // iteration (the primal step), eta the candidate of the running trial.
+  int32_t mp_on;
+  int32_t mp_stage;       // 0: the next attempt starts an iteration; 1: it retries the dual trial
+  int32_t mp_commit;      // the last trial was accepted: K~^T y^ is to become K~^T y
+  int32_t pad1;
+  double mp_theta;        // theta_k = eta_{k-1} / eta_k
+  double mp_bf, mp_df, mp_ic;   // breaking factor, downscaling factor, interpolation coefficient
 };
 
 // Small record the host reads after every enqueued block.

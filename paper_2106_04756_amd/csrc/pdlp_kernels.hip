@@ -435,6 +435,10 @@ __device__ __forceinline__ double* pick(double* const (&a)[2], int P) { return P
 __device__ __forceinline__ bool attempt_runs(const DevState& S) {
   return !S.done && !S.check_pending && S.k < S.iter_limit;
 }
+// The primal step of an attempt runs unless the attempt retries a Malitsky-Pock dual trial.
+__device__ __forceinline__ bool primal_runs(const DevState& S) {
+  return attempt_runs(S) && !(S.mp_on && S.mp_stage);
+}
 __device__ __forceinline__ bool check_runs(const DevState& S) {
   return !S.done && S.check_pending;
 }
@@ -446,7 +450,8 @@ __device__ bool pred_ok(const DevState& S, int pred) {
     case kPredKty: return !S.kty_valid;
     case kPredCheckRestart: return check_runs(S) && S.restart;
     case kPredAttempt: return attempt_runs(S);
-    case kPredAttemptKty: return attempt_runs(S) && !S.kty_valid;
+    case kPredAttemptKty: return primal_runs(S) && !S.kty_valid;
+    case kPredMpNew: return primal_runs(S);
     default: return false;
   }
 }
@@ -573,12 +578,18 @@ __device__ void finish_attempt(DevState* st, const Bufs& B, const double* partA,
   }
 }
 
+// Step of the primal update: the attempt's eta (Algorithm 2, constant step) or, under the
+// Malitsky-Pock line search, the step eta_k of the last accepted iteration.
+__device__ __forceinline__ double primal_step(const DevState& S) {
+  return (S.mp_on ? S.eta_hat : S.eta) / S.omega;
+}
+
 __global__ __launch_bounds__(kBlock) void k_primal(CsrDev AT, DevState* st, Bufs B, double* partA) {
   const DevState& S = *st;
-  if (!attempt_runs(S)) return;
+  if (!primal_runs(S)) return;
   const int P = S.parity;
   const int kty_valid = S.kty_valid;
-  PrimalEpi epi{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  PrimalEpi epi{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, primal_step(S), S.w_pending, !kty_valid};
   double acc[1] = {0.0};
   if (kty_valid) csr_rows_stored(AT, B.KTy, epi, acc, partA);
   else csr_rows<kProd>(AT, pick(B.Y, P), epi, acc, partA);
@@ -619,6 +630,185 @@ __global__ __launch_bounds__(kBlock) void k_snapshot(DevState* st, Bufs B, unsig
     }
     reset_ticket(ticket);
   }
+}
+
+// ------------------------------------------------------------------------------------------
+// Malitsky-Pock line search (Appendix C): x' from the step eta_k of the last iteration, then
+// dual trials y^ = proj_Y(y + omega eta^ (q - K~(x' + th (x' - x)))), th = eta_k / eta^,
+// accepted when eta^ ||K~^T (y^ - y)|| <= breaking_factor ||y^ - y||, else eta^ is scaled down.
+// K~(x' + th (x' - x)) is formed as (1 + th) K~x' - th K~x from the cached K~x.
+// ------------------------------------------------------------------------------------------
+
+// First candidate of an iteration from the accepted step eta_k (in W.eta_hat) and theta_k.
+__device__ __forceinline__ void mp_first_candidate(DevState& W) {
+  W.eta = W.eta_hat + W.mp_ic * (sqrt(1.0 + W.mp_theta) - 1.0) * W.eta_hat;
+  W.mp_stage = 0;
+}
+
+// Dual trial of row i given s = (K~ x')_i; stores K~ x' when the product was just formed, adds
+// the pending average weight of the last accepted y (first trial of an iteration only).
+struct MpDualEpi {
+  static constexpr int N = 1;
+  const double* __restrict__ q;
+  const double* __restrict__ y;
+  const double* __restrict__ kx;
+  double* __restrict__ yn;
+  double* __restrict__ kxn;
+  double* __restrict__ sy;
+  double sigma, th, w;
+  int m1, store_kx;
+  __device__ __forceinline__ void row(int i, double s, double (&out)[1]) const {
+    const double yi = y[i];
+    if (store_kx) kxn[i] = s;
+    if (w != 0.0) sy[i] = sy[i] + w * yi;
+    double v = yi + sigma * (q[i] - ((1.0 + th) * s - th * kx[i]));
+    if (i < m1) v = fmax(v, 0.0);
+    yn[i] = v;
+    const double d = v - yi;
+    out[0] = d * d;
+  }
+};
+
+// K~^T y^ of the trial: stored, and ||K~^T y^ - K~^T y||^2 accumulated.
+struct MpKtyEpi {
+  static constexpr int N = 1;
+  const double* __restrict__ kty;
+  double* __restrict__ ktyh;
+  __device__ __forceinline__ void row(int j, double s, double (&out)[1]) const {
+    ktyh[j] = s;
+    const double d = s - kty[j];
+    out[0] = d * d;
+  }
+};
+
+__device__ __forceinline__ MpDualEpi mp_dual_epi(const DevState& S, const Bufs& B, int store_kx) {
+  const int P = S.parity;
+  return MpDualEpi{B.q, pick(B.Y, P), pick(B.KX, P), pick(B.Y, P ^ 1), pick(B.KX, P ^ 1), B.Sy,
+                   S.omega * S.eta, S.eta_hat / S.eta, S.w_pending, B.m1, store_kx};
+}
+
+// First trial of an iteration, fused with the product K~ x' (plain layout).
+__global__ __launch_bounds__(kBlock) void k_mp_dual(CsrDev A, DevState* st, Bufs B, double* partB) {
+  const DevState& S = *st;
+  if (!primal_runs(S)) return;
+  const MpDualEpi epi = mp_dual_epi(S, B, 1);
+  double acc[1] = {0.0};
+  csr_rows<kProd>(A, pick(B.X, S.parity ^ 1), epi, acc, partB);
+  block_sum<1>(acc);
+  write_slot<1>(partB, blockIdx.x, acc);
+}
+
+// Same, second pass of the XCD-panel layout.
+__global__ __launch_bounds__(kBlock) void k_mp_dual_combine(CsrDev A, DevState* st, Bufs B, const double* part,
+                                                            double* partB) {
+  const DevState& S = *st;
+  if (!primal_runs(S)) return;
+  const MpDualEpi epi = mp_dual_epi(S, B, 1);
+  double acc[1] = {0.0};
+  combine_rows<kProd>(A, part, nullptr, epi, acc);
+  block_sum<1>(acc);
+  write_slot<1>(partB, blockIdx.x, acc);
+}
+
+// A retried trial: the same row update from the stored K~ x'.
+__global__ __launch_bounds__(kBlock) void k_mp_retry(DevState* st, Bufs B, double* partB) {
+  const DevState& S = *st;
+  if (!(attempt_runs(S) && S.mp_stage)) return;
+  const MpDualEpi epi = mp_dual_epi(S, B, 0);
+  const double* kxn = pick(B.KX, S.parity ^ 1);
+  double acc[1] = {0.0};
+  for (int i = blockIdx.x * kBlock + threadIdx.x; i < B.m; i += gridDim.x * kBlock) {
+    double c[1];
+    epi.row(i, kxn[i], c);
+    acc[0] += c[0];
+  }
+  block_sum<1>(acc);
+  write_slot<1>(partB, blockIdx.x, acc);
+}
+
+// K~^T y^ of every trial (plain layout).
+__global__ __launch_bounds__(kBlock) void k_mp_kty(CsrDev AT, DevState* st, Bufs B, double* partA) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const MpKtyEpi epi{B.KTy, B.KTyH};
+  double acc[1] = {0.0};
+  csr_rows<kProd>(AT, pick(B.Y, S.parity ^ 1), epi, acc, partA);
+  block_sum<1>(acc);
+  write_slot<1>(partA, blockIdx.x, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mp_kty_combine(CsrDev AT, DevState* st, Bufs B, const double* part,
+                                                           double* partA) {
+  const DevState& S = *st;
+  if (!attempt_runs(S)) return;
+  const MpKtyEpi epi{B.KTy, B.KTyH};
+  double acc[1] = {0.0};
+  combine_rows<kProd>(AT, part, nullptr, epi, acc);
+  block_sum<1>(acc);
+  write_slot<1>(partA, blockIdx.x, acc);
+}
+
+// The line-search test and the bookkeeping of Algorithm 1 for one trial.  One thread.
+__device__ void mp_decide(DevState& W, double dy2, double kdy2, pdlp_attempt_rec* att) {
+  const double eta = W.eta;
+  const double ndy = sqrt(dy2), nkdy = sqrt(kdy2);
+  const double eta_bar = (nkdy > 0.0) ? W.mp_bf * ndy / nkdy : INFINITY;
+  const bool ok = isfinite(dy2) && isfinite(kdy2);
+  const bool accepted = ok && (eta * nkdy <= W.mp_bf * ndy);
+  if (att && W.trace_cap > 0) {
+    pdlp_attempt_rec& rec = att[W.n_att_log % W.trace_cap];
+    rec.k = W.k;
+    rec.eta = eta;
+    rec.eta_bar = eta_bar;
+    rec.accepted = accepted ? 1 : 0;
+    rec.pad = 0;
+  }
+  W.n_att_log += 1;
+  W.attempts += 1;
+  W.spmv_KT += 1;                         // K~^T y^
+  if (W.mp_stage == 0) {
+    W.spmv_K += 1;                        // K~ x'
+    if (!W.kty_valid) {                   // the primal step formed K~^T y
+      W.spmv_KT += 1;
+      W.kty_valid = 1;
+    }
+  }
+  W.w_pending = 0.0;
+  W.mp_commit = accepted ? 1 : 0;
+  if (!ok) {
+    W.status = PDLP_NUMERICAL_ERROR;
+    W.done = 1;
+    return;
+  }
+  if (accepted) {
+    W.parity ^= 1;
+    W.w_pending = eta;
+    W.s_eta += eta;
+    W.mp_theta = W.eta_hat / eta;         // theta_{k+1} = eta_k / eta_{k+1}
+    W.eta_hat = eta;
+    mp_first_candidate(W);
+    W.k += 1;
+    W.t += 1;
+    W.retries = 0;
+    if (W.k % W.check_every == 0) W.check_pending = 1;
+    if (W.k <= W.trace_iters) W.snap_pending = 1;
+  } else {
+    W.eta = W.mp_df * eta;
+    W.mp_stage = 1;
+    W.retries += 1;
+    if (W.retries >= W.max_retries) {
+      W.status = PDLP_NUMERICAL_ERROR;
+      W.done = 1;
+    }
+  }
+}
+
+// After an accepted trial: K~^T y <- K~^T y^ (the product of the new current y).  The flag is
+// the outcome of the latest trial, so a repeated copy (a slot whose attempt did not run) copies
+// the same values again; a restart clears it.
+__global__ __launch_bounds__(kBlock) void k_mp_commit(DevState* st, Bufs B) {
+  if (!st->mp_commit) return;
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < B.n; j += gridDim.x * kBlock) B.KTy[j] = B.KTyH[j];
 }
 
 // ------------------------------------------------------------------------------------------
@@ -682,10 +872,10 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, c
 __global__ __launch_bounds__(kBlock) void k_primal_combine(CsrDev AT, DevState* st, Bufs B,
                                                            const double* part, double* partA) {
   const DevState& S = *st;
-  if (!attempt_runs(S)) return;
+  if (!primal_runs(S)) return;
   const int P = S.parity;
   const int kty_valid = S.kty_valid;
-  PrimalEpi epi{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
+  PrimalEpi epi{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, primal_step(S), S.w_pending, !kty_valid};
   double acc[1] = {0.0};
   combine_rows<kProd>(AT, part, kty_valid ? B.KTy : nullptr, epi, acc);
   block_sum<1>(acc);
@@ -836,6 +1026,10 @@ __global__ __launch_bounds__(kBlock) void k_init(CsrDev A, DevState* st, Bufs B,
   W.omega = ((nc > eps_zero && nq > eps_zero) ? nc / nq : 1.0) * primal_importance;
   W.eta_hat = (mx > 0.0) ? 1.0 / mx : 1.0;
   W.eta = W.eta_hat;
+  if (W.mp_on) {
+    W.mp_theta = 1.0;
+    mp_first_candidate(W);
+  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -1178,6 +1372,11 @@ __device__ void apply_decide(DevState& W) {
     W.n_outer += 1;
     W.mu_prev = INFINITY;
     W.kty_valid = 1;
+    if (W.mp_on) {                       // the line search starts afresh: theta = 1
+      W.mp_theta = 1.0;
+      W.mp_commit = 0;
+      mp_first_candidate(W);
+    }
   } else if (W.restarts_on) {
     W.mu_prev = W.mu_c;
   }
@@ -1328,7 +1527,7 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, un
 
 enum TailKind : int {
   kTailAttempt = 0, kTailSpmv, kTailPrepare, kTailGapSetup, kTailGapBisect, kTailGapFinal, kTailKkt,
-  kTailApply
+  kTailApply, kTailMp
 };
 
 // The tail of a kernel launched without a ticket, in one workgroup after it; it re-evaluates
@@ -1365,6 +1564,15 @@ __global__ __launch_bounds__(kBlock) void k_tail(DevState* st, Bufs B, int kind,
     case kTailApply:
       if (check_runs(S)) apply_tail(st);
       break;
+    case kTailMp:   // part: the trial's ||dy||^2 slots (nslot for a first trial, pred for a
+                    // retry); partA: the ||K^T dy||^2 slots
+      if (attempt_runs(S)) {
+        double a[1], b[1];
+        sum_slots<1>(part, S.mp_stage ? pred : nslot, a);
+        sum_slots<1>(partA, nslotA, b);
+        if (threadIdx.x == 0) mp_decide(*st, a[0], b[0], B.att);
+      }
+      break;
     default:
       break;
   }
@@ -1394,6 +1602,11 @@ __global__ void k_set_state(DevState* st, pdlp_state v) {
     W.use_avg = 0;
     W.out_avg = 0;
     W.snap_pending = 0;
+    if (W.mp_on) {
+      W.mp_theta = 1.0;
+      W.mp_commit = 0;
+      mp_first_candidate(W);
+    }
   }
 }
 

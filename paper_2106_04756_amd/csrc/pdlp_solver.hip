@@ -362,6 +362,42 @@ int enqueue_kkt(pdlp_solver* s, int mode) {
   return launch_tail(s, g, kTailKkt, mode, s->partX, g);
 }
 
+// The dual side of one Malitsky-Pock attempt: the first trial of an iteration (K~ x' and y^)
+// or a retried trial (y^ from the stored K~ x'), then K~^T y^, the line-search test, and the
+// commit of K~^T y^ after an accepted trial.  Every kernel reads its go/no-go from the state.
+int enqueue_mp_trial(pdlp_solver* s) {
+  Bufs& B = s->B;
+  const bool panT = s->KT.npanel > 1, panK = s->K.npanel > 1;
+  if (panK) {
+    k_panel_rows<0><<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B.X[1], B.X[0], 1, s->partPK,
+                                                     kPredMpNew, kProd);
+    PDLP_LAUNCH(s);
+    k_mp_dual_combine<<<s->gBc, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partPK, s->partB);
+  } else {
+    k_mp_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partB);
+  }
+  PDLP_LAUNCH(s);
+  const int gR = s->gBc;
+  k_mp_retry<<<gR, kBlock, 0, s->stream>>>(s->st, B, s->partB);
+  PDLP_LAUNCH(s);
+  if (panT) {
+    k_panel_rows<1><<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B.Y[1], B.Y[0], 1, s->partPT,
+                                                     kPredAttempt, kProd);
+    PDLP_LAUNCH(s);
+    k_mp_kty_combine<<<s->gAc, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partPT, s->partA);
+  } else {
+    k_mp_kty<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA);
+  }
+  PDLP_LAUNCH(s);
+  const int nslotB = panK ? s->gBc : s->gB + s->K.nsplit;
+  const int nslotA = panT ? s->gAc : s->gA + s->KT.nsplit;
+  k_tail<<<1, kBlock, 0, s->stream>>>(s->st, B, kTailMp, 0, s->partB, nslotB, s->partA, nslotA, gR, 0);
+  PDLP_LAUNCH(s);
+  k_mp_commit<<<s->gAc, kBlock, 0, s->stream>>>(s->st, B);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
 int enqueue_block(pdlp_solver* s, int par) {
   const pdlp_options& o = s->opts;
   unsigned* tk = s->tickets;
@@ -384,6 +420,15 @@ int enqueue_block(pdlp_solver* s, int par) {
     }
     PDLP_LAUNCH(s);
     if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 1], s->stream));
+    if (o.step_policy == 2) {
+      if ((rc = enqueue_mp_trial(s))) return rc;
+      if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 2], s->stream));
+      if (o.trace_iters > 0) {
+        k_snapshot<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkSnap);
+        PDLP_LAUNCH(s);
+      }
+      continue;
+    }
     if (panK) {
       k_panel_rows<0><<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B.X[1], B.X[0], 1, s->partPK,
                                                     kPredAttempt, kProd);
@@ -586,6 +631,7 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
     PDLP_HIP(s, s->alloc(&B.GB[p], NM));
   }
   PDLP_HIP(s, s->alloc(&B.KTy, N));
+  PDLP_HIP(s, s->alloc(&B.KTyH, N));
   PDLP_HIP(s, s->alloc(&B.Sx, N));
   PDLP_HIP(s, s->alloc(&B.Sy, M));
   PDLP_HIP(s, s->alloc(&B.XB, N));
@@ -637,6 +683,11 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   h.trace_cap = cap;
   h.restarts_on = s->opts.adaptive_restarts;
   h.constant_step = s->opts.step_policy == 1;
+  h.mp_on = s->opts.step_policy == 2;
+  h.mp_theta = 1.0;
+  h.mp_bf = s->opts.mp_breaking_factor;
+  h.mp_df = s->opts.mp_downscaling;
+  h.mp_ic = s->opts.mp_interpolation;
   h.to_current = s->opts.restart_to_current != 0;
   h.pw_on = s->opts.primal_weight_update;
   h.beta_suff = s->opts.beta_sufficient;
@@ -906,6 +957,9 @@ void pdlp_default_options(pdlp_options* o) {
   o->time_kernels = 0;
   o->xcd_panels = -1;
   o->step_policy = 0;
+  o->mp_breaking_factor = 1.0;
+  o->mp_downscaling = 0.5;
+  o->mp_interpolation = 0.4;
   o->restart_to_current = 1;
   o->power_iters = 200;
   o->beta_sufficient = 0.1;
@@ -938,7 +992,9 @@ int pdlp_create(pdlp_solver** out, int64_t m, int64_t n, int64_t n_eq, const dou
   if (o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || o.trace_iters < 0 ||
       o.trace_capacity < 0 || !(o.theta >= 0.0 && o.theta <= 1.0) || !(o.primal_importance > 0.0) ||
       !(o.eps_zero >= 0.0) || !(o.beta_sufficient > 0.0) || !(o.beta_necessary > 0.0) ||
-      !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 1 || o.power_iters < 1) {
+      !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 2 || o.power_iters < 1 ||
+      !(o.mp_breaking_factor > 0.0) || !(o.mp_downscaling > 0.0 && o.mp_downscaling < 1.0) ||
+      !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0)) {
     g_create_error = "invalid options";
     delete s;
     return PDLP_ERR_INVALID_ARGUMENT;

@@ -260,6 +260,32 @@ def test_solve_config0_to_1e8():
     assert 0.5 * ref.k <= info["iterations"] <= 2 * ref.k
 
 
+@pytest.mark.parametrize("panels", [0, 1])
+def test_malitsky_pock_trajectory_parity(panels):
+    """The line search of Appendix C (step_policy 2): the first 100 iterates, every trial's
+    step and acceptance, and the checks against the oracle, free-running, in the plain row
+    layout and in forced XCD panels."""
+    worst = _trajectory_parity(lpgen.config0(), opts=O.Options(step_policy="malitsky_pock"), step_policy=2,
+                               xcd_panels=panels)
+    say("malitsky-pock worst iterate error", worst)
+
+
+def test_malitsky_pock_solve_to_1e8():
+    lp = lpgen.config0()
+    say("solve config0 malitsky-pock")
+    s = make(lp, step_policy=2)
+    st = s.solve(1e-8, 100000)
+    assert st == P.OPTIMAL
+    x, y, kkt = s.get()
+    k = O.kkt(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, x, y)
+    assert k["kkt"] <= 1e-8
+    ref = O.solve_lp(lp, tol=1e-8, opts=O.Options(step_policy="malitsky_pock"))
+    info = s.info()
+    assert 0.5 * ref.k <= info["iterations"] <= 2 * ref.k
+    # each iteration forms K~ x' once and K~^T y^ once per trial
+    assert info["spmv_K"] >= info["iterations"] and info["spmv_KT"] >= info["attempts"]
+
+
 def test_solve_pagerank_matches_stationary_vector():
     N = 20000
     lp = lpgen.pagerank_lp(2, N)
