@@ -80,7 +80,9 @@ typedef struct pdlp_options {
   int32_t restart_to_current;    /* 1 (default): candidate by GetRestartCandidate; 0: always
                                     the average (Appendix C "adaptive restart (theory)")      */
   int32_t power_iters;           /* power iterations for ||K~||_2 (constant policy): 200     */
-  int32_t reserved1;
+  int32_t use_graphs;            /* replay each block of check_every attempts and its check as
+                                    a captured HIP graph (one launch instead of one per
+                                    kernel): 1 (default); ignored while time_kernels is set   */
   double mp_breaking_factor;     /* Malitsky-Pock (step_policy 2): a trial step eta^ is kept
                                     when eta^ ||K~^T (y^ - y)|| <= this * ||y^ - y||: 1       */
   double mp_downscaling;         /* factor applied to eta^ after a failed trial, in (0,1): 0.5 */

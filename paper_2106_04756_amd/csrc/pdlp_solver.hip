@@ -73,6 +73,10 @@ struct pdlp_solver {
   int gA = 1, gB = 1, gE = 1, maxG = 1;
   DevState* h_st = nullptr;            // pinned, two records
   hipEvent_t blk_ev[2] = {nullptr, nullptr};
+  hipStream_t cap_stream = nullptr;    // private stream the block graphs are captured on
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  bool graphs_tried = false;
   std::vector<hipEvent_t> tev[2];
   double t_ms[2] = {0.0, 0.0};
   int64_t t_cnt[2] = {0, 0};
@@ -109,11 +113,14 @@ struct pdlp_solver {
 
   ~pdlp_solver() {
     if (stream) (void)hipStreamSynchronize(stream);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     for (void* p : allocs) (void)hipFree(p);
     for (void* p : U.allocs) (void)hipFree(p);
     if (h_st) (void)hipHostFree(h_st);
     for (int b = 0; b < 2; ++b) {
       if (blk_ev[b]) (void)hipEventDestroy(blk_ev[b]);
+      if (gexec[b]) (void)hipGraphExecDestroy(gexec[b]);
+      if (graph[b]) (void)hipGraphDestroy(graph[b]);
       for (hipEvent_t e : tev[b]) (void)hipEventDestroy(e);
     }
   }
@@ -463,6 +470,54 @@ int enqueue_block(pdlp_solver* s, int par) {
   PDLP_LAUNCH(s);
   if ((rc = launch_tail(s, gE, kTailApply, 0, nullptr, 0))) return rc;
   PDLP_HIP(s, hipMemcpyAsync(&s->h_st[par], s->st, sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+  return 0;
+}
+
+// Captures the launch sequence of a block (parity 0 and 1) as two HIP graphs on a private
+// stream.  Every kernel reads its go/no-go and its parity-selected buffers from the device
+// state, so a block's launches and arguments never change and one capture serves every
+// block of the solve.  On any failure the solver keeps launching kernel by kernel.
+void capture_block_graphs(pdlp_solver* s) {
+  s->graphs_tried = true;
+  if (!s->opts.use_graphs || s->opts.time_kernels) return;
+  if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    s->cap_stream = nullptr;
+    return;
+  }
+  hipStream_t user = s->stream;
+  bool ok = true;
+  for (int par = 0; par < 2 && ok; ++par) {
+    s->stream = s->cap_stream;
+    ok = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    const int rc = ok ? enqueue_block(s, par) : 0;
+    hipGraph_t g = nullptr;
+    const bool ended = ok && hipStreamEndCapture(s->cap_stream, &g) == hipSuccess;
+    ok = ok && rc == 0 && ended && g &&
+         hipGraphInstantiate(&s->gexec[par], g, nullptr, nullptr, 0) == hipSuccess;
+    s->graph[par] = g;
+  }
+  s->stream = user;
+  if (!ok) {
+    (void)hipGetLastError();
+    for (int par = 0; par < 2; ++par) {
+      if (s->gexec[par]) (void)hipGraphExecDestroy(s->gexec[par]);
+      if (s->graph[par]) (void)hipGraphDestroy(s->graph[par]);
+      s->gexec[par] = nullptr;
+      s->graph[par] = nullptr;
+    }
+    s->err.clear();
+  }
+}
+
+// Enqueues block `par` (graph replay or kernel by kernel) and the event the host waits on.
+int launch_block(pdlp_solver* s, int par) {
+  if (s->gexec[par]) {
+    PDLP_HIP(s, hipGraphLaunch(s->gexec[par], s->stream));
+  } else {
+    int rc;
+    if ((rc = enqueue_block(s, par))) return rc;
+  }
   PDLP_HIP(s, hipEventRecord(s->blk_ev[par], s->stream));
   return 0;
 }
@@ -962,6 +1017,7 @@ void pdlp_default_options(pdlp_options* o) {
   o->mp_interpolation = 0.4;
   o->restart_to_current = 1;
   o->power_iters = 200;
+  o->use_graphs = 1;
   o->beta_sufficient = 0.1;
   o->beta_necessary = 0.9;
   o->beta_artificial = 0.5;
@@ -1037,9 +1093,10 @@ int pdlp_solve(pdlp_solver* s, double tol, int64_t iter_limit) {
   DevState h;
   if ((rc = read_state(s, &h))) return rc;
   if (!block_stops(h)) {
+    if (!s->graphs_tried) capture_block_graphs(s);
     int b = 0;
     for (;;) {
-      if ((rc = enqueue_block(s, b & 1))) return rc;
+      if ((rc = launch_block(s, b & 1))) return rc;
       if (b > 0) {
         if ((rc = wait_block(s, (b - 1) & 1))) return rc;
         if (block_stops(s->h_st[(b - 1) & 1])) break;

@@ -39,7 +39,7 @@ class Options(ctypes.Structure):
                 ("beta_artificial", ctypes.c_double), ("theta", ctypes.c_double),
                 ("primal_importance", ctypes.c_double), ("eps_zero", ctypes.c_double),
                 ("step_policy", ctypes.c_int32), ("restart_to_current", ctypes.c_int32),
-                ("power_iters", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("power_iters", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
                 ("mp_breaking_factor", ctypes.c_double), ("mp_downscaling", ctypes.c_double),
                 ("mp_interpolation", ctypes.c_double)]
 

@@ -318,6 +318,37 @@ def test_two_runs_are_bitwise_equal_and_resume_is_seamless(panels):
     assert ia["iterations"] == ib["iterations"] == 300 and ia["omega"] == ib["omega"]
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(xcd_panels=1), dict(step_policy=2)])
+def test_graph_replay_equals_kernel_by_kernel(kw):
+    """Blocks replayed as captured HIP graphs give bit-identical iterates, counters and every
+    attempt and check record (each block's replay is compared) as launching kernel by kernel,
+    with host synchronisation between the blocks as in every solve."""
+    lp = lpgen.config0()
+    say("graph replay vs eager", kw)
+    out = []
+    for graphs in (1, 0):
+        s = make(lp, use_graphs=graphs, **kw)
+        st = s.solve(1e-8, 2000)
+        st2 = s.solve(1e-8, 100000)          # a second call continues with the same graphs
+        x, y, kkt = s.get()
+        info = s.info()
+        tr = s.trace()
+        out.append((st, st2, x, y, kkt, info, tr))
+        s.close()
+    a, b = out
+    assert a[0] == b[0] and a[1] == b[1] == P.OPTIMAL
+    for i in (2, 3, 4):
+        assert np.array_equal(a[i], b[i])
+    for key in ("iterations", "attempts", "restarts", "checks", "spmv_K", "spmv_KT", "omega", "eta_hat"):
+        assert a[5][key] == b[5][key], key
+    assert a[6]["attempts"] == b[6]["attempts"]
+    assert len(a[6]["checks"]) == len(b[6]["checks"])
+    for ca, cb in zip(a[6]["checks"], b[6]["checks"]):
+        for key in ca:       # NaN (no anchor gap without a restart) compares as equal to NaN
+            va, vb = ca[key], cb[key]
+            assert va == vb or (isinstance(va, float) and math.isnan(va) and math.isnan(vb)), key
+
+
 def test_edge_cases():
     # no constraints at all: min c^T x over a box
     n = 7

@@ -52,6 +52,7 @@ def test_default_options_are_the_papers():
     assert o.eps_zero == 1e-10 and o.primal_importance == 1.0
     assert (o.step_policy, o.restart_to_current, o.power_iters, o.xcd_panels) == (0, 1, 200, -1)
     assert (o.mp_breaking_factor, o.mp_downscaling, o.mp_interpolation) == (1.0, 0.5, 0.4)
+    assert o.use_graphs == 1
 
 
 def _check_schedule(row_ptr):
