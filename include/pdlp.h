@@ -88,6 +88,12 @@ typedef struct pdlp_options {
   double mp_downscaling;         /* factor applied to eta^ after a failed trial, in (0,1): 0.5 */
   double mp_interpolation;       /* first trial eta_k + this (sqrt(1+theta_k) - 1) eta_k,
                                     in [0,1]: 0.4 (the paper's best setting)                  */
+  int32_t column_order;          /* internal order of the primal variables: -1 automatic (on
+                                    exactly when the K~ copy may use XCD panels), 0 the user's
+                                    order, 1 within each panel's column range the columns with
+                                    the most nonzeros first.  Invisible at this interface:
+                                    every n-vector in or out is in the user's order.           */
+  int32_t reserved2;
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

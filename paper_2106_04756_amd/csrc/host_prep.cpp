@@ -94,12 +94,7 @@ void push_wave_tasks(Schedule& s, const std::vector<int64_t>& prow_ptr, int64_t 
 
 }  // namespace
 
-bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
-                  double max_prow_frac, PanelLayout& L) {
-  const int64_t nnz = rp[nrows];
-  L = PanelLayout();
-  L.P = P;
-  // column cuts with about nnz / P nonzeros per panel
+std::vector<int32_t> panel_cuts(const int32_t* ci, int64_t nnz, int64_t ncols, int P) {
   std::vector<int64_t> colcnt(size_t(ncols) + 1, 0);
   for (int64_t e = 0; e < nnz; ++e) colcnt[size_t(ci[e]) + 1]++;
   for (int64_t j = 0; j < ncols; ++j) colcnt[size_t(j) + 1] += colcnt[size_t(j)];
@@ -110,7 +105,28 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
     cut[size_t(p)] = int32_t(std::lower_bound(colcnt.begin(), colcnt.end(), target) - colcnt.begin());
     cut[size_t(p)] = std::max(cut[size_t(p)], cut[size_t(p) - 1]);
   }
-  std::vector<int64_t>().swap(colcnt);
+  return cut;
+}
+
+std::vector<int32_t> hot_column_order(const int32_t* ci, int64_t nnz, int64_t ncols,
+                                      const std::vector<int32_t>& cut) {
+  const int P = int(cut.size()) - 1;
+  std::vector<int64_t> cnt(size_t(ncols), 0);
+  for (int64_t e = 0; e < nnz; ++e) cnt[size_t(ci[e])]++;
+  std::vector<int32_t> order(static_cast<size_t>(ncols));
+  for (int64_t j = 0; j < ncols; ++j) order[size_t(j)] = int32_t(j);
+  for (int p = 0; p < P; ++p)
+    std::stable_sort(order.begin() + cut[size_t(p)], order.begin() + cut[size_t(p) + 1],
+                     [&](int32_t a, int32_t b) { return cnt[size_t(a)] > cnt[size_t(b)]; });
+  return order;
+}
+
+bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
+                  double max_prow_frac, PanelLayout& L, const std::vector<int32_t>* given_cuts) {
+  const int64_t nnz = rp[nrows];
+  L = PanelLayout();
+  L.P = P;
+  const std::vector<int32_t> cut = given_cuts ? *given_cuts : panel_cuts(ci, nnz, ncols, P);
   // panel-row lengths: seg[r * P + p] = nonzeros of row r in panel p
   std::vector<int32_t> seg(size_t(nrows) * size_t(P), 0);
   int64_t nprow = 0;

@@ -16,4 +16,15 @@ std::string validate_lp(int64_t m, int64_t n, int64_t n_eq, const double* c, con
 void transpose_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, const double* v,
                    std::vector<int64_t>& rpT, std::vector<int32_t>& ciT, std::vector<double>& vT);
 
+// Column cuts of the XCD panels: P + 1 offsets splitting columns 0..ncols into ranges of
+// about nnz / P nonzeros each (the same cuts build_panels uses).
+std::vector<int32_t> panel_cuts(const int32_t* ci, int64_t nnz, int64_t ncols, int P);
+
+// A column order that keeps every column inside its range of `cut` and, within each range, puts
+// the columns with the most nonzeros first (ties by index): order[j'] = column at position j'.
+// Gathers from the few dense columns of a skewed matrix then hit a small contiguous slice.
+// The panels of the reordered matrix must then be built with the same cuts.
+std::vector<int32_t> hot_column_order(const int32_t* ci, int64_t nnz, int64_t ncols,
+                                      const std::vector<int32_t>& cut);
+
 }  // namespace pdlp

@@ -62,8 +62,10 @@ struct PanelLayout {
 
 // Builds the layout with P panels; returns false (and leaves `out` unusable) when the panel
 // rows would cost more than `max_prow_frac` of the nonzeros.
+// given_cuts: the P + 1 column cuts to use (nullptr: about nnz / P nonzeros per panel).
 bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
-                  double max_prow_frac, PanelLayout& out);
+                  double max_prow_frac, PanelLayout& out,
+                  const std::vector<int32_t>* given_cuts = nullptr);
 
 // Scalar state of one solve, resident in device memory.  Kernels read it at entry; only the
 // last workgroup of a kernel (after every other workgroup has arrived) writes it.

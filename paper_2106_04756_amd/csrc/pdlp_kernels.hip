@@ -1660,6 +1660,13 @@ __global__ void k_mark_limit(DevState* st) {
   }
 }
 
+// dst[i] = src[idx[i]] for i < len (reordering of n-vectors at the interface).
+__global__ __launch_bounds__(kBlock) void k_gather(const double* __restrict__ src, const int32_t* __restrict__ idx,
+                                                  double* __restrict__ dst, int64_t len) {
+  for (int64_t i = blockIdx.x * int64_t(kBlock) + threadIdx.x; i < len; i += int64_t(gridDim.x) * kBlock)
+    dst[i] = src[idx[i]];
+}
+
 // x = D2 x~ and y = D1 y~ of the returned point (or the current iterate, scaled = 1).
 __global__ __launch_bounds__(kBlock) void k_output(const DevState* st, Bufs B, double* xo, double* yo,
                                                    int which) {

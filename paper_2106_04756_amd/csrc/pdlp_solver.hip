@@ -77,6 +77,12 @@ struct pdlp_solver {
   hipGraph_t graph[2] = {nullptr, nullptr};
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   bool graphs_tried = false;
+  // internal order of the primal variables (empty = the user's order): col_user[j'] is the
+  // user's index of internal column j', col_int its inverse; device copies for the gathers
+  std::vector<int32_t> col_user, col_int;
+  const int32_t* d_col_user = nullptr;
+  const int32_t* d_col_int = nullptr;
+  double* permbuf = nullptr;           // n values of staging for the reordering gathers
   std::vector<hipEvent_t> tev[2];
   double t_ms[2] = {0.0, 0.0};
   int64_t t_cnt[2] = {0, 0};
@@ -171,6 +177,31 @@ int write_output(pdlp_solver* s, void* dst, const void* src_dev, size_t bytes) {
   return 0;
 }
 
+// n values in the solver's column order (device src) to dst in the user's order.
+int write_n(pdlp_solver* s, double* dst, const double* src) {
+  if (!dst) return 0;
+  if (s->col_user.empty()) return write_output(s, dst, src, size_t(s->n) * 8);
+  const int g = int(std::max<int64_t>(1, std::min<int64_t>((s->n + kBlock - 1) / kBlock, s->maxG)));
+  k_gather<<<g, kBlock, 0, s->stream>>>(src, s->d_col_int, s->permbuf, s->n);
+  PDLP_LAUNCH(s);
+  return write_output(s, dst, s->permbuf, size_t(s->n) * 8);
+}
+
+// n values in the user's order (host or device src) into device dst in the solver's order.
+int read_n(pdlp_solver* s, const double* src, double* dst) {
+  const size_t bytes = size_t(s->n) * 8;
+  const hipMemcpyKind kind = is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (s->col_user.empty()) {
+    PDLP_HIP(s, hipMemcpyAsync(dst, src, bytes, kind, s->stream));
+    return 0;
+  }
+  PDLP_HIP(s, hipMemcpyAsync(s->permbuf, src, bytes, kind, s->stream));
+  const int g = int(std::max<int64_t>(1, std::min<int64_t>((s->n + kBlock - 1) / kBlock, s->maxG)));
+  k_gather<<<g, kBlock, 0, s->stream>>>(s->permbuf, s->d_col_user, dst, s->n);
+  PDLP_LAUNCH(s);
+  return 0;
+}
+
 template <class T>
 int upload_vec(pdlp_solver* s, const std::vector<T>& h, const T** out) {
   T* d;
@@ -208,14 +239,15 @@ int upload_tasks(pdlp_solver* s, const Schedule& sc, CsrDev& A) {
 // column panels; *vdev receives the device values (the scaling kernels rewrite them) and
 // *prow_part the panel-row partial buffer (panel mode only).
 int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp, const int32_t* ci,
-                const double* v, CsrDev& A, double** vdev, double** prow_part) {
+                const double* v, CsrDev& A, double** vdev, double** prow_part,
+                const std::vector<int32_t>* cuts = nullptr) {
   int rc;
   const int64_t nnz = rp[nrows];
   const int mode = s->opts.xcd_panels;
   PanelLayout PL;
   bool panel = false;
   if (nnz > 0 && (mode == 1 || (mode < 0 && ncols * 8 > (int64_t(4) << 20))))
-    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : 0.25, PL);
+    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : 0.25, PL, cuts);
   A.nrows_orig = int32_t(nrows);
   if (panel) {
     const int64_t nprow = int64_t(PL.prow_row.size());
@@ -640,6 +672,55 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   s->n_eq = n_eq;
   s->nnz = nnz;
 
+  // internal column order: each XCD panel's columns with the most nonzeros first, so the
+  // gathers of the K~ x products that hit the dense columns stay in a small slice of x
+  const int co = s->opts.column_order;
+  const bool reorder = nnz > 0 && (co == 1 || (co < 0 && s->opts.xcd_panels != 0 &&
+                                               (s->opts.xcd_panels == 1 || n * 8 > (int64_t(4) << 20))));
+  std::vector<int32_t> ci_r, cuts;
+  std::vector<double> c_r, l_r, u_r, v_r;
+  if (reorder) {
+    cuts = panel_cuts(ci, nnz, n, kMaxPanels);     // of the user's order; kept for the panels
+    s->col_user = hot_column_order(ci, nnz, n, cuts);
+    s->col_int.assign(size_t(n), 0);
+    for (int64_t j = 0; j < n; ++j) s->col_int[size_t(s->col_user[size_t(j)])] = int32_t(j);
+    ci_r.resize(static_cast<size_t>(nnz));
+    for (int64_t e = 0; e < nnz; ++e) ci_r[size_t(e)] = s->col_int[size_t(ci[e])];
+    {
+      // each row's entries in the new column order (hot columns of a panel first); the
+      // panel of an entry still never decreases along a row
+      v_r.assign(v, v + nnz);
+      std::vector<std::pair<int32_t, double>> tmp;
+      for (int64_t i = 0; i < m; ++i) {
+        const int64_t a = rp[i], b = rp[i + 1];
+        tmp.clear();
+        for (int64_t e = a; e < b; ++e) tmp.emplace_back(ci_r[size_t(e)], v[e]);
+        std::sort(tmp.begin(), tmp.end());
+        for (int64_t e = a; e < b; ++e) {
+          ci_r[size_t(e)] = tmp[size_t(e - a)].first;
+          v_r[size_t(e)] = tmp[size_t(e - a)].second;
+        }
+      }
+      v = v_r.data();
+    }
+    c_r.resize(size_t(n));
+    l_r.resize(size_t(n));
+    u_r.resize(size_t(n));
+    for (int64_t j = 0; j < n; ++j) {
+      const size_t uj = size_t(s->col_user[size_t(j)]);
+      c_r[size_t(j)] = hc[uj];
+      l_r[size_t(j)] = hl[uj];
+      u_r[size_t(j)] = hu[uj];
+    }
+    ci = ci_r.data();
+    hc = c_r.data();
+    hl = l_r.data();
+    hu = u_r.data();
+    if ((rc = upload_vec(s, s->col_user, &s->d_col_user)) || (rc = upload_vec(s, s->col_int, &s->d_col_int)))
+      return rc;
+    PDLP_HIP(s, s->alloc(&s->permbuf, size_t(n)));
+  }
+
   std::vector<int64_t> rpT;
   std::vector<int32_t> ciT;
   std::vector<double> vT;
@@ -652,7 +733,7 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   s->maxG = std::max(1, ncu * 8);
 
   // the two CSR copies (K~ and K~^T), each in the plain or the XCD-panel layout
-  if ((rc = upload_copy(s, m, n, rp, ci, v, s->K, &s->vK, &s->partPK))) return rc;
+  if ((rc = upload_copy(s, m, n, rp, ci, v, s->K, &s->vK, &s->partPK, reorder ? &cuts : nullptr))) return rc;
   if ((rc = upload_copy(s, n, m, rpT.data(), ciT.data(), vT.data(), s->KT, &s->vKT, &s->partPT))) return rc;
   std::vector<int64_t>().swap(rpT);
   std::vector<int32_t>().swap(ciT);
@@ -916,7 +997,11 @@ int unroll_forward_impl(pdlp_solver* s, const double* c, const double* q, int64_
   U.S = S;
   U.nseg = nseg;
   // c~ = D2 c, q~ = D1 q (the LP's own c, q when null), z0 = (proj_X(0), 0, K~ proj_X(0))
-  if ((rc = stage_in(s, c ? c : s->B.c0, U.gin, n))) return rc;
+  if (c) {
+    if ((rc = read_n(s, c, U.gin))) return rc;
+  } else if ((rc = stage_in(s, s->B.c0, U.gin, n))) {
+    return rc;
+  }
   if ((rc = stage_in(s, q ? q : s->B.q0, U.gin + n, m))) return rc;
   const int gE = s->gE;
   k_unroll_start<<<gE, kBlock, 0, s->stream>>>(U.gin, U.gin + n, s->B.D1, s->B.D2, s->B.l, s->B.u, U.ct,
@@ -930,7 +1015,7 @@ int unroll_forward_impl(pdlp_solver* s, const double* c, const double* q, int64_
   }
   k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.z, s->B.D2, int(n), U.z + n, s->B.D1, int(m), U.out);
   PDLP_LAUNCH(s);
-  if ((rc = write_output(s, x_T, U.out, size_t(n) * 8))) return rc;
+  if ((rc = write_n(s, x_T, U.out))) return rc;
   if ((rc = write_output(s, y_T, U.out + n, size_t(m) * 8))) return rc;
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
   U.ready = true;
@@ -950,7 +1035,7 @@ int unroll_backward_impl(pdlp_solver* s, const double* gx, const double* gy, dou
   const double t0 = now_s();
   const double tau = U.eta / U.omega, sigma = U.eta * U.omega;
   const int gE = s->gE;
-  if (gx && (rc = stage_in(s, gx, U.gin, n))) return rc;
+  if (gx && (rc = read_n(s, gx, U.gin))) return rc;
   if (gy && (rc = stage_in(s, gy, U.gin + n, m))) return rc;
   U.recomputed = 0;
   if (U.nseg == 0) {
@@ -987,7 +1072,7 @@ int unroll_backward_impl(pdlp_solver* s, const double* gx, const double* gy, dou
   U.masks_last = U.nseg == 1;
   k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.cb, s->B.D2, int(n), U.cb + n, s->B.D1, int(m), U.out);
   PDLP_LAUNCH(s);
-  if ((rc = write_output(s, gc, U.out, size_t(n) * 8))) return rc;
+  if ((rc = write_n(s, gc, U.out))) return rc;
   if ((rc = write_output(s, gq, U.out + n, size_t(m) * 8))) return rc;
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
   U.bwd_s = now_s() - t0;
@@ -1018,6 +1103,7 @@ void pdlp_default_options(pdlp_options* o) {
   o->restart_to_current = 1;
   o->power_iters = 200;
   o->use_graphs = 1;
+  o->column_order = -1;
   o->beta_sufficient = 0.1;
   o->beta_necessary = 0.9;
   o->beta_artificial = 0.5;
@@ -1050,7 +1136,8 @@ int pdlp_create(pdlp_solver** out, int64_t m, int64_t n, int64_t n_eq, const dou
       !(o.eps_zero >= 0.0) || !(o.beta_sufficient > 0.0) || !(o.beta_necessary > 0.0) ||
       !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 2 || o.power_iters < 1 ||
       !(o.mp_breaking_factor > 0.0) || !(o.mp_downscaling > 0.0 && o.mp_downscaling < 1.0) ||
-      !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0)) {
+      !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0) || o.column_order < -1 ||
+      o.column_order > 1) {
     g_create_error = "invalid options";
     delete s;
     return PDLP_ERR_INVALID_ARGUMENT;
@@ -1131,7 +1218,7 @@ int pdlp_get(const pdlp_solver* cs, double* x, double* y, double* kkt) {
   if (x || y) {
     k_output<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, s->outbuf, s->outbuf + s->n, 0);
     PDLP_LAUNCH(s);
-    if ((rc = write_output(s, x, s->outbuf, size_t(s->n) * 8))) return rc;
+    if ((rc = write_n(s, x, s->outbuf))) return rc;
     if ((rc = write_output(s, y, s->outbuf + s->n, size_t(s->m) * 8))) return rc;
   }
   if (kkt) {
@@ -1196,6 +1283,13 @@ int pdlp_get_state(const pdlp_solver* cs, double* x, double* y, double* xa, doub
     for (size_t j = 0; j < N; ++j) hsx[j] = hsx[j] + h.w_pending * hx[j];
     for (size_t i = 0; i < M; ++i) hsy[i] = hsy[i] + h.w_pending * hy[i];
   }
+  if (!s->col_user.empty()) {            // to the user's column order
+    std::vector<double> t(N);
+    for (size_t j = 0; j < N; ++j) t[j] = hx[size_t(s->col_int[j])];
+    hx.swap(t);
+    for (size_t j = 0; j < N; ++j) t[j] = hsx[size_t(s->col_int[j])];
+    hsx.swap(t);
+  }
   auto put = [&](double* dst, const double* src, size_t cnt) -> int {
     if (!dst || cnt == 0) return 0;
     if (is_device_ptr(dst)) PDLP_HIP(s, hipMemcpy(dst, src, cnt * 8, hipMemcpyHostToDevice));
@@ -1205,7 +1299,7 @@ int pdlp_get_state(const pdlp_solver* cs, double* x, double* y, double* xa, doub
   if ((rc = put(x, hx.data(), N)) || (rc = put(y, hy.data(), M)) || (rc = put(sx, hsx.data(), N)) ||
       (rc = put(sy, hsy.data(), M)))
     return rc;
-  if ((rc = write_output(s, xa, s->B.XA, N * 8))) return rc;
+  if ((rc = write_n(s, xa, s->B.XA))) return rc;
   if ((rc = write_output(s, ya, s->B.YA, M * 8))) return rc;
   if (out) {
     out->k = h.k;
@@ -1228,7 +1322,7 @@ int pdlp_set_state(pdlp_solver* s, const double* x, const double* y, const doubl
     s->err = "invalid checkpoint scalars";
     return PDLP_ERR_INVALID_ARGUMENT;
   }
-  const size_t N = size_t(s->n), M = size_t(s->m);
+  const size_t M = size_t(s->m);
   auto get = [&](double* dst, const double* src, size_t cnt) -> int {
     if (cnt == 0) return 0;
     const hipMemcpyKind kind = is_device_ptr(src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -1236,8 +1330,8 @@ int pdlp_set_state(pdlp_solver* s, const double* x, const double* y, const doubl
     return 0;
   };
   int rc;
-  if ((rc = get(s->B.X[0], x, N)) || (rc = get(s->B.Y[0], y, M)) || (rc = get(s->B.XA, xa, N)) ||
-      (rc = get(s->B.YA, ya, M)) || (rc = get(s->B.Sx, sx, N)) || (rc = get(s->B.Sy, sy, M)))
+  if ((rc = read_n(s, x, s->B.X[0])) || (rc = get(s->B.Y[0], y, M)) || (rc = read_n(s, xa, s->B.XA)) ||
+      (rc = get(s->B.YA, ya, M)) || (rc = read_n(s, sx, s->B.Sx)) || (rc = get(s->B.Sy, sy, M)))
     return rc;
   k_set_state<<<1, 1, 0, s->stream>>>(s->st, *v);
   PDLP_LAUNCH(s);
@@ -1252,7 +1346,7 @@ int pdlp_get_scaling(const pdlp_solver* cs, double* D1, double* D2) {
   pdlp_solver* s = const_cast<pdlp_solver*>(cs);
   int rc;
   if ((rc = write_output(s, D1, s->B.D1, size_t(s->m) * 8))) return rc;
-  if ((rc = write_output(s, D2, s->B.D2, size_t(s->n) * 8))) return rc;
+  if ((rc = write_n(s, D2, s->B.D2))) return rc;
   return 0;
 }
 
@@ -1262,7 +1356,7 @@ int pdlp_get_iterate(const pdlp_solver* cs, double* xs, double* ys) {
   int rc;
   k_output<<<s->gE, kBlock, 0, s->stream>>>(s->st, s->B, s->outbuf, s->outbuf + s->n, 1);
   PDLP_LAUNCH(s);
-  if ((rc = write_output(s, xs, s->outbuf, size_t(s->n) * 8))) return rc;
+  if ((rc = write_n(s, xs, s->outbuf))) return rc;
   if ((rc = write_output(s, ys, s->outbuf + s->n, size_t(s->m) * 8))) return rc;
   return 0;
 }
@@ -1299,7 +1393,9 @@ int pdlp_get_trace(const pdlp_solver* cs, pdlp_attempt_rec* att, int64_t att_cap
   const int64_t ni = std::min<int64_t>(h.n_iter_log, cs->opts.trace_iters);
   if (n_iter) *n_iter = ni;
   if (ni > 0) {
-    if ((rc = write_output(s, xs, s->B.tx, size_t(ni) * size_t(s->n) * 8))) return rc;
+    if (xs)
+      for (int64_t r = 0; r < ni; ++r)
+        if ((rc = write_n(s, xs + r * s->n, s->B.tx + r * s->n))) return rc;
     if ((rc = write_output(s, ys, s->B.ty, size_t(ni) * size_t(s->m) * 8))) return rc;
   }
   return 0;
@@ -1309,7 +1405,15 @@ int pdlp_spmv(pdlp_solver* s, int transpose, const double* x, double* out) {
   if (!s || !x || !out) return PDLP_ERR_INVALID_ARGUMENT;
   int rc;
   const CsrDev& A = transpose ? s->KT : s->K;
-  if ((rc = launch_spmv(s, A, x, nullptr, 0, out, nullptr, 0, kPredAlways, 0))) return rc;
+  if (s->col_user.empty()) {
+    if ((rc = launch_spmv(s, A, x, nullptr, 0, out, nullptr, 0, kPredAlways, 0))) return rc;
+  } else if (!transpose) {               // x in the user's order -> solver's order (gap scratch)
+    if ((rc = read_n(s, x, s->B.GA[0]))) return rc;
+    if ((rc = launch_spmv(s, A, s->B.GA[0], nullptr, 0, out, nullptr, 0, kPredAlways, 0))) return rc;
+  } else {
+    if ((rc = launch_spmv(s, A, x, nullptr, 0, s->B.GA[0], nullptr, 0, kPredAlways, 0))) return rc;
+    if ((rc = write_n(s, out, s->B.GA[0]))) return rc;
+  }
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
   return 0;
 }

@@ -41,7 +41,8 @@ class Options(ctypes.Structure):
                 ("step_policy", ctypes.c_int32), ("restart_to_current", ctypes.c_int32),
                 ("power_iters", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
                 ("mp_breaking_factor", ctypes.c_double), ("mp_downscaling", ctypes.c_double),
-                ("mp_interpolation", ctypes.c_double)]
+                ("mp_interpolation", ctypes.c_double), ("column_order", ctypes.c_int32),
+                ("reserved2", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -47,8 +47,8 @@ def rel(a, b):
 
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("panels", [0, 1])
-def test_spmv_matches_scipy_on_ragged_shapes(panels):
+@pytest.mark.parametrize("panels,order", [(0, 0), (1, 0), (1, 1)])
+def test_spmv_matches_scipy_on_ragged_shapes(panels, order):
     """Unscaled products (no preconditioning) on every schedule path: lane-group rows of
     every width, one-workgroup rows, split giant rows, empty rows/columns; in the plain row
     layout and in XCD column panels."""
@@ -65,8 +65,8 @@ def test_spmv_matches_scipy_on_ragged_shapes(panels):
                       shape=(m, n))
     K.sort_indices()
     lp = lpgen.from_csr(K, np.ones(n), np.zeros(m), np.zeros(n), np.full(n, 1.0), n_eq=0)
-    say("spmv ragged", m, n, K.nnz, "panels", panels)
-    s = make(lp, ruiz_iters=0, pock_chambolle=0, xcd_panels=panels)
+    say("spmv ragged", m, n, K.nnz, "panels", panels, "column order", order)
+    s = make(lp, ruiz_iters=0, pock_chambolle=0, xcd_panels=panels, column_order=order)
     for trial in range(2):
         x = rng.standard_normal(n)
         y = rng.standard_normal(m)
@@ -135,6 +135,12 @@ def _trajectory_parity(lp, iters=100, opts=None, **kw):
 def test_trajectory_parity_config0():
     """Free-running: the GPU's first 100 iterates against the oracle's, 1e-11 per iterate."""
     _trajectory_parity(lpgen.config0())
+
+
+def test_trajectory_parity_config0_reordered_columns():
+    """The same with the internal column order (dense columns first in each XCD panel): every
+    n-vector of the trace comes back in the user's order."""
+    _trajectory_parity(lpgen.config0(), xcd_panels=1, column_order=1)
 
 
 EPS = np.finfo(np.float64).eps
@@ -206,6 +212,13 @@ def test_replayed_step_parity(maker):
 ])
 def test_replayed_step_parity_xcd_panels(maker):
     _replay_parity(maker(), xcd_panels=1)
+
+
+@pytest.mark.parametrize("maker", [lpgen.config0, lambda: lpgen.large_plain(21, 400, 900)])
+def test_replayed_step_parity_reordered_columns(maker):
+    """Checkpoints in and out (x, anchor, weighted sums) cross the interface in the user's
+    order while the solver keeps its own column order."""
+    _replay_parity(maker(), xcd_panels=1, column_order=1)
 
 
 # the paper's ablation switches (Appendix C): same option on both sides

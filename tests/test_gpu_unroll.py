@@ -55,16 +55,16 @@ def gpu_grad(s, lp, x_tgt, T, segment, eta, omega, gy=None):
     return x, y, gc, gq
 
 
-@pytest.mark.parametrize("segment", [0, 7])
-def test_unroll_matches_oracle_small(segment):
+@pytest.mark.parametrize("segment,kw", [(0, {}), (7, {}), (7, dict(xcd_panels=1, column_order=1))])
+def test_unroll_matches_oracle_small(segment, kw):
     lp = lpgen.config0()
     rng = np.random.default_rng(40)
     x_tgt = rng.uniform(0, 5, lp.n)
     gy = rng.standard_normal(lp.m)
     T = 60
-    say("unroll small", lp.name, "T", T, "segment", segment)
+    say("unroll small", lp.name, "T", T, "segment", segment, kw)
     ref = oracle_case(lp, x_tgt, T, gy)
-    with P.Solver.from_lp(lp) as s:
+    with P.Solver.from_lp(lp, **kw) as s:
         x, y, gc, gq = gpu_grad(s, lp, x_tgt, T, segment, ref["eta"], ref["omega"], gy)
         info = s.unroll_info()
     close(x, ref["x_T"], 1e-10)
