@@ -93,7 +93,10 @@ typedef struct pdlp_options {
                                     order, 1 within each panel's column range the columns with
                                     the most nonzeros first.  Invisible at this interface:
                                     every n-vector in or out is in the user's order.           */
-  int32_t reserved2;
+  int32_t pw_power_of_two;       /* with adaptive_restarts = 0: the "no restart" mode of
+                                    Appendix C, which still updates the primal weight
+                                    (Algorithm 3, from the current iterate and the previous
+                                    update's) at k = 2, 4, 8, ...: 0 (off)                    */
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

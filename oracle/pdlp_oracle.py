@@ -52,6 +52,8 @@ class Options:
     mp_downscaling: float = 0.5
     mp_interpolation: float = 0.4
     restarts: bool = True                # Section 3.2 adaptive restarts
+    pw_power_of_two: bool = False        # with restarts off: Appendix C "no restart" mode, the
+                                         # primal weight still updated at k = 2, 4, 8, ... (R10)
     restart_to_current: bool = True      # False: the candidate is always the average
                                          # (Appendix C "adaptive restart (theory)")
     beta_sufficient: float = 0.1         # reading R4: the printed 0.9 / 0.1 are transposed
@@ -458,6 +460,7 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
     mu_prev = math.inf
     mu_anchor = math.inf
     mp_theta = 1.0                              # Malitsky-Pock theta_k (1 at the start, R8)
+    pw_done = 0                                 # k of the last "no restart" weight update
     kty = KtT @ y                               # K~^T y of the current y
 
     def finish(status, xs, ys):
@@ -470,6 +473,17 @@ def solve(c, K, q, l, u, n_eq, tol=1e-8, iter_limit=100000, opts: Options | None
         return finish(OPTIMAL, x, y)
 
     while True:
+        if k >= 2 and (k & (k - 1)) == 0 and k != pw_done and not opts.restarts and opts.pw_power_of_two:
+            # "no restart" mode (Appendix C, reading R10): at k = 2^j the weight is updated as an
+            # artificial restart would, from the distance of the current iterate to the iterate
+            # of the previous update, and that anchor moves; iterate and averages stay
+            pw_done = k
+            if opts.primal_weight_update:
+                omega = primal_weight_update(float(np.linalg.norm(x - xa)), float(np.linalg.norm(y - ya)),
+                                             omega, opts.theta, opts.eps_zero)
+            xa, ya = x.copy(), y.copy()
+            n_outer += 1
+            mp_theta = 1.0
         if tr is not None and k <= record_states and (not tr.states or tr.states[-1]["k"] != k):
             tr.states.append(dict(k=k, t=t, n_outer=n_outer, x=x.copy(), y=y.copy(), xa=xa.copy(),
                                   ya=ya.copy(), Sx=Sx.copy(), Sy=Sy.copy(), Seta=Seta,

@@ -121,6 +121,8 @@ struct DevState {
   int32_t mp_on;
   int32_t mp_stage;       // 0: the next attempt starts an iteration; 1: it retries the dual trial
   int32_t mp_commit;      // the last trial was accepted: K~^T y^ is to become K~^T y
+  int32_t pw_pow2;        // restarts off, primal weight updated at k = 2, 4, 8, ...
+  int32_t pw_event;       // the pending check is such an update only
   int32_t pad1;
   double mp_theta;        // theta_k = eta_{k-1} / eta_k
   double mp_bf, mp_df, mp_ic;   // breaking factor, downscaling factor, interpolation coefficient

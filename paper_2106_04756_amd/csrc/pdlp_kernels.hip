@@ -510,6 +510,16 @@ struct DualEpi {
   }
 };
 
+// "No restart" mode (restarts off; Appendix C): the primal weight is still updated when an
+// artificial restart would have fired, i.e. at k = 2, 4, 8, ...  Such a k gets a check of its
+// own, which only updates the weight and moves the anchor.
+__device__ __forceinline__ void mark_weight_event(DevState& W) {
+  if (W.pw_pow2 && W.k >= 2 && (W.k & (W.k - 1)) == 0) {
+    W.check_pending = 1;
+    W.pw_event = 1;
+  }
+}
+
 // Algorithm 2 decision for one attempt: the largest step Eq. (5) allows, the next proposal,
 // accept or retry, and the bookkeeping of Algorithm 1.  One thread.
 __device__ void attempt_decide(DevState& W, double dx2, double dy2, double cross, pdlp_attempt_rec* att) {
@@ -554,6 +564,7 @@ __device__ void attempt_decide(DevState& W, double dx2, double dy2, double cross
     W.kty_valid = 0;
     W.retries = 0;
     if (W.k % W.check_every == 0) W.check_pending = 1;
+    mark_weight_event(W);
     if (W.k <= W.trace_iters) W.snap_pending = 1;
   } else {
     W.eta = eta_next;
@@ -791,6 +802,7 @@ __device__ void mp_decide(DevState& W, double dy2, double kdy2, pdlp_attempt_rec
     W.t += 1;
     W.retries = 0;
     if (W.k % W.check_every == 0) W.check_pending = 1;
+    mark_weight_event(W);
     if (W.k <= W.trace_iters) W.snap_pending = 1;
   } else {
     W.eta = W.mp_df * eta;
@@ -1271,6 +1283,15 @@ __device__ __forceinline__ bool kkt_point_is_average(const DevState& S, int mode
 //         (i)-(iii)) and the primal-weight update (Algorithm 3);
 // mode 1: the current point before the first step (termination only);
 // mode 2: the returned point after the solve stopped.
+// Algorithm 3 from the current iterate's distance to the anchor (t[5], t[6] of the KKT pass).
+__device__ __forceinline__ void weight_event_update(DevState& W, const double (&t)[7]) {
+  const double dxn = sqrt(t[5]), dyn = sqrt(t[6]);
+  W.dx_norm = dxn;
+  W.dy_norm = dyn;
+  if (W.pw_on && dxn > W.eps_zero && dyn > W.eps_zero)
+    W.omega = exp(W.theta * log(dyn / dxn) + (1.0 - W.theta) * log(W.omega));
+}
+
 __device__ void kkt_decide(DevState& W, int mode, const double (&t)[7], pdlp_check_rec* chk) {
   const double pobj = t[0], dobj = t[1] + t[2];
   const double e_gap = fabs(dobj - pobj) / (1.0 + fabs(dobj) + fabs(pobj));
@@ -1292,6 +1313,13 @@ __device__ void kkt_decide(DevState& W, int mode, const double (&t)[7], pdlp_che
   }
   if (mode == 2) {
     if (W.status == PDLP_NUMERICAL_ERROR && conv) W.status = PDLP_OPTIMAL;
+    return;
+  }
+  if (W.pw_event && W.k % W.check_every != 0) {
+    // only a weight update of the "no restart" mode: no termination test, no record
+    weight_event_update(W, t);
+    W.mask = 0;
+    W.restart = 0;
     return;
   }
   W.checks += 1;
@@ -1338,6 +1366,9 @@ __device__ void kkt_decide(DevState& W, int mode, const double (&t)[7], pdlp_che
     rec->mask = mask;
     rec->omega_after = W.omega;
   }
+  // a regular check at k = 2^j (check_every dividing it): the "no restart" weight update
+  // follows the check, as it precedes the next step
+  if (W.pw_event) weight_event_update(W, t);
 }
 
 // Restart (Algorithm 1): z <- z_c, anchor <- z_c, sums cleared; then close the check.
@@ -1373,6 +1404,14 @@ __device__ void apply_decide(DevState& W) {
     W.mu_prev = INFINITY;
     W.kty_valid = 1;
     if (W.mp_on) {                       // the line search starts afresh: theta = 1
+      W.mp_theta = 1.0;
+      W.mp_commit = 0;
+      mp_first_candidate(W);
+    }
+  } else if (W.pw_event) {              // anchor moved; iterate, averages and t stay
+    W.n_outer += 1;
+    W.pw_event = 0;
+    if (W.mp_on) {
       W.mp_theta = 1.0;
       W.mp_commit = 0;
       mp_first_candidate(W);
@@ -1519,6 +1558,11 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(DevState* st, Bufs B, un
   if (S.restart) {
     const bool avg = S.use_avg != 0;
     PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) apply_elem(B, P, avg, idx);
+  } else if (S.pw_event) {
+    PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) {
+      if (idx < B.n) B.XA[idx] = pick(B.X, P)[idx];
+      else B.YA[idx - B.n] = pick(B.Y, P)[idx - B.n];
+    }
   }
   if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
@@ -1602,6 +1646,7 @@ __global__ void k_set_state(DevState* st, pdlp_state v) {
     W.use_avg = 0;
     W.out_avg = 0;
     W.snap_pending = 0;
+    W.pw_event = 0;
     if (W.mp_on) {
       W.mp_theta = 1.0;
       W.mp_commit = 0;

@@ -820,6 +820,7 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   h.restarts_on = s->opts.adaptive_restarts;
   h.constant_step = s->opts.step_policy == 1;
   h.mp_on = s->opts.step_policy == 2;
+  h.pw_pow2 = s->opts.pw_power_of_two;
   h.mp_theta = 1.0;
   h.mp_bf = s->opts.mp_breaking_factor;
   h.mp_df = s->opts.mp_downscaling;
@@ -1137,7 +1138,7 @@ int pdlp_create(pdlp_solver** out, int64_t m, int64_t n, int64_t n_eq, const dou
       !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 2 || o.power_iters < 1 ||
       !(o.mp_breaking_factor > 0.0) || !(o.mp_downscaling > 0.0 && o.mp_downscaling < 1.0) ||
       !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0) || o.column_order < -1 ||
-      o.column_order > 1) {
+      o.column_order > 1 || (o.pw_power_of_two != 0 && (o.pw_power_of_two != 1 || o.adaptive_restarts))) {
     g_create_error = "invalid options";
     delete s;
     return PDLP_ERR_INVALID_ARGUMENT;

@@ -231,6 +231,8 @@ ABLATIONS = {
                      dict(primal_weight_update=0, primal_importance=0.1)),
     "no_scaling": (dict(ruiz_iters=0, pock_chambolle=False), dict(ruiz_iters=0, pock_chambolle=0)),
     "ruiz_only": (dict(pock_chambolle=False), dict(pock_chambolle=0)),
+    "no_restart_weight_at_2j": (dict(restarts=False, pw_power_of_two=True),
+                                dict(adaptive_restarts=0, pw_power_of_two=1)),
 }
 
 

@@ -159,6 +159,10 @@ def test_create_rejects_bad_sizes_and_options():
         P.Solver(lp.m, 0, lp.n_eq, lp.c, lp.row_ptr, lp.col_idx, lp.val, lp.q, lp.l, lp.u)
     with pytest.raises(P.PdlpError, match="options"):
         _create(lp, check_every=0)
+    with pytest.raises(P.PdlpError, match="options"):      # needs restarts off
+        _create(lp, pw_power_of_two=1)
+    with pytest.raises(P.PdlpError, match="options"):
+        _create(lp, step_policy=3)
 
 
 def test_schedule_rounds_follow_matrix_size():

@@ -548,3 +548,21 @@ def test_malitsky_pock_solves_to_highs_objective():
         elif abs(eta - eta_bar) > 1e-12 * eta:
             assert acc == (eta < eta_bar)
     assert rejected > 0          # the line search did shrink steps on this LP
+
+
+def test_no_restart_mode_updates_weight_at_powers_of_two():
+    # Appendix C "no restart": restarts off, primal weight still updated at k = 2, 4, 8, ...
+    lp = lpgen.tiny_plain(4, 60, 140, 24, 4)
+    opts = O.Options(restarts=False, pw_power_of_two=True)
+    r = O.solve_lp(lp, tol=1e-30, iter_limit=300, opts=opts, record_states=300)
+    states = r.trace.states
+    changed = [s["k"] for a, s in zip(states, states[1:]) if s["omega"] != a["omega"]]
+    assert changed == [2, 4, 8, 16, 32, 64, 128, 256]
+    # the anchor is the iterate of the previous update; iterates and averages are not reset
+    for st in states:
+        if st["k"] in (64, 128):
+            assert np.array_equal(st["xa"], st["x"]) and st["t"] == st["k"]
+    assert r.restarts == 8
+    # without the mode, restarts off keeps the initial weight
+    r0 = O.solve_lp(lp, tol=1e-30, iter_limit=300, opts=O.Options(restarts=False), record_states=300)
+    assert len({s["omega"] for s in r0.trace.states}) == 1
