@@ -24,6 +24,7 @@ struct BatchInst {
 
 struct BatchDev {
   const BatchInst* inst;
+  const int32_t* order;  // member run by workgroup b (largest members first)
   const int64_t* rp;
   const int32_t* ci;
   double* v;
@@ -185,7 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
                                                         int64_t iter_limit, int ruiz_iters,
                                                         int pock_chambolle, double primal_importance) {
   __shared__ DevState S;
-  const BatchInst I = D.inst[blockIdx.x];
+  const int mb = D.order[blockIdx.x];
+  const BatchInst I = D.inst[mb];
   const Bufs B = batch_bufs(D, I);
   const LocalCsr K{D.rp + I.rp, D.ci + I.nz, D.v + I.nz, I.m};
   const LocalCsr KT{D.rpT + I.rpT, D.ciT + I.nz, D.vT + I.nz, I.n};
@@ -379,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
     }
     batch_kkt(S, B, 2);
   }
-  if (threadIdx.x == 0) D.out_state[blockIdx.x] = S;
+  if (threadIdx.x == 0) D.out_state[mb] = S;
 }
 
 // x = D2 x~, y = D1 y~ of every member's returned point into packed outputs.

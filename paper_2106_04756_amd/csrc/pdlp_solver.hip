@@ -1649,6 +1649,20 @@ int batch_create_impl(pdlp_batch* b, int64_t count, const int64_t* hm, const int
       (rc = batch_upload(b, hu, size_t(tn), &D.u0)) || (rc = batch_upload(b, hq, size_t(tm), &D.q0)))
     return rc;
   D.inst = dinst;
+  {
+    // workgroup order: members with the most nonzeros first (ties by index), so the longest
+    // solves start early and the small ones fill in behind them
+    std::vector<int32_t> order(static_cast<size_t>(count));
+    for (int64_t k = 0; k < count; ++k) order[size_t(k)] = int32_t(k);
+    auto nz_of = [&](int32_t k) {
+      const BatchInst& I = b->inst[size_t(k)];
+      return rp[I.rp + I.m];
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return nz_of(a) > nz_of(c); });
+    int32_t* dorder;
+    if ((rc = batch_upload(b, order.data(), order.size(), &dorder))) return rc;
+    D.order = dorder;
+  }
   D.rp = drp;
   D.rpT = drpT;
   D.ci = dci;
