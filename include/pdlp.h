@@ -314,6 +314,8 @@ int pdlp_get_state(const pdlp_solver *s, double *x, double *y, double *xa, doubl
  * pdlp_set_state - resume Algorithm 1 from a checkpoint with the layout of pdlp_get_state
  * (all six vectors and st are required).  The next pdlp_solve continues from it without a
  * new termination check at its start.  Used for warm starts and for replaying single steps.
+ * Under the Malitsky-Pock policy the line search resumes with theta = 1 and eta_hat as its
+ * last accepted step.
  */
 int pdlp_set_state(pdlp_solver *s, const double *x, const double *y, const double *xa,
                    const double *ya, const double *sx, const double *sy, const pdlp_state *st);
