@@ -37,11 +37,10 @@ STEP_SOURCES = ["pdlp_kernels.hip", "pdlp_solver.hip", "pdlp_device.h", "pdlp_in
 
 
 def kernel_sources_digest():
-    """sha256 over the sources of the timed step kernels and the C header (names and contents)."""
+    """sha256 over the sources of the timed step kernels (names and contents)."""
     import hashlib
     h = hashlib.sha256()
-    files = [os.path.join(ROOT, "paper_2106_04756_amd", "csrc", f) for f in STEP_SOURCES]
-    for f in files + [os.path.join(ROOT, "include", "pdlp.h")]:
+    for f in [os.path.join(ROOT, "paper_2106_04756_amd", "csrc", f) for f in STEP_SOURCES]:
         h.update(os.path.relpath(f, ROOT).encode())
         with open(f, "rb") as fh:
             h.update(fh.read())
