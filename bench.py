@@ -166,6 +166,83 @@ def bench_unroll(P, lpgen, T=500, segment=50, reps=5):
             "oracle_adjoint_ms": 1e3 * (t2 - t1), "oracle_cores": 1}
 
 
+def measure_steps(P, torch, lp, W, K):
+    """Warm up W accepted steps, then time K more of Algorithm 1 (HIP events around every step
+    kernel) and account the algorithmic bytes of the timed step kernels.  Returns (dict, solver)."""
+    t = time.time()
+    s = P.Solver.from_lp(lp, time_kernels=1)
+    info = s.info()
+    log(f"created solver in {time.time() - t:.1f}s (library create {info['create_seconds']:.1f}s)")
+    st = s.solve(1e-8, W)
+    log(f"warmup {W} steps: status {P.STATUS_NAMES[st]}")
+    s.reset_kernel_times()
+    i0 = s.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.solve(1e-8, W + K)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    info = s.info()
+    steps = info["iterations"] - i0["iterations"]
+    dt = t1 - t0
+    log(f"timed {steps} steps in {dt:.3f}s: status {P.STATUS_NAMES[st]}, attempts {info['attempts']}, "
+        f"restarts {info['restarts']}, kkt {info['kkt'][3]:.3e}")
+    # Algorithmic bytes of the timed step kernels.  The primal step skips its K~^T y product
+    # when y is unchanged since that product was last formed (after a rejected attempt, and
+    # after a check, which forms it), and a slot whose attempt does not run (a check pending)
+    # does nothing; so count the products from the solver's counters: each check forms two
+    # K~^T products (of the average and of the current y) and one K~ product.
+    times, counts = s.kernel_times()
+    m, n, nnz = lp.m, lp.n, lp.nnz
+    d_att = info["attempts"] - i0["attempts"]
+    d_chk = info["checks"] - i0["checks"]
+    prim_products = (info["spmv_KT"] - i0["spmv_KT"]) - 2 * d_chk
+    dual_products = (info["spmv_K"] - i0["spmv_K"]) - d_chk
+    bytes_primal = 8.0 * (n + 1) + 12.0 * nnz + 8.0 * m + 64.0 * n     # K~^T y, then 8 n-vectors
+    bytes_primal_epi = 64.0 * n                                         # the same without the product
+    bytes_dual = 8.0 * (m + 1) + 12.0 * nnz + 8.0 * n + 56.0 * m        # K~ x', then 7 m-vectors
+    total_bytes = [prim_products * bytes_primal + (d_att - prim_products) * bytes_primal_epi,
+                   dual_products * bytes_dual]
+    dom = 0 if times[0] >= times[1] else 1
+    name = ["primal step: K~^T y product fused with the primal update (k_panel_rows<1> + k_primal_combine "
+            "in XCD-panel mode, else k_primal)",
+            "dual step: K~ x' product fused with the dual update and the step rule (k_panel_rows<0> + "
+            "k_dual_combine in XCD-panel mode, else k_dual)"][dom]
+    avg_ms = times[dom] / counts[dom]
+    bpl = total_bytes[dom] / counts[dom]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            "avg_launch_ms": avg_ms, "launches": int(counts[dom]),
+            "products": int([prim_products, dual_products][dom]), "attempts": int(d_att),
+            "algorithmic_bytes_per_launch": bpl, "slot": ["primal", "dual"][dom]}
+    return ({"steps_taken": steps, "seconds": dt, "roofline": roof,
+             "step_gbs_algorithmic": info["step_bytes"] * steps / dt / 1e9,
+             "step_avg_ms": {"primal": times[0] / counts[0], "dual": times[1] / counts[1]},
+             "algorithmic_bytes_per_slot": {"primal": total_bytes[0] / counts[0],
+                                            "dual": total_bytes[1] / counts[1]}}, s)
+
+
+def measure_copy_gbs(torch, nbytes=2 << 30, reps=10):
+    """Device-to-device copy bandwidth (bytes read + written per second) on this GPU."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    log(f"device copy: {gbs:.0f} GB/s (read + write)")
+    return gbs
+
+
 def calibrate_copy(nbytes=1 << 30):
     """A plain device copy of known size, for scaling the HBM byte counters."""
     import torch
@@ -209,54 +286,16 @@ def main():
     t = time.time()
     lp = lpgen.config1(args.seed)
     log(f"generated {lp.name}: m={lp.m} n={lp.n} nnz={lp.nnz} in {time.time() - t:.1f}s")
-    t = time.time()
-    s = P.Solver.from_lp(lp, time_kernels=1)
-    info = s.info()
-    log(f"created solver in {time.time() - t:.1f}s (library create {info['create_seconds']:.1f}s)")
-
     W, K = args.warmup, args.steps
-    st = s.solve(1e-8, W)
-    log(f"warmup {W} steps: status {P.STATUS_NAMES[st]}")
-    s.reset_kernel_times()
-    i0 = s.info()
-    k0 = i0["iterations"]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = s.solve(1e-8, W + K)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    info = s.info()
-    steps = info["iterations"] - k0
-    dt = t1 - t0
-    log(f"timed {steps} steps in {dt:.3f}s: status {P.STATUS_NAMES[st]}, attempts {info['attempts']}, "
-        f"restarts {info['restarts']}, kkt {info['kkt'][3]:.3e}")
-
-    # Algorithmic bytes of the timed step kernels.  The primal step skips its K~^T y product
-    # when y is unchanged since that product was last formed (after a rejected attempt, and
-    # after a check, which forms it), and a slot whose attempt does not run (a check pending)
-    # does nothing; so count the products from the solver's counters: each check forms two
-    # K~^T products (of the average and of the current y) and one K~ product.
-    times, counts = s.kernel_times()
+    r, s = measure_steps(P, torch, lp, W, K)
+    steps, dt = r["steps_taken"], r["seconds"]
     m, n, nnz = lp.m, lp.n, lp.nnz
-    d_att = info["attempts"] - i0["attempts"]
-    d_chk = info["checks"] - i0["checks"]
-    prim_products = (info["spmv_KT"] - i0["spmv_KT"]) - 2 * d_chk
-    dual_products = (info["spmv_K"] - i0["spmv_K"]) - d_chk
-    bytes_primal = 8.0 * (n + 1) + 12.0 * nnz + 8.0 * m + 64.0 * n     # K~^T y, then 8 n-vectors
-    bytes_primal_epi = 64.0 * n                                         # the same without the product
-    bytes_dual = 8.0 * (m + 1) + 12.0 * nnz + 8.0 * n + 56.0 * m        # K~ x', then 7 m-vectors
-    total_bytes = [prim_products * bytes_primal + (d_att - prim_products) * bytes_primal_epi,
-                   dual_products * bytes_dual]
-    dom = 0 if times[0] >= times[1] else 1
-    name = ["primal step: K~^T y product fused with the primal update (k_panel_rows<1> + k_primal_combine "
-            "in XCD-panel mode, else k_primal)",
-            "dual step: K~ x' product fused with the dual update and the step rule (k_panel_rows<0> + "
-            "k_dual_combine in XCD-panel mode, else k_dual)"][dom]
-    avg_ms = times[dom] / counts[dom]
-    bpl = total_bytes[dom] / counts[dom]
-    achieved = bpl / (avg_ms * 1e-3) / 1e9
-    step_gbs = info["step_bytes"] * steps / dt / 1e9
     traffic = profiled_traffic(K, W)
+    roof = r["roofline"]
+    roof["traffic"] = (traffic or {}).get(roof.pop("slot"))
+    copy_gbs = measure_copy_gbs(torch)
+    roof["measured_copy_gbs"] = copy_gbs
+    roof["frac_of_measured_copy"] = roof["achieved"] / copy_gbs
     out = {
         "metric": "PDHG iters/s",
         "value": steps / dt,
@@ -273,17 +312,23 @@ def main():
         "config": {"workload": f"large plain LP m={m} n={n} nnz={nnz} (Zipf(1.5) column counts, "
                                f"30% equality rows, mixed bounds), seed {args.seed}",
                    "tol": 1e-8, "steps_taken": steps},
-        "roofline": {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (traffic or {}).get(["primal", "dual"][dom]),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
-                     "avg_launch_ms": avg_ms, "launches": int(counts[dom]),
-                     "products": int([prim_products, dual_products][dom]), "attempts": int(d_att),
-                     "algorithmic_bytes_per_launch": bpl},
-        "step_gbs_algorithmic": step_gbs,
-        "step_avg_ms": {"primal": times[0] / counts[0], "dual": times[1] / counts[1]},
-        "algorithmic_bytes_per_slot": {"primal": total_bytes[0] / counts[0], "dual": total_bytes[1] / counts[1]},
+        "roofline": roof,
+        "step_gbs_algorithmic": r["step_gbs_algorithmic"],
+        "step_avg_ms": r["step_avg_ms"],
+        "algorithmic_bytes_per_slot": r["algorithmic_bytes_per_slot"],
     }
+    s.close()
+    # the same LP at its stated size (column counts truncated to [1, 190], nnz ~2.1e7)
+    lpb = lpgen.config1b(args.seed)
+    log(f"generated {lpb.name}: nnz={lpb.nnz}")
+    rb, sb = measure_steps(P, torch, lpb, W, K)
+    sb.close()
+    rb["roofline"].pop("slot")
+    out["config1b"] = {"workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
+                                   f"counts truncated to [1,190]), seed {args.seed}",
+                       "iters_per_s": rb["steps_taken"] / rb["seconds"], "steps": rb["steps_taken"],
+                       "roofline": rb["roofline"], "step_gbs_algorithmic": rb["step_gbs_algorithmic"]}
+    log(f"config1b: {out['config1b']['iters_per_s']:.1f} iters/s, {rb['roofline']['frac'] * 100:.1f}% of HBM peak")
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
     tiny = lpgen.config0()
     st0 = P.Solver.from_lp(tiny)

@@ -66,7 +66,7 @@ typedef struct pdlp_options {
   int32_t time_kernels;          /* time every primal/dual step kernel with HIP events: 0    */
   int32_t xcd_panels;            /* XCD column panels for the products: -1 automatic (default:
                                     on for a copy whose gathered vector exceeds 4 MiB and whose
-                                    panel rows stay below a quarter of its nonzeros), 0 off,
+                                    panel rows stay below 0.4 of its nonzeros), 0 off,
                                     1 on whenever the copy has at least one nonzero            */
   double beta_sufficient;        /* restart criterion (i):  0.1 (see the design notes)        */
   double beta_necessary;         /* restart criterion (ii): 0.9                               */

@@ -14,6 +14,11 @@ constexpr int kRounds = 4;             // rows per lane group in one wavefront t
 constexpr int kFillWaves = 8192;       // wavefronts of a full grid: 256 CUs x 8 workgroups x 4
 constexpr int kVectorMax = 16384;      // longest row one workgroup reduces alone
 constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
+// Automatic panel mode keeps a copy in panels while its panel rows stay below this fraction of
+// its nonzeros (each panel row costs an offset, a partial and a combine read, 28 bytes against
+// 12 per nonzero; on a 1e6 x 2e6 LP with 2.1e7 nonzeros, ratios 0.35 / 0.29, panels still
+// gave +28%).
+constexpr double kPanelRowFrac = 0.4;
 constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per XCD of an MI355X)
 
 enum DescKind : int32_t { kWaveRows = 0, kVector = 1, kSplit = 2 };

@@ -247,7 +247,7 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
   PanelLayout PL;
   bool panel = false;
   if (nnz > 0 && (mode == 1 || (mode < 0 && ncols * 8 > (int64_t(4) << 20))))
-    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : 0.25, PL, cuts);
+    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts);
   A.nrows_orig = int32_t(nrows);
   if (panel) {
     const int64_t nprow = int64_t(PL.prow_row.size());

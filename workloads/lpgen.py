@@ -167,13 +167,24 @@ def config0(seed: int = 0) -> LP:
 
 def large_plain(seed: int = 1, m: int = 1_000_000, n: int = 2_000_000, eq_frac: float = 0.3,
                 zipf_a: float = 1.5, max_col: int = 2000, big_frac: float = 0.01,
-                name="large plain LP") -> LP:
+                name="large plain LP", truncate: bool = False) -> LP:
     """Large plain LP: column nonzero counts min(Zipf(a), max_col) at distinct uniform rows,
     N(0,1) values with big_frac of the columns multiplied by 1e3, the last eq_frac of the rows
     equalities, mixed column bounds (50% [0,inf), 30% [l,u] with l~U[-5,0], u~U[0,5], 20% free).
-    x0: U[l,u] on boxed, U[0,5] on [0,inf), U[-5,5] on free columns.  s = 0 on free columns."""
+    x0: U[l,u] on boxed, U[0,5] on [0,inf), U[-5,5] on free columns.  s = 0 on free columns.
+    truncate=True draws the counts from Zipf(a) conditioned on <= max_col (redrawing larger
+    values) instead of clipping them."""
     rng = np.random.default_rng(seed)
-    counts = np.minimum(rng.zipf(zipf_a, size=n), min(max_col, m)).astype(np.int64)
+    if truncate:
+        counts = rng.zipf(zipf_a, size=n)
+        while True:
+            bad = counts > max_col
+            if not bad.any():
+                break
+            counts[bad] = rng.zipf(zipf_a, size=int(bad.sum()))
+        counts = np.minimum(counts, m).astype(np.int64)
+    else:
+        counts = np.minimum(rng.zipf(zipf_a, size=n), min(max_col, m)).astype(np.int64)
     key = _distinct_rows_per_column(rng, counts, m)
     vals = rng.standard_normal(key.shape[0])
     big = rng.choice(n, size=int(round(big_frac * n)), replace=False)
@@ -206,6 +217,13 @@ def large_plain(seed: int = 1, m: int = 1_000_000, n: int = 2_000_000, eq_frac: 
 def config1(seed: int = 1) -> LP:
     """Large plain LP m=1e6, n=2e6, Zipf(1.5) column counts clipped to [1,2000] (nnz ~1.36e8)."""
     return large_plain(seed, name="large plain LP m=1e6 n=2e6 Zipf(1.5) columns")
+
+
+def config1b(seed: int = 1) -> LP:
+    """The large plain LP at its stated size: as config1, with the column counts Zipf(1.5)
+    truncated to [1, 190] (mean ~10.6, nnz ~2.1e7)."""
+    return large_plain(seed, max_col=190, truncate=True,
+                       name="large plain LP m=1e6 n=2e6 Zipf(1.5) columns truncated to [1,190]")
 
 
 def preferential_attachment_graph(seed: int, n_nodes: int, out_deg: int = 8):
