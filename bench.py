@@ -133,7 +133,7 @@ def bench_unroll(P, lpgen, T=500, segment=50, reps=5):
     oracle's NumPy forward + reverse pass timed once beside it (1 thread)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
-    lp, x_tgt = lpgen.config4()
+    lp, x_tgt = lpgen.unroll_lp()
     s = P.Solver.from_lp(lp)
     res = {}
     for seg in (segment, 0):
@@ -284,7 +284,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t = time.time()
-    lp = lpgen.config1(args.seed)
+    lp = lpgen.large_lp(args.seed)
     log(f"generated {lp.name}: m={lp.m} n={lp.n} nnz={lp.nnz} in {time.time() - t:.1f}s")
     W, K = args.warmup, args.steps
     r, s = measure_steps(P, torch, lp, W, K)
@@ -319,18 +319,18 @@ def main():
     }
     s.close()
     # the same LP at its stated size (column counts truncated to [1, 190], nnz ~2.1e7)
-    lpb = lpgen.config1b(args.seed)
+    lpb = lpgen.large_lp_truncated(args.seed)
     log(f"generated {lpb.name}: nnz={lpb.nnz}")
     rb, sb = measure_steps(P, torch, lpb, W, K)
     sb.close()
     rb["roofline"].pop("slot")
-    out["config1b"] = {"workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
+    out["large_lp_truncated"] = {"workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
                                    f"counts truncated to [1,190]), seed {args.seed}",
                        "iters_per_s": rb["steps_taken"] / rb["seconds"], "steps": rb["steps_taken"],
                        "roofline": rb["roofline"], "step_gbs_algorithmic": rb["step_gbs_algorithmic"]}
-    log(f"config1b: {out['config1b']['iters_per_s']:.1f} iters/s, {rb['roofline']['frac'] * 100:.1f}% of HBM peak")
+    log(f"large_lp_truncated: {out['large_lp_truncated']['iters_per_s']:.1f} iters/s, {rb['roofline']['frac'] * 100:.1f}% of HBM peak")
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
-    tiny = lpgen.config0()
+    tiny = lpgen.tiny_lp()
     st0 = P.Solver.from_lp(tiny)
     st0.solve(1e-8, 1)          # first launches / module load outside the timing
     st0.close()

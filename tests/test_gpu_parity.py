@@ -84,7 +84,7 @@ def test_spmv_matches_scipy_on_ragged_shapes(panels, order):
 
 @pytest.mark.parametrize("panels", [0, 1])
 def test_preconditioning_matches_oracle(panels):
-    for lp in (lpgen.config0(), lpgen.large_plain(11, 2000, 4000), lpgen.pagerank_lp(2, 30000)):
+    for lp in (lpgen.tiny_lp(), lpgen.large_plain(11, 2000, 4000), lpgen.pagerank_lp(2, 30000)):
         say("scaling", lp.name, lp.m, lp.n, lp.nnz, "panels", panels)
         s = make(lp, xcd_panels=panels)
         D1, D2 = s.scaling()
@@ -132,15 +132,15 @@ def _trajectory_parity(lp, iters=100, opts=None, **kw):
     return worst
 
 
-def test_trajectory_parity_config0():
+def test_trajectory_parity_tiny_lp():
     """Free-running: the GPU's first 100 iterates against the oracle's, 1e-11 per iterate."""
-    _trajectory_parity(lpgen.config0())
+    _trajectory_parity(lpgen.tiny_lp())
 
 
-def test_trajectory_parity_config0_reordered_columns():
+def test_trajectory_parity_tiny_lp_reordered_columns():
     """The same with the internal column order (dense columns first in each XCD panel): every
     n-vector of the trace comes back in the user's order."""
-    _trajectory_parity(lpgen.config0(), xcd_panels=1, column_order=1)
+    _trajectory_parity(lpgen.tiny_lp(), xcd_panels=1, column_order=1)
 
 
 EPS = np.finfo(np.float64).eps
@@ -195,7 +195,7 @@ def _replay_parity(lp, steps=100, opts=None, **kw):
 
 
 @pytest.mark.parametrize("maker", [
-    lpgen.config0,
+    lpgen.tiny_lp,
     lambda: lpgen.large_plain(21, 400, 900),
     lambda: lpgen.large_plain(22, 400, 900),
     lambda: lpgen.add_empty_row_and_column(lpgen.tiny_plain(1, 150, 300, 60, 4)),
@@ -206,7 +206,7 @@ def test_replayed_step_parity(maker):
 
 
 @pytest.mark.parametrize("maker", [
-    lpgen.config0,
+    lpgen.tiny_lp,
     lambda: lpgen.large_plain(21, 400, 900),
     lambda: lpgen.pagerank_lp(2, 20000),
 ])
@@ -214,7 +214,7 @@ def test_replayed_step_parity_xcd_panels(maker):
     _replay_parity(maker(), xcd_panels=1)
 
 
-@pytest.mark.parametrize("maker", [lpgen.config0, lambda: lpgen.large_plain(21, 400, 900)])
+@pytest.mark.parametrize("maker", [lpgen.tiny_lp, lambda: lpgen.large_plain(21, 400, 900)])
 def test_replayed_step_parity_reordered_columns(maker):
     """Checkpoints in and out (x, anchor, weighted sums) cross the interface in the user's
     order while the solver keeps its own column order."""
@@ -243,7 +243,7 @@ def test_ablation_switches_replay(name):
 
 
 def test_constant_step_uses_power_iteration_norm():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     say("constant step size")
     s = make(lp, step_policy=1)
     Kt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)[0]
@@ -254,9 +254,9 @@ def test_constant_step_uses_power_iteration_norm():
     assert 0.99 * sigma <= sigma_est <= sigma * (1 + 1e-12)
 
 
-def test_solve_config0_to_1e8():
-    lp = lpgen.config0()
-    say("solve config0")
+def test_solve_tiny_lp_to_1e8():
+    lp = lpgen.tiny_lp()
+    say("solve tiny_lp")
     s = make(lp)
     st = s.solve(1e-8, 100000)
     assert st == P.OPTIMAL
@@ -280,14 +280,14 @@ def test_malitsky_pock_trajectory_parity(panels):
     """The line search of Appendix C (step_policy 2): the first 100 iterates, every trial's
     step and acceptance, and the checks against the oracle, free-running, in the plain row
     layout and in forced XCD panels."""
-    worst = _trajectory_parity(lpgen.config0(), opts=O.Options(step_policy="malitsky_pock"), step_policy=2,
+    worst = _trajectory_parity(lpgen.tiny_lp(), opts=O.Options(step_policy="malitsky_pock"), step_policy=2,
                                xcd_panels=panels)
     say("malitsky-pock worst iterate error", worst)
 
 
 def test_malitsky_pock_solve_to_1e8():
-    lp = lpgen.config0()
-    say("solve config0 malitsky-pock")
+    lp = lpgen.tiny_lp()
+    say("solve tiny_lp malitsky-pock")
     s = make(lp, step_policy=2)
     st = s.solve(1e-8, 100000)
     assert st == P.OPTIMAL
@@ -338,7 +338,7 @@ def test_graph_replay_equals_kernel_by_kernel(kw):
     """Blocks replayed as captured HIP graphs give bit-identical iterates, counters and every
     attempt and check record (each block's replay is compared) as launching kernel by kernel,
     with host synchronisation between the blocks as in every solve."""
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     say("graph replay vs eager", kw)
     out = []
     for graphs in (1, 0):
@@ -386,7 +386,7 @@ def test_edge_cases():
     assert s.solve(1e-8, 200000) == P.OPTIMAL
     # iteration limit 0 and tolerance 0
     say("edge limits")
-    s = make(lpgen.config0())
+    s = make(lpgen.tiny_lp())
     assert s.solve(1e-8, 0) == P.ITERATION_LIMIT
     assert s.info()["iterations"] == 0
     assert s.solve(0.0, 57) == P.ITERATION_LIMIT
@@ -397,7 +397,7 @@ def test_edge_cases():
 
 def test_get_before_solve_and_device_outputs():
     import torch
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     say("api states")
     s = make(lp)
     with pytest.raises(P.PdlpError):
@@ -422,7 +422,7 @@ def test_get_before_solve_and_device_outputs():
 # ------------------------------------------------------------------------------------------
 
 def test_batched_solve_matches_oracle_and_single_solver():
-    members = [lpgen.batched_instance(i) for i in (2, 3, 5, 7)] + [lpgen.config0(1)] + \
+    members = [lpgen.batched_instance(i) for i in (2, 3, 5, 7)] + [lpgen.tiny_lp(1)] + \
               [lpgen.add_empty_row_and_column(lpgen.tiny_plain(3, 60, 150, 20, 4))]
     say("batch", [lp.m for lp in members])
     b = P.Batch(members)
@@ -452,7 +452,7 @@ def test_batched_first_steps_match_oracle():
 
 
 def test_batched_rejects_bad_member():
-    lps = [lpgen.batched_instance(0), lpgen.config0()]
+    lps = [lpgen.batched_instance(0), lpgen.tiny_lp()]
     lps[1].l = lps[1].l.copy()
     lps[1].l[3] = 20.0
     with pytest.raises(P.PdlpError, match="member 1"):

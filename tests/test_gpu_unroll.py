@@ -57,7 +57,7 @@ def gpu_grad(s, lp, x_tgt, T, segment, eta, omega, gy=None):
 
 @pytest.mark.parametrize("segment,kw", [(0, {}), (7, {}), (7, dict(xcd_panels=1, column_order=1))])
 def test_unroll_matches_oracle_small(segment, kw):
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     rng = np.random.default_rng(40)
     x_tgt = rng.uniform(0, 5, lp.n)
     gy = rng.standard_normal(lp.m)
@@ -77,7 +77,7 @@ def test_unroll_matches_oracle_small(segment, kw):
 
 
 def test_unroll_segments_are_bit_identical():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     rng = np.random.default_rng(41)
     x_tgt = rng.uniform(0, 5, lp.n)
     gy = rng.standard_normal(lp.m)
@@ -96,7 +96,7 @@ def test_unroll_segments_are_bit_identical():
 
 
 def test_unroll_default_step_and_weight():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     say("unroll defaults", lp.name)
     Kt, ct, qt, lt, ut, D1, D2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
     eta = 0.9 / O.power_iteration_norm(Kt, 200)
@@ -133,7 +133,7 @@ def test_unroll_edge_cases():
 
 
 def test_unroll_errors():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     say("unroll errors")
     with P.Solver.from_lp(lp) as s:
         with pytest.raises(P.PdlpError, match="no forward pass"):
@@ -145,7 +145,7 @@ def test_unroll_errors():
 
 
 def test_unroll_full_size_matches_oracle():
-    lp, x_tgt = lpgen.config4()
+    lp, x_tgt = lpgen.unroll_lp()
     T = 500
     say("unroll full size", lp.name, "T", T, "segment 50")
     ref = oracle_case(lp, x_tgt, T)
@@ -166,7 +166,7 @@ def test_unroll_full_size_finite_differences():
     and (x_T(c) - x_T(c - h e)) . w / h both equal dL/dc_j up to round-off unless a mask
     changes inside the interval; then the side without the kink still does.  Every coordinate
     must match on at least one side; kink-free ones on both sides and centrally."""
-    lp, x_tgt = lpgen.config4()
+    lp, x_tgt = lpgen.unroll_lp()
     T = 500
     rng = np.random.default_rng(44)
     say("unroll FD", lp.name, "T", T)
@@ -206,7 +206,7 @@ def test_unroll_full_size_finite_differences():
 def test_unroll_autograd_function():
     import torch
     from paper_2106_04756_amd.unroll import unrolled_pdhg
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     rng = np.random.default_rng(45)
     x_tgt = rng.uniform(0, 5, lp.n)
     T = 40

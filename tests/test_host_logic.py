@@ -132,7 +132,7 @@ def _create(lp, **kw):
     (lambda d: d.__setitem__("l", np.full(d["l"].size, np.inf)), None),
 ])
 def test_create_rejects_invalid_input(mutate, needle):
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     d = dict(m=lp.m, n=lp.n, n_eq=lp.n_eq, c=lp.c.copy(), row_ptr=lp.row_ptr.copy(),
              col_idx=lp.col_idx.copy(), val=lp.val.copy(), q=lp.q.copy(), l=lp.l.copy(), u=lp.u.copy())
     mutate(d)
@@ -145,7 +145,7 @@ def test_create_rejects_invalid_input(mutate, needle):
 
 
 def test_create_rejects_unsorted_columns():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     ci = lp.col_idx.copy()
     s, e = lp.row_ptr[5], lp.row_ptr[6]
     ci[s:e] = ci[s:e][::-1]
@@ -154,7 +154,7 @@ def test_create_rejects_unsorted_columns():
 
 
 def test_create_rejects_bad_sizes_and_options():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     with pytest.raises(P.PdlpError, match="sizes"):
         P.Solver(lp.m, 0, lp.n_eq, lp.c, lp.row_ptr, lp.col_idx, lp.val, lp.q, lp.l, lp.u)
     with pytest.raises(P.PdlpError, match="options"):

@@ -74,8 +74,8 @@ def test_vertex_enumeration_matches_oracle(seed):
     assert abs(r.kkt["pobj"] - opt) <= 1e-7 * (1 + abs(opt))
 
 
-def test_highs_optimum_config0():
-    lp = lpgen.config0()
+def test_highs_optimum_tiny_lp():
+    lp = lpgen.tiny_lp()
     fun, _, _ = _highs(lp)
     r = O.solve_lp(lp, tol=1e-8)
     assert r.status == O.OPTIMAL and r.kkt["kkt"] <= 1e-8
@@ -87,7 +87,7 @@ def test_highs_optimum_config0():
 def test_kkt_evaluator_at_highs_solution():
     """At HiGHS's primal/dual optimum the relative KKT error is at round-off level, and it
     grows when the point is perturbed (pins the sign conventions of kkt())."""
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     fun, x, y = _highs(lp)
     k = O.kkt(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, x, y)
     assert k["kkt"] < 1e-8
@@ -117,7 +117,7 @@ def test_reduced_cost_projection_sets():
     assert lam.tolist() == [0.0, 0.0, 0.0, -1.0, 1.0, 0.0, 1.0, -1.0]
 
 
-@pytest.mark.parametrize("maker", [lpgen.config0, lambda: lpgen.large_plain(7, 300, 600)])
+@pytest.mark.parametrize("maker", [lpgen.tiny_lp, lambda: lpgen.large_plain(7, 300, 600)])
 def test_generator_certificates(maker):
     """x0 is feasible and (y0, lambda = s) dual feasible, so dual bound <= optimum <= c^T x0."""
     lp = maker()
@@ -134,8 +134,8 @@ def test_generator_certificates(maker):
     assert dual_bound <= fun + 1e-7 * abs(fun) and fun <= float(lp.c @ lp.x0) + 1e-7 * abs(fun)
 
 
-def test_config0_generator_is_deterministic():
-    a, b = lpgen.config0(), lpgen.config0()
+def test_tiny_lp_generator_is_deterministic():
+    a, b = lpgen.tiny_lp(), lpgen.tiny_lp()
     assert a.sha256() == b.sha256()
     assert a.m == 200 and a.n == 500 and a.nnz == 2500 and a.n_eq == 120
     assert np.all(np.diff(a.row_ptr) >= 0)
@@ -174,7 +174,7 @@ def test_pdhg_projection_onto_dual_cone():
 
 
 def test_optimum_is_fixed_point_of_pdhg():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     _, x, y = _highs(lp)
     K = lp.K()
     xp, yp = O.pdhg_step(x, y, 0.1, 1.0, lp.c, K, K.T.tocsr(), lp.q, lp.l, lp.u, lp.m1)
@@ -183,7 +183,7 @@ def test_optimum_is_fixed_point_of_pdhg():
 
 def test_eta_bar_at_least_inverse_spectral_norm():
     """Algorithm 2: eta_bar >= 1/||K~||_2 on every attempt; every accepted eta <= eta_bar."""
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     Kt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)[0]
     nrm = np.linalg.norm(Kt.toarray(), 2)
     r = O.solve_lp(lp, tol=1e-8, iter_limit=3000, record_trace=True)
@@ -263,7 +263,7 @@ def test_normalized_gap_ball_inside_box():
 
 
 def test_normalized_gap_zero_at_optimum():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     _, x, y = _highs(lp)
     K = lp.K()
     gx = lp.c - K.T @ y
@@ -311,7 +311,7 @@ def test_primal_weight_update_closed_form():
 def test_first_checks_restart_artificially():
     """In the first outer loop t = k, so criterion (iii) restarts at k = 40; at k = 80,
     t = 40 >= 0.5 * 80 restarts again (reading Z9)."""
-    r = O.solve_lp(lpgen.config0(), tol=1e-8, iter_limit=80, record_trace=True)
+    r = O.solve_lp(lpgen.tiny_lp(), tol=1e-8, iter_limit=80, record_trace=True)
     ch = r.trace.checks
     assert [c["k"] for c in ch] == [40, 80]
     assert ch[0]["mask"] & O.RESTART_ARTIFICIAL and ch[1]["mask"] & O.RESTART_ARTIFICIAL
@@ -336,7 +336,7 @@ def test_ruiz_norms_converge_to_one():
 
 
 def test_pock_chambolle_spectral_bound_and_same_optimum():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     Kt, ct, qt, lt, ut, D1, D2 = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)
     assert np.linalg.norm(Kt.toarray(), 2) <= 1.0 + 1e-12
     np.testing.assert_allclose(Kt.toarray(), np.diag(D1) @ lp.K().toarray() @ np.diag(D2), rtol=1e-13)
@@ -369,7 +369,7 @@ def _scaled_lp(lp, gamma, ax, ay):
 def test_scale_invariance_constant_step_bitwise():
     """Proposition 1 with powers of two: x^ = a_x x and y^ = a_y y exactly for the baseline
     PDHG (constant step, omega = InitializePrimalWeight, no scaling, no restarts)."""
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     g, ax, ay = 4.0, 2.0, 8.0
     opts = O.Options(ruiz_iters=0, pock_chambolle=False, step_policy="constant", restarts=False,
                      power_iters=100)
@@ -384,7 +384,7 @@ def test_scale_invariance_full_pdlp():
     bitwise before the first primal-weight update; after it the log/exp of Algorithm 3 round
     differently on the two problems and the trajectories agree to round-off amplified by the
     iteration (1e-9 relative over 200 steps)."""
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     g, ax, ay = 4.0, 2.0, 8.0
     a = O.solve_lp(lp, 1e-30, 200, trace_iters=200)
     b = O.solve_lp(_scaled_lp(lp, g, ax, ay), 1e-30, 200, trace_iters=200)
@@ -533,7 +533,7 @@ def test_malitsky_pock_candidate_range():
 
 
 def test_malitsky_pock_solves_to_highs_objective():
-    lp = lpgen.config0()
+    lp = lpgen.tiny_lp()
     opts = O.Options(step_policy="malitsky_pock")
     r = O.solve_lp(lp, tol=1e-8, iter_limit=60000, opts=opts, record_trace=True)
     assert r.status == O.OPTIMAL and r.kkt["kkt"] <= 1e-8

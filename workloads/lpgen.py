@@ -160,7 +160,7 @@ def tiny_plain(seed: int = 0, m: int = 200, n: int = 500, n_le: int = 80, per_co
     return _finish_plain_lp(rng, K, n_le, x0, l, u, None, name)
 
 
-def config0(seed: int = 0) -> LP:
+def tiny_lp(seed: int = 0) -> LP:
     """Tiny plain LP: m=200 (80 '<=' rows, 120 equalities), n=500, 5 nonzeros per column."""
     return tiny_plain(seed, 200, 500, 80, 5, name="tiny plain LP m=200 n=500 nnz=2500")
 
@@ -214,14 +214,14 @@ def large_plain(seed: int = 1, m: int = 1_000_000, n: int = 2_000_000, eq_frac: 
     return lp
 
 
-def config1(seed: int = 1) -> LP:
+def large_lp(seed: int = 1) -> LP:
     """Large plain LP m=1e6, n=2e6, Zipf(1.5) column counts clipped to [1,2000] (nnz ~1.36e8)."""
     return large_plain(seed, name="large plain LP m=1e6 n=2e6 Zipf(1.5) columns")
 
 
-def config1b(seed: int = 1) -> LP:
-    """The large plain LP at its stated size: as config1, with the column counts Zipf(1.5)
-    truncated to [1, 190] (mean ~10.6, nnz ~2.1e7)."""
+def large_lp_truncated(seed: int = 1) -> LP:
+    """Large plain LP m=1e6, n=2e6 with about 2.1e7 nonzeros: as large_lp, with the column
+    counts Zipf(1.5) truncated to [1, 190] (mean ~10.6)."""
     return large_plain(seed, max_col=190, truncate=True,
                        name="large plain LP m=1e6 n=2e6 Zipf(1.5) columns truncated to [1,190]")
 
@@ -294,7 +294,7 @@ def pagerank_lp(seed: int = 2, n_nodes: int = 5_000_000, out_deg: int = 8, dampi
     return lp
 
 
-def config2(seed: int = 2) -> LP:
+def pagerank_5m(seed: int = 2) -> LP:
     """PageRank LP on 5e6 nodes, out-degree 8 (nnz 5.0e7)."""
     return pagerank_lp(seed, 5_000_000, name="PageRank LP 5e6 nodes out-degree 8")
 
@@ -317,7 +317,7 @@ def batched_instance(i: int, base_seed: int = 3000) -> LP:
     return lp
 
 
-def config4(seed: int = 4):
+def unroll_lp(seed: int = 4):
     """Unroll workload: m=2e4 (8000 '<=' rows, 12000 equalities), n=5e4, 6 nonzeros per column;
     x_tgt ~ U[0,5]^n drawn from a fresh generator with the same seed after the instance."""
     lp = tiny_plain(seed, 20_000, 50_000, 8_000, 6, name="unroll LP m=2e4 n=5e4 nnz=3e5")
