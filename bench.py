@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-unroll", action="store_true")
+    ap.add_argument("--no-truncated", action="store_true",
+                    help="skip the large LP with column counts truncated to [1,190]")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-iter-limit", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -318,17 +320,20 @@ def main():
         "algorithmic_bytes_per_slot": r["algorithmic_bytes_per_slot"],
     }
     s.close()
-    # the same LP at its stated size (column counts truncated to [1, 190], nnz ~2.1e7)
-    lpb = lpgen.large_lp_truncated(args.seed)
-    log(f"generated {lpb.name}: nnz={lpb.nnz}")
-    rb, sb = measure_steps(P, torch, lpb, W, K)
-    sb.close()
-    rb["roofline"].pop("slot")
-    out["large_lp_truncated"] = {"workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
-                                   f"counts truncated to [1,190]), seed {args.seed}",
-                       "iters_per_s": rb["steps_taken"] / rb["seconds"], "steps": rb["steps_taken"],
-                       "roofline": rb["roofline"], "step_gbs_algorithmic": rb["step_gbs_algorithmic"]}
-    log(f"large_lp_truncated: {out['large_lp_truncated']['iters_per_s']:.1f} iters/s, {rb['roofline']['frac'] * 100:.1f}% of HBM peak")
+    if not args.no_truncated:
+        # the same shape with column counts truncated to [1, 190] (nnz ~2.1e7)
+        lpb = lpgen.large_lp_truncated(args.seed)
+        log(f"generated {lpb.name}: nnz={lpb.nnz}")
+        rb, sb = measure_steps(P, torch, lpb, W, K)
+        sb.close()
+        rb["roofline"].pop("slot")
+        out["large_lp_truncated"] = {
+            "workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
+                        f"counts truncated to [1,190]), seed {args.seed}",
+            "iters_per_s": rb["steps_taken"] / rb["seconds"], "steps": rb["steps_taken"],
+            "roofline": rb["roofline"], "step_gbs_algorithmic": rb["step_gbs_algorithmic"]}
+        log(f"large_lp_truncated: {out['large_lp_truncated']['iters_per_s']:.1f} iters/s, "
+            f"{rb['roofline']['frac'] * 100:.1f}% of HBM peak")
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
     tiny = lpgen.tiny_lp()
     st0 = P.Solver.from_lp(tiny)
