@@ -19,13 +19,9 @@ from scipy.optimize import linprog
 import paper_2106_04756_amd as P
 from oracle import pdlp_oracle as O
 from workloads import lpgen
+from replay import rel, replay_steps, say
 
 pytestmark = pytest.mark.gpu
-
-
-def say(*a):
-    print("[gpu-case]", *a, flush=True)
-    sys.stdout.flush()
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -38,11 +34,6 @@ def _gpu():
 
 def make(lp, **kw):
     return P.Solver.from_lp(lp, **kw)
-
-
-def rel(a, b):
-    nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
 # ------------------------------------------------------------------------------------------
@@ -143,55 +134,19 @@ def test_trajectory_parity_tiny_lp_reordered_columns():
     _trajectory_parity(lpgen.tiny_lp(), xcd_panels=1, column_order=1)
 
 
-EPS = np.finfo(np.float64).eps
-
-
 def _replay_parity(lp, steps=100, opts=None, **kw):
     """Replayed steps: for k = 0..steps-1 the GPU is put in the oracle's exact state before
-    step k+1 (pdlp_set_state) and must land on the oracle's state after it, including the
-    restart check at multiples of 40.  This tests every step's arithmetic without the
-    amplification of round-off that a free-running PDLP trajectory shows (the step-size
-    ratio of Algorithm 2 is ill-conditioned, so last-bit differences grow along a trajectory).
-
-    Tolerances: iterates, anchors and weighted sums 1e-12 relative (one step of float64
-    arithmetic from identical inputs); the proposed step eta_hat within the conditioning of
-    the denominator 2 dy^T K dx of Algorithm 2, which the GPU forms as dy^T (K x' - K x):
-    its error is bounded by 2 eps sum_i |dy_i| len_i ((|K||x'|)_i + (|K||x|)_i)."""
+    step k+1 and must land on the oracle's state after it (replay.replay_steps).  This tests
+    every step's arithmetic without the amplification of round-off that a free-running PDLP
+    trajectory shows (the step-size ratio of Algorithm 2 is ill-conditioned, so last-bit
+    differences grow along a trajectory)."""
     ref = O.solve_lp(lp, tol=1e-30, iter_limit=steps, opts=opts, record_states=steps,
                      trace_iters=steps, record_trace=True)
-    Kt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u)[0]
-    absK = abs(Kt)
-    rowlen = np.diff(Kt.indptr).astype(np.float64)
+    o = opts or O.Options()
+    Kt, ct, qt = O.precondition(lp.K(), lp.c, lp.q, lp.l, lp.u, ruiz_iters=o.ruiz_iters,
+                                pock_chambolle=o.pock_chambolle)[:3]
     say("replay", lp.name, lp.m, lp.n, lp.nnz, kw)
-    s = make(lp, **kw)
-    states = ref.trace.states
-    att_by_k = {}
-    for a in ref.trace.attempts:
-        att_by_k.setdefault(a[0], []).append(a)
-    for k in range(steps):
-        a, b = states[k], states[k + 1]
-        s.set_state(a)
-        s.solve(1e-30, k + 1)
-        g = s.get_state()
-        assert (g["k"], g["t"], g["n_outer"]) == (b["k"], b["t"], b["n_outer"]), k
-        for key in ("x", "y", "xa", "ya", "Sx", "Sy"):
-            assert rel(g[key], b[key]) <= 1e-12, (k, key, rel(g[key], b[key]))
-        assert abs(g["Seta"] - b["Seta"]) <= 1e-15 * b["Seta"], k
-        assert abs(g["omega"] - b["omega"]) <= 1e-13 * b["omega"], k
-        for key in ("mu_prev", "mu_anchor"):
-            if math.isfinite(b[key]):
-                assert abs(g[key] - b[key]) <= 1e-9 * abs(b[key]), (k, key)
-            else:
-                assert g[key] == b[key], (k, key)
-        # conditioning of eta_bar on the accepted attempt
-        _, xp, yp = ref.trace.iterates[k]
-        dx, dy = xp - a["x"], yp - a["y"]
-        den = abs(float(dy @ (Kt @ dx)))
-        err_den = 2 * EPS * float(np.abs(dy) @ (rowlen * (absK @ np.abs(xp) + absK @ np.abs(a["x"]))))
-        tol = 1e-13 + (4 * err_den / den if den > 0 else 0.0)
-        if len(att_by_k[k]) > 1:
-            tol = max(tol, 1e-9)            # a rejected attempt chains two step proposals
-        assert abs(g["eta_hat"] - b["eta_hat"]) <= tol * b["eta_hat"], (k, g["eta_hat"], b["eta_hat"], tol)
+    replay_steps(make(lp, **kw), ref, Kt, range(steps), ct, qt)
 
 
 @pytest.mark.parametrize("maker", [
