@@ -97,6 +97,16 @@ typedef struct pdlp_options {
                                     Appendix C, which still updates the primal weight
                                     (Algorithm 3, from the current iterate and the previous
                                     update's) at k = 2, 4, 8, ...: 0 (off)                    */
+  int32_t lds_gather;            /* operand of a product in panels staged in LDS (one
+                                    workgroup of 1024 threads per CU): -1 automatic (default:
+                                    slices of lds_entries columns, one panel each, for a copy
+                                    whose columns keep their order, when its panel rows stay
+                                    below 0.4 of its nonzeros), 0 off,
+                                    1 the slices whenever a copy is in panels, 2 XCD panels
+                                    with each panel's first lds_entries columns staged.  Never
+                                    for a copy with a panel row longer than 512 nonzeros.      */
+  int32_t lds_entries;           /* operand entries staged per panel: 0 = 15360 (the most;
+                                    120 KiB of LDS), else 1 .. 15360                           */
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

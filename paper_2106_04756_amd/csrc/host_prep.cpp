@@ -126,59 +126,86 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
   const int64_t nnz = rp[nrows];
   L = PanelLayout();
   L.P = P;
-  const std::vector<int32_t> cut = given_cuts ? *given_cuts : panel_cuts(ci, nnz, ncols, P);
-  // panel-row lengths: seg[r * P + p] = nonzeros of row r in panel p
-  std::vector<int32_t> seg(size_t(nrows) * size_t(P), 0);
-  int64_t nprow = 0;
+  L.cut = given_cuts ? *given_cuts : panel_cuts(ci, nnz, ncols, P);
+  const std::vector<int32_t>& cut = L.cut;
+  // Row segments: the nonempty panel rows of row r are segments sp[r] .. sp[r + 1], in panel
+  // order, with their panel and length (a sparse form of the rows x panels length table).
+  std::vector<int64_t> sp(size_t(nrows) + 1, 0);
   for (int64_t r = 0; r < nrows; ++r) {
-    int p = 0;
+    int64_t cntr = 0;
+    int p = -1;
     for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
-      while (ci[e] >= cut[size_t(p) + 1]) ++p;
-      seg[size_t(r) * P + p]++;
+      int q = p < 0 ? 0 : p;
+      while (ci[e] >= cut[size_t(q) + 1]) ++q;
+      if (q != p) { ++cntr; p = q; }
     }
-    for (int q = 0; q < P; ++q) nprow += seg[size_t(r) * P + q] > 0;
+    sp[size_t(r) + 1] = sp[size_t(r)] + cntr;
   }
+  const int64_t nprow = sp[size_t(nrows)];
   if (double(nprow) > max_prow_frac * double(std::max<int64_t>(nnz, 1))) return false;
+  std::vector<int32_t> seg_p(static_cast<size_t>(nprow)), seg_len(static_cast<size_t>(nprow));
+  for (int64_t r = 0; r < nrows; ++r) {
+    int64_t k = sp[size_t(r)] - 1;
+    int p = -1;
+    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+      int q = p < 0 ? 0 : p;
+      while (ci[e] >= cut[size_t(q) + 1]) ++q;
+      if (q != p) { ++k; p = q; seg_p[size_t(k)] = q; seg_len[size_t(k)] = 0; }
+      seg_len[size_t(k)]++;
+    }
+  }
+  // segments of each panel in row order (counting sort by panel)
+  std::vector<int64_t> pp(size_t(P) + 1, 0);
+  for (int64_t k = 0; k < nprow; ++k) pp[size_t(seg_p[size_t(k)]) + 1]++;
+  for (int p = 0; p < P; ++p) pp[size_t(p) + 1] += pp[size_t(p)];
+  std::vector<int64_t> by_panel(static_cast<size_t>(nprow)), fill(pp.begin(), pp.end() - 1);
+  std::vector<int32_t> seg_row(static_cast<size_t>(nprow));
+  for (int64_t r = 0; r < nrows; ++r)
+    for (int64_t k = sp[size_t(r)]; k < sp[size_t(r) + 1]; ++k) {
+      seg_row[size_t(k)] = int32_t(r);
+      by_panel[size_t(fill[size_t(seg_p[size_t(k)])]++)] = k;
+    }
   // order panel rows: panel, then lane class (wavefront rows by p, then long rows), then
   // length (wavefront classes), then row
   L.prow_ptr.reserve(size_t(nprow) + 1);
   L.prow_ptr.push_back(0);
   L.prow_row.reserve(size_t(nprow));
-  std::vector<int32_t> prow_of(size_t(nrows) * size_t(P), -1);
+  std::vector<int32_t> prow_of(static_cast<size_t>(nprow), -1);   // panel row id of each segment
   L.wave_begin.push_back(0);
   L.block_begin.push_back(0);
   Schedule& S = L.sched;
+  std::vector<int64_t> cls_segs[8];
   for (int p = 0; p < P; ++p) {
+    for (auto& v : cls_segs) v.clear();
+    for (int64_t i = pp[size_t(p)]; i < pp[size_t(p) + 1]; ++i) {
+      const int64_t k = by_panel[size_t(i)];
+      const int64_t len = seg_len[size_t(k)];
+      cls_segs[(len <= kWaveMaxLen) ? lanes_log2_for(len) : 7].push_back(k);
+    }
     for (int cls = 0; cls <= 7; ++cls) {           // 0..6 lane classes, 7 = long rows
       const int64_t k0 = int64_t(L.prow_row.size());
-      std::vector<int32_t> rows_cls;
-      for (int64_t r = 0; r < nrows; ++r) {
-        const int64_t len = seg[size_t(r) * P + p];
-        if (len == 0) continue;
-        const int c = (len <= kWaveMaxLen) ? lanes_log2_for(len) : 7;
-        if (c == cls) rows_cls.push_back(int32_t(r));
-      }
+      std::vector<int64_t>& segs = cls_segs[cls];
       if (cls < 7)
-        std::stable_sort(rows_cls.begin(), rows_cls.end(), [&](int32_t x, int32_t y) {
-          return seg[size_t(x) * P + p] < seg[size_t(y) * P + p];
+        std::stable_sort(segs.begin(), segs.end(), [&](int64_t x, int64_t y) {
+          return seg_len[size_t(x)] < seg_len[size_t(y)];
         });
-      for (const int32_t r : rows_cls) {
-        const int64_t len = seg[size_t(r) * P + p];
-        prow_of[size_t(r) * P + p] = int32_t(L.prow_row.size());
-        L.prow_row.push_back(int32_t(r));
+      for (const int64_t k : segs) {
+        const int64_t len = seg_len[size_t(k)];
+        prow_of[size_t(k)] = int32_t(L.prow_row.size());
+        L.prow_row.push_back(seg_row[size_t(k)]);
         L.prow_ptr.push_back(L.prow_ptr.back() + len);
         if (cls == 7) {
-          const int32_t k = int32_t(L.prow_row.size() - 1);
+          const int32_t kk = int32_t(L.prow_row.size() - 1);
           if (len <= kVectorMax) {
-            S.block.push_back(RowDesc{k, 0, kVector, 0});
+            S.block.push_back(RowDesc{kk, 0, kVector, 0});
           } else {
             const int32_t id = int32_t(S.split_row.size());
             const int32_t nch = int32_t((len + kChunk - 1) / kChunk);
-            S.split_row.push_back(k);
+            S.split_row.push_back(kk);
             S.split_nchunks.push_back(nch);
             S.split_base.push_back(int32_t(S.total_chunks));
             S.total_chunks += nch;
-            for (int32_t cc = 0; cc < nch; ++cc) S.block.push_back(RowDesc{k, cc, kSplit, id});
+            for (int32_t cc = 0; cc < nch; ++cc) S.block.push_back(RowDesc{kk, cc, kSplit, id});
           }
         }
       }
@@ -193,18 +220,97 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
   L.slot_idx.reserve(size_t(nprow));
   for (int64_t r = 0; r < nrows; ++r) {
     int64_t e = rp[r];
-    for (int p = 0; p < P; ++p) {
-      const int32_t len = seg[size_t(r) * P + p];
-      if (len == 0) continue;
-      const int32_t k = prow_of[size_t(r) * P + p];
-      int64_t dst = L.prow_ptr[size_t(k)];
+    for (int64_t k = sp[size_t(r)]; k < sp[size_t(r) + 1]; ++k) {
+      const int32_t len = seg_len[size_t(k)];
+      const int32_t id = prow_of[size_t(k)];
+      const int64_t dst = L.prow_ptr[size_t(id)];
       for (int32_t t = 0; t < len; ++t) L.src[size_t(dst + t)] = e + t;
       e += len;
-      L.slot_idx.push_back(k);
+      L.slot_idx.push_back(id);
     }
     L.slot_ptr[size_t(r) + 1] = int64_t(L.slot_idx.size());
   }
   return true;
+}
+
+void build_interleaved(const Schedule& S, const int64_t* rp, const int32_t* ci, const double* v,
+                       const int32_t* perm, std::vector<int64_t>& off, std::vector<int32_t>& cis,
+                       std::vector<double>& vs) {
+  const size_t nt = S.wave.size();
+  off.assign(nt + 1, 0);
+  for (size_t t = 0; t < nt; ++t) {
+    const RowDesc& D = S.wave[t];
+    const int lg = D.kind_l >> 8;
+    const int64_t per_round = 64 >> lg;
+    const int64_t rounds = (int64_t(D.b) + per_round - 1) / per_round;
+    off[t + 1] = off[t] + rounds * 64 * int64_t(D.aux);
+  }
+  cis.assign(size_t(off[nt]), 0);
+  vs.assign(size_t(off[nt]), 0.0);
+  for (size_t t = 0; t < nt; ++t) {
+    const RowDesc& D = S.wave[t];
+    const int lg = D.kind_l >> 8, L = 1 << lg, E = D.aux;
+    const int per_round = 64 >> lg;
+    for (int base = 0, i = 0; base < D.b; base += per_round, ++i) {
+      const int64_t blk = off[t] + int64_t(i) * 64 * E;
+      for (int j = 0; j < 64; ++j) {
+        const int slot = base + (j >> lg), lane = j & (L - 1);
+        int64_t q0 = 0, len = 0;
+        if (slot < D.b) {
+          const int64_t r = perm ? perm[D.a + slot] : D.a + slot;
+          q0 = rp[r];
+          len = rp[r + 1] - q0;
+        }
+        const int32_t pad_col = len > 0 ? ci[q0] : 0;
+        for (int k = 0; k < E; ++k) {
+          const int64_t e = int64_t(k) * L + lane;
+          const size_t pos = size_t(blk + int64_t(k) * 64 + j);
+          if (e < len) {
+            cis[pos] = ci[q0 + e];
+            vs[pos] = v[q0 + e];
+          } else {
+            cis[pos] = pad_col;
+          }
+        }
+      }
+    }
+  }
+}
+
+std::vector<int32_t> lds_segments(const PanelLayout& L, int G, bool aligned, std::vector<LdsSeg>& seg) {
+  const std::vector<RowDesc>& W = L.sched.wave;
+  const int nt = int(W.size());
+  std::vector<double> pre(size_t(nt) + 1, 0.0);
+  for (int t = 0; t < nt; ++t) {
+    const RowDesc& D = W[size_t(t)];
+    const int64_t nz = L.prow_ptr[size_t(D.a + D.b)] - L.prow_ptr[size_t(D.a)];
+    pre[size_t(t) + 1] = pre[size_t(t)] + 12.0 * double(nz) + 16.0 * double(D.b) + 64.0;
+  }
+  // first task of share j of `parts` equal-cost shares of tasks [t0, t1)
+  auto share_start = [&](int t0, int t1, int parts, int j) -> int {
+    if (j <= 0) return t0;
+    if (j >= parts) return t1;
+    const double target = pre[size_t(t0)] + (pre[size_t(t1)] - pre[size_t(t0)]) * double(j) / double(parts);
+    return int(std::lower_bound(pre.begin() + t0, pre.begin() + t1, target) - pre.begin());
+  };
+  std::vector<int32_t> seg_ptr(size_t(G) + 1, 0);
+  seg.clear();
+  for (int b = 0; b < G; ++b) {
+    if (aligned) {
+      const int p = b % L.P, j = b / L.P, parts = G / L.P;
+      const int t0 = L.wave_begin[size_t(p)], t1 = L.wave_begin[size_t(p) + 1];
+      const int ta = share_start(t0, t1, parts, j), tb = share_start(t0, t1, parts, j + 1);
+      if (tb > ta) seg.push_back(LdsSeg{p, ta, tb, 0});
+    } else {
+      const int ta = share_start(0, nt, G, b), tb = share_start(0, nt, G, b + 1);
+      for (int p = 0; p < L.P && ta < tb; ++p) {
+        const int lo = std::max(ta, L.wave_begin[size_t(p)]), hi = std::min(tb, L.wave_begin[size_t(p) + 1]);
+        if (hi > lo) seg.push_back(LdsSeg{p, lo, hi, 0});
+      }
+    }
+    seg_ptr[size_t(b) + 1] = int32_t(seg.size());
+  }
+  return seg_ptr;
 }
 
 std::string validate_lp(int64_t m, int64_t n, int64_t n_eq, const double* c, const int64_t* rp,

@@ -20,6 +20,9 @@ struct CsrDev {
   const int32_t* perm;   // row of each wavefront slot (nullptr: identity)
   const RowDesc* wave;
   const RowDesc* block;
+  const int64_t* task_off;     // interleaved entries of wavefront task t from task_off[t]
+  const double* vs;            // (build_interleaved); the CSR arrays serve workgroup tasks
+  const int32_t* cis;
   const int32_t* wave_begin;   // npanel + 1 task offsets per panel
   const int32_t* block_begin;
   const int32_t* prow_row;     // panel mode: original row of each panel row
@@ -33,6 +36,14 @@ struct CsrDev {
   int32_t pad;
   double* split_part;    // partial sums of split-row chunks
   unsigned* split_cnt;   // chunk arrival counters (reset to 0 by the last arrival)
+  // LDS-staged products (lds_h > 0, panel mode, wavefront tasks only): lds_grid workgroups of
+  // kLdsBlock threads; workgroup b runs segments lds_seg[lds_seg_ptr[b] .. lds_seg_ptr[b + 1]);
+  // panel p covers columns col_cut[p] .. col_cut[p + 1], of which the first lds_h are staged.
+  int32_t lds_h;
+  int32_t lds_grid;
+  const int32_t* col_cut;
+  const int32_t* lds_seg_ptr;
+  const LdsSeg* lds_seg;
 };
 
 // Device vectors of a solver.  n-vectors are indexed by column j, m-vectors by row i.

@@ -20,6 +20,16 @@ constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
 // gave +28%).
 constexpr double kPanelRowFrac = 0.4;
 constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per XCD of an MI355X)
+// LDS-staged products: one workgroup of kLdsBlock threads per CU holds up to kLdsEntries
+// entries of the gathered vector (120 KiB of the CU's 160 KiB of LDS).  A copy whose
+// gathered vector, cut into slices of that width, costs at most kLdsRowFrac panel rows per
+// nonzero gets one panel per slice and gathers only from LDS; otherwise a copy in XCD panels
+// whose columns are ordered hot-first stages each panel's first kLdsEntries columns.
+constexpr int kLdsBlock = 1024;
+constexpr int kLdsWaves = kLdsBlock / 64;
+constexpr int kLdsEntries = 15360;
+constexpr int kMaxLdsPanels = 4096;
+constexpr double kLdsRowFrac = 0.4;
 
 enum DescKind : int32_t { kWaveRows = 0, kVector = 1, kSplit = 2 };
 
@@ -55,6 +65,7 @@ Schedule build_schedule(const int64_t* row_ptr, int64_t nrows);
 // each row in panel order.
 struct PanelLayout {
   int P = 1;
+  std::vector<int32_t> cut;            // P + 1 column offsets of the panels
   std::vector<int64_t> prow_ptr;       // total panel rows + 1
   std::vector<int32_t> prow_row;       // original row of each panel row
   std::vector<int64_t> src;            // row-major nonzero index of each panel-ordered nonzero
@@ -65,12 +76,38 @@ struct PanelLayout {
   std::vector<int32_t> block_begin;    // P + 1 offsets of each panel's workgroup tasks
 };
 
+// The work of one LDS-staged pass: wavefront tasks wave[tb .. te) of panel p.
+struct LdsSeg {
+  int32_t p;
+  int32_t tb;
+  int32_t te;
+  int32_t pad;
+};
+
 // Builds the layout with P panels; returns false (and leaves `out` unusable) when the panel
 // rows would cost more than `max_prow_frac` of the nonzeros.
 // given_cuts: the P + 1 column cuts to use (nullptr: about nnz / P nonzeros per panel).
 bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
                   double max_prow_frac, PanelLayout& out,
                   const std::vector<int32_t>* given_cuts = nullptr);
+
+// Interleaved entries of the wavefront tasks (a sliced-ELL form): round i of task t, with E
+// entries per lane, owns 64 E slots from off[t] + 64 E i; entry k of lane j (row group
+// j >> log2 L, lane j mod L of it) sits at slot 64 k + j and holds entry k L + (j mod L) of
+// that row, so each of a wavefront's E loads reads 64 consecutive values.  Slots past a row's
+// end, and of row groups past the task's last row, hold the value 0 and the row's first column
+// (column 0 for an empty row or a missing row).  Rows of the task: perm[a + slot] when perm is
+// given, else a + slot.  rp, ci, v: the copy in CSR form (row order of the layout).
+void build_interleaved(const Schedule& S, const int64_t* rp, const int32_t* ci, const double* v,
+                       const int32_t* perm, std::vector<int64_t>& off, std::vector<int32_t>& cis,
+                       std::vector<double>& vs);
+
+// Splits the wavefront tasks of a panel layout among G workgroups at about equal cost (12
+// bytes per nonzero, 16 per panel row, 64 per task): aligned (G a multiple of P): workgroup b
+// takes a contiguous share of panel b mod P's tasks, so it stays on that panel's XCD;
+// otherwise workgroup b takes the b-th share of all tasks in panel order, cut into one segment
+// per panel it touches.  Returns the G + 1 offsets of each workgroup's segments in `seg`.
+std::vector<int32_t> lds_segments(const PanelLayout& L, int G, bool aligned, std::vector<LdsSeg>& seg);
 
 // Scalar state of one solve, resident in device memory.  Kernels read it at entry; only the
 // last workgroup of a kernel (after every other workgroup has arrived) writes it.

@@ -252,58 +252,107 @@ __device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const double* _
   }
 }
 
+// Sources of the gathered operand of a product: device memory, or the LDS stage of a panel
+// (its columns c0 .. c0 + h, h >= 1) with device memory for the rest.  Every lane reads the
+// stage at its column clamped into it; only lanes whose column lies outside read device
+// memory, behind a branch, so served lanes send no request to the caches.
+struct GlobalGather {
+  const double* __restrict__ x;
+};
+struct LdsGather {
+  const double* stage;
+  const double* __restrict__ x;
+  int32_t c0;
+  uint32_t h;
+};
+template <int E>
+__device__ __forceinline__ void gather_all(const GlobalGather& g, const int32_t (&c)[E], double (&xv)[E]) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) xv[k] = g.x[c[k]];
+}
+template <int E>
+__device__ __forceinline__ void gather_all(const LdsGather& g, const int32_t (&c)[E], double (&xv)[E]) {
+  bool far = false;
+#pragma unroll
+  for (int k = 0; k < E; ++k) {
+    const uint32_t d = uint32_t(c[k] - g.c0);
+    far = far || d >= g.h;
+    xv[k] = g.stage[d < g.h ? d : g.h - 1];
+  }
+  if (far) {
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+      if (uint32_t(c[k] - g.c0) >= g.h) xv[k] = g.x[c[k]];
+  }
+}
+
 // One wavefront task: rows perm[D.a .. D.a + D.b) (panel rows D.a .. in panel mode), each by a
-// group of L = 2^p lanes, E entries per lane (E L >= every row length of the task).
-// Branch-free loads: every lane loads its E entries with the index clamped into the row, so all
-// loads (and then all gathers) are in flight together; entries past the row end are masked to
-// +0.0, which leaves the sum bit-identical for any E.
-template <int MODE, int E, class Epi>
-__device__ __forceinline__ void wave_task(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
-                                          double (&acc)[Epi::N], const RowDesc& D, int lane64) {
+// group of L = 2^p lanes, E entries per lane (E L >= every row length of the task), read from
+// the task's interleaved entries at `off` (each of the E loads covers 64 consecutive slots).
+// All E loads, then all gathers, are in flight together; entries past the row end are masked
+// to +0.0, which leaves the sum bit-identical for any E.
+template <int MODE, int E, class Epi, class G>
+__device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi& epi,
+                                          double (&acc)[Epi::N], const RowDesc& D, int64_t off, int lane64) {
   const int lg = D.kind_l >> 8, L = 1 << lg;
   const int g = lane64 >> lg, lane = lane64 & (L - 1);
   const int per_round = 64 >> lg;
-  for (int base = 0; base < D.b; base += per_round) {
+  int64_t blk = off + lane64;
+  for (int base = 0; base < D.b; base += per_round, blk += 64 * E) {
     const int slot = base + g;
     const bool active = slot < D.b;
     int r = 0;
     double s = 0.0;
     if (active) {
       r = A.perm ? A.perm[D.a + slot] : D.a + slot;
-      const int64_t q0 = A.rp[r], p1 = A.rp[r + 1];
-      if (p1 > q0) {
-        const int64_t p0 = q0 + lane;
+      const int64_t len = A.rp[r + 1] - A.rp[r];
+      if (len > 0) {
         double v[E];
         int32_t c[E];
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          const int64_t e = p0 + int64_t(k) * L;
-          const int64_t ec = (e < p1) ? e : p1 - 1;
-          v[k] = A.v[ec];
-          if constexpr (MODE == kProd) c[k] = A.ci[ec];
+          v[k] = A.vs[blk + int64_t(k) * 64];
+          if constexpr (MODE == kProd) c[k] = A.cis[blk + int64_t(k) * 64];
         }
         if constexpr (MODE == kProd) {
           double xv[E];
-#pragma unroll
-          for (int k = 0; k < E; ++k) xv[k] = x[c[k]];
+          gather_all<E>(x, c, xv);
 #pragma unroll
           for (int k = 0; k < E; ++k) {
             const double t = v[k] * xv[k];
-            s = s + ((p0 + int64_t(k) * L < p1) ? t : 0.0);
+            s = s + ((k * L + lane < len) ? t : 0.0);
           }
         } else {
 #pragma unroll
-          for (int k = 0; k < E; ++k) s = comb<MODE>(s, (p0 + int64_t(k) * L < p1) ? fabs(v[k]) : 0.0);
+          for (int k = 0; k < E; ++k) s = comb<MODE>(s, (k * L + lane < len) ? fabs(v[k]) : 0.0);
         }
       }
     }
-    for (int off = L >> 1; off > 0; off >>= 1) s = comb<MODE>(s, __shfl_xor(s, off, 64));
+    for (int off2 = L >> 1; off2 > 0; off2 >>= 1) s = comb<MODE>(s, __shfl_xor(s, off2, 64));
     if (active && lane == 0) {
       double cc[Epi::N];
       epi.row(r, s, cc);
 #pragma unroll
       for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
     }
+  }
+}
+
+// wave_task with the entries per lane of the task (uniform across the wavefront).
+template <int MODE, class Epi, class G>
+__device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const Epi& epi,
+                                            double (&acc)[Epi::N], int t, int lane64) {
+  const RowDesc D = A.wave[t];
+  const int64_t off = A.task_off[t];
+  switch (D.aux) {
+    case 1: wave_task<MODE, 1>(A, x, epi, acc, D, off, lane64); break;
+    case 2: wave_task<MODE, 2>(A, x, epi, acc, D, off, lane64); break;
+    case 3: wave_task<MODE, 3>(A, x, epi, acc, D, off, lane64); break;
+    case 4: wave_task<MODE, 4>(A, x, epi, acc, D, off, lane64); break;
+    case 5: wave_task<MODE, 5>(A, x, epi, acc, D, off, lane64); break;
+    case 6: wave_task<MODE, 6>(A, x, epi, acc, D, off, lane64); break;
+    case 7: wave_task<MODE, 7>(A, x, epi, acc, D, off, lane64); break;
+    default: wave_task<MODE, kElemsPerLane>(A, x, epi, acc, D, off, lane64); break;
   }
 }
 
@@ -321,19 +370,8 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
   const int nw = ps.nb * kWaves;
   const int t1 = A.wave_begin[ps.p + 1];
   const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[ps.p] + ps.lb * kWaves + (threadIdx.x >> 6));
-  for (int t = w0; t < t1; t += nw) {
-    const RowDesc D = A.wave[t];
-    switch (D.aux) {       // entries per lane of this task (uniform across the wavefront)
-      case 1: wave_task<MODE, 1>(A, x, epi, acc, D, lane64); break;
-      case 2: wave_task<MODE, 2>(A, x, epi, acc, D, lane64); break;
-      case 3: wave_task<MODE, 3>(A, x, epi, acc, D, lane64); break;
-      case 4: wave_task<MODE, 4>(A, x, epi, acc, D, lane64); break;
-      case 5: wave_task<MODE, 5>(A, x, epi, acc, D, lane64); break;
-      case 6: wave_task<MODE, 6>(A, x, epi, acc, D, lane64); break;
-      case 7: wave_task<MODE, 7>(A, x, epi, acc, D, lane64); break;
-      default: wave_task<MODE, kElemsPerLane>(A, x, epi, acc, D, lane64); break;
-    }
-  }
+  const GlobalGather gx{x};
+  for (int t = w0; t < t1; t += nw) wave_task_e<MODE>(A, gx, epi, acc, t, lane64);
   csr_block_tasks<MODE>(A, x, epi, acc, part);
 }
 
@@ -881,6 +919,35 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, c
   else csr_rows<kAbsSum>(A, nullptr, epi, acc, nullptr);
 }
 
+// First pass of a panel-mode product with the gathered operand staged in LDS: the panel-row
+// values of k_panel_rows (mode kProd), summed in the same order.  One workgroup of kLdsBlock
+// threads per CU; for each of its segments the workgroup stages the panel's first lds_h
+// entries of the operand, then its wavefronts share the segment's tasks.
+template <int COPY>
+__global__ __launch_bounds__(kLdsBlock) void k_lds_rows(CsrDev A, DevState* st, const double* in0,
+                                                        const double* in1, int in_parity, double* out,
+                                                        int pred) {
+  __shared__ double stage[kLdsEntries];
+  const DevState& S = *st;
+  if (!pred_ok(S, pred)) return;
+  const double* in = (in_parity && S.parity) ? in1 : in0;
+  StoreEpi epi{out};
+  double acc[1] = {0.0};
+  const int lane64 = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int s0 = A.lds_seg_ptr[blockIdx.x], s1 = A.lds_seg_ptr[blockIdx.x + 1];
+  for (int sg = s0; sg < s1; ++sg) {
+    const LdsSeg G = A.lds_seg[sg];
+    const int32_t c0 = A.col_cut[G.p];
+    const int32_t h = min(A.lds_h, A.col_cut[G.p + 1] - c0);
+    if (sg > s0) __syncthreads();        // every wavefront is done with the previous stage
+    for (int i = threadIdx.x; i < h; i += kLdsBlock) stage[i] = in[c0 + i];
+    __syncthreads();
+    const LdsGather gx{stage, in, c0, uint32_t(h)};
+    for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd>(A, gx, epi, acc, t, lane64);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_primal_combine(CsrDev AT, DevState* st, Bufs B,
                                                            const double* part, double* partA) {
   const DevState& S = *st;
@@ -956,13 +1023,37 @@ __global__ __launch_bounds__(kBlock) void k_scale_factors(const double* norms, d
 // K~_ij <- (K~_ij * dr_i) * dc_j, on the row-major copy (transposed = 0) or on the
 // transposed copy (transposed = 1, where the CSR row is j and the column is i); the same
 // expression keeps the two copies bitwise transposes of each other.
-__global__ __launch_bounds__(kBlock) void k_scale_values(CsrDev A, double* v, const double* dr,
+__global__ __launch_bounds__(kBlock) void k_scale_values(CsrDev A, double* v, double* vs, const double* dr,
                                                          const double* dc, int transposed) {
   csr_elements(A, [&](int64_t e, int r, int col) {
     const int i = transposed ? col : r;
     const int j = transposed ? r : col;
     v[e] = (v[e] * dr[i]) * dc[j];
   });
+  // the interleaved entries of the wavefront tasks, with the same expression
+  const int nw = gridDim.x * kWaves;
+  const int lane64 = threadIdx.x & 63;
+  for (int t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < A.nwave; t += nw) {
+    const RowDesc D = A.wave[t];
+    const int lg = D.kind_l >> 8, L = 1 << lg, E = D.aux;
+    const int g = lane64 >> lg, lane = lane64 & (L - 1), per_round = 64 >> lg;
+    int64_t blk = A.task_off[t] + lane64;
+    for (int base = 0; base < D.b; base += per_round, blk += int64_t(64) * E) {
+      const int slot = base + g;
+      if (slot >= D.b) continue;
+      const int k = A.perm ? A.perm[D.a + slot] : D.a + slot;
+      const int r = A.prow_row ? A.prow_row[k] : k;
+      const int64_t len = A.rp[k + 1] - A.rp[k];
+      for (int q = 0; q < E; ++q) {
+        if (int64_t(q) * L + lane >= len) break;
+        const int64_t pos = blk + int64_t(q) * 64;
+        const int col = A.cis[pos];
+        const int i = transposed ? col : r;
+        const int j = transposed ? r : col;
+        vs[pos] = (vs[pos] * dr[i]) * dc[j];
+      }
+    }
+  }
 }
 
 // c~ = D2 c, l~ = l / D2, u~ = u / D2, q~ = D1 q

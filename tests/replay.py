@@ -17,6 +17,14 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def row_bound(A, v):
+    """Largest difference between two float64 sums of row i of A v in any orders: each is
+    within (len_i - 1) u (|A||v|)_i of the exact value (u = eps / 2), so their difference is
+    within len_i eps (|A||v|)_i; never below 1e-13 of (|A||v|)_i."""
+    lens = np.diff(A.indptr).astype(np.float64)
+    return np.maximum(1e-13, lens * EPS) * (abs(A) @ np.abs(v)) + 1e-300
+
+
 def _step_bounds(Kt, KtT, ct, qt, a, xp, yp, eta, omega):
     """Elementwise bounds on the difference between two float64 evaluations of one PDHG step
     (Eq. (3)) from the same state a with step eta and weight omega, whose products sum in

@@ -19,7 +19,7 @@ from scipy.optimize import linprog
 import paper_2106_04756_amd as P
 from oracle import pdlp_oracle as O
 from workloads import lpgen
-from replay import rel, replay_steps, say
+from replay import rel, replay_steps, row_bound, say
 
 pytestmark = pytest.mark.gpu
 
@@ -71,6 +71,45 @@ def test_spmv_matches_scipy_on_ragged_shapes(panels, order):
         refT = K.T @ y
         scaleT = abs(K.T) @ np.abs(y)
         assert np.all(np.abs(outT.cpu().numpy() - refT) <= 1e-13 * scaleT + 1e-300)
+
+
+LDS_MODES = {
+    # one panel per 64-column slice, every gather from LDS
+    "slices": dict(xcd_panels=1, lds_gather=1, lds_entries=64),
+    # XCD panels, hot columns first, each panel's first 50 columns staged, the rest from memory
+    "xcd_stage": dict(xcd_panels=1, column_order=1, lds_gather=2, lds_entries=50),
+}
+
+
+@pytest.mark.parametrize("mode", sorted(LDS_MODES))
+def test_spmv_with_lds_stage_matches_scipy(mode):
+    """Products with the gathered operand staged in LDS: rows of every lane width up to the
+    512-entry limit of the LDS path, empty rows and columns, several tasks per segment."""
+    import torch
+    rng = np.random.default_rng(9)
+    m, n = 2500, 9000
+    lens = np.concatenate([rng.poisson(6, m - 8), [0, 0, 1, 64, 65, 200, 511, 512]])
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        cs = rng.choice(n - 3, size=ln, replace=False)       # the last 3 columns stay empty
+        rows.append(np.full(cs.size, i))
+        cols.append(cs)
+    K = sp.csr_matrix((rng.standard_normal(int(lens.sum())), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(m, n))
+    K.sort_indices()
+    lp = lpgen.from_csr(K, np.ones(n), np.zeros(m), np.zeros(n), np.full(n, 1.0), n_eq=0)
+    say("spmv lds", mode, m, n, K.nnz)
+    s = make(lp, ruiz_iters=0, pock_chambolle=0, **LDS_MODES[mode])
+    for trial in range(2):
+        x = rng.standard_normal(n)
+        y = rng.standard_normal(m)
+        out = torch.empty(m, dtype=torch.float64, device="cuda")
+        s.spmv(torch.from_numpy(x).cuda(), out)
+        assert np.all(np.abs(out.cpu().numpy() - K @ x) <= row_bound(K, x))
+        outT = torch.empty(n, dtype=torch.float64, device="cuda")
+        s.spmv(torch.from_numpy(y).cuda(), outT, transpose=True)
+        KT = K.T.tocsr()
+        assert np.all(np.abs(outT.cpu().numpy() - KT @ y) <= row_bound(KT, y))
 
 
 @pytest.mark.parametrize("panels", [0, 1])
@@ -167,6 +206,17 @@ def test_replayed_step_parity(maker):
 ])
 def test_replayed_step_parity_xcd_panels(maker):
     _replay_parity(maker(), xcd_panels=1)
+
+
+@pytest.mark.parametrize("mode", sorted(LDS_MODES))
+@pytest.mark.parametrize("maker", [lpgen.tiny_lp, lambda: lpgen.large_plain(21, 400, 900)])
+def test_replayed_step_parity_lds_stage(maker, mode):
+    _replay_parity(maker(), **LDS_MODES[mode])
+
+
+@pytest.mark.parametrize("mode", sorted(LDS_MODES))
+def test_trajectory_parity_tiny_lp_lds_stage(mode):
+    _trajectory_parity(lpgen.tiny_lp(), **LDS_MODES[mode])
 
 
 @pytest.mark.parametrize("maker", [lpgen.tiny_lp, lambda: lpgen.large_plain(21, 400, 900)])
@@ -288,7 +338,8 @@ def test_two_runs_are_bitwise_equal_and_resume_is_seamless(panels):
     assert ia["iterations"] == ib["iterations"] == 300 and ia["omega"] == ib["omega"]
 
 
-@pytest.mark.parametrize("kw", [dict(), dict(xcd_panels=1), dict(step_policy=2)])
+@pytest.mark.parametrize("kw", [dict(), dict(xcd_panels=1), dict(step_policy=2),
+                                dict(LDS_MODES["slices"]), dict(LDS_MODES["xcd_stage"], step_policy=2)])
 def test_graph_replay_equals_kernel_by_kernel(kw):
     """Blocks replayed as captured HIP graphs give bit-identical iterates, counters and every
     attempt and check record (each block's replay is compared) as launching kernel by kernel,

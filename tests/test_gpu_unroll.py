@@ -55,7 +55,8 @@ def gpu_grad(s, lp, x_tgt, T, segment, eta, omega, gy=None):
     return x, y, gc, gq
 
 
-@pytest.mark.parametrize("segment,kw", [(0, {}), (7, {}), (7, dict(xcd_panels=1, column_order=1))])
+@pytest.mark.parametrize("segment,kw", [(0, {}), (7, {}), (7, dict(xcd_panels=1, column_order=1)),
+                                        (7, dict(xcd_panels=1, lds_gather=1, lds_entries=64))])
 def test_unroll_matches_oracle_small(segment, kw):
     lp = lpgen.tiny_lp()
     rng = np.random.default_rng(40)

@@ -21,7 +21,7 @@ import pytest
 
 import paper_2106_04756_amd as P
 from oracle import pdlp_oracle as O
-from replay import replay_steps, say
+from replay import replay_steps, row_bound, say
 from workloads import lpgen
 
 pytestmark = pytest.mark.gpu
@@ -37,14 +37,6 @@ def _gpu():
     P.lib()
 
 
-def _row_bound(A, v):
-    """Largest difference between two float64 sums of row i of A v in any orders: each is
-    within (len_i - 1) u (|A||v|)_i of the exact value (u = eps / 2), so their difference is
-    within len_i eps (|A||v|)_i; never below 1e-13 of (|A||v|)_i."""
-    lens = np.diff(A.indptr).astype(np.float64)
-    return np.maximum(1e-13, lens * np.finfo(np.float64).eps) * (abs(A) @ np.abs(v)) + 1e-300
-
-
 def _products(s, K, seed):
     """K x and K^T y of the solver's (unscaled) matrix against scipy, element by element."""
     import torch
@@ -54,11 +46,11 @@ def _products(s, K, seed):
     y = rng.standard_normal(m)
     out = torch.empty(m, dtype=torch.float64, device="cuda")
     s.spmv(torch.from_numpy(x).cuda(), out)
-    assert np.all(np.abs(out.cpu().numpy() - K @ x) <= _row_bound(K, x))
+    assert np.all(np.abs(out.cpu().numpy() - K @ x) <= row_bound(K, x))
     outT = torch.empty(n, dtype=torch.float64, device="cuda")
     s.spmv(torch.from_numpy(y).cuda(), outT, transpose=True)
     KT = K.T.tocsr()
-    assert np.all(np.abs(outT.cpu().numpy() - KT @ y) <= _row_bound(KT, y))
+    assert np.all(np.abs(outT.cpu().numpy() - KT @ y) <= row_bound(KT, y))
 
 
 def _unscaled_case(lp, steps=2):
