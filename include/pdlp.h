@@ -99,9 +99,10 @@ typedef struct pdlp_options {
                                     update's) at k = 2, 4, 8, ...: 0 (off)                    */
   int32_t lds_gather;            /* operand of a product in panels staged in LDS (one
                                     workgroup of 1024 threads per CU): -1 automatic (default:
-                                    slices of lds_entries columns, one panel each, for a copy
-                                    whose columns keep their order, when its panel rows stay
-                                    below 0.4 of its nonzeros), 0 off,
+                                    the hot-first K~ copy stages each XCD panel's first
+                                    lds_entries columns; a copy whose columns keep their order
+                                    gets slices of lds_entries columns, one panel each, when
+                                    its panel rows stay below 0.4 of its nonzeros), 0 off,
                                     1 the slices whenever a copy is in panels, 2 XCD panels
                                     with each panel's first lds_entries columns staged.  Never
                                     for a copy with a panel row longer than 512 nonzeros.      */

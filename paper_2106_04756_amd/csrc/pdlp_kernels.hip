@@ -289,70 +289,94 @@ __device__ __forceinline__ void gather_all(const LdsGather& g, const int32_t (&c
 // One wavefront task: rows perm[D.a .. D.a + D.b) (panel rows D.a .. in panel mode), each by a
 // group of L = 2^p lanes, E entries per lane (E L >= every row length of the task), read from
 // the task's interleaved entries at `off` (each of the E loads covers 64 consecutive slots).
-// All E loads, then all gathers, are in flight together; entries past the row end are masked
-// to +0.0, which leaves the sum bit-identical for any E.
-template <int MODE, int E, class Epi, class G>
+// R rounds of rows at a time: all their loads, then all their gathers, are in flight
+// together.  Entries past a row end are masked to +0.0, which leaves each row's sum
+// bit-identical for any E and R; rows reach the epilogue in task order for any R.
+template <int MODE, int E, int R, class Epi, class G>
 __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi& epi,
                                           double (&acc)[Epi::N], const RowDesc& D, int64_t off, int lane64) {
   const int lg = D.kind_l >> 8, L = 1 << lg;
   const int g = lane64 >> lg, lane = lane64 & (L - 1);
   const int per_round = 64 >> lg;
   int64_t blk = off + lane64;
-  for (int base = 0; base < D.b; base += per_round, blk += 64 * E) {
-    const int slot = base + g;
-    const bool active = slot < D.b;
-    int r = 0;
-    double s = 0.0;
-    if (active) {
-      r = A.perm ? A.perm[D.a + slot] : D.a + slot;
-      const int64_t len = A.rp[r + 1] - A.rp[r];
-      if (len > 0) {
-        double v[E];
-        int32_t c[E];
+  for (int base = 0; base < D.b; base += R * per_round, blk += int64_t(R) * 64 * E) {
+    int r[R];
+    int64_t len[R];
+    bool active[R];
+    double v[R][E];
+    int32_t c[R][E];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int slot = base + q * per_round + g;
+      active[q] = slot < D.b;
+      r[q] = 0;
+      len[q] = 0;
+      if (active[q]) {
+        r[q] = A.perm ? A.perm[D.a + slot] : D.a + slot;
+        len[q] = A.rp[r[q] + 1] - A.rp[r[q]];
 #pragma unroll
         for (int k = 0; k < E; ++k) {
-          v[k] = A.vs[blk + int64_t(k) * 64];
-          if constexpr (MODE == kProd) c[k] = A.cis[blk + int64_t(k) * 64];
-        }
-        if constexpr (MODE == kProd) {
-          double xv[E];
-          gather_all<E>(x, c, xv);
-#pragma unroll
-          for (int k = 0; k < E; ++k) {
-            const double t = v[k] * xv[k];
-            s = s + ((k * L + lane < len) ? t : 0.0);
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < E; ++k) s = comb<MODE>(s, (k * L + lane < len) ? fabs(v[k]) : 0.0);
+          v[q][k] = A.vs[blk + int64_t(q * E + k) * 64];
+          if constexpr (MODE == kProd) c[q][k] = A.cis[blk + int64_t(q * E + k) * 64];
         }
       }
     }
-    for (int off2 = L >> 1; off2 > 0; off2 >>= 1) s = comb<MODE>(s, __shfl_xor(s, off2, 64));
-    if (active && lane == 0) {
-      double cc[Epi::N];
-      epi.row(r, s, cc);
+    double s[R];
+    if constexpr (MODE == kProd) {
+      double xv[R][E];
 #pragma unroll
-      for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
+      for (int q = 0; q < R; ++q)
+        if (active[q]) gather_all<E>(x, c[q], xv[q]);
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        s[q] = 0.0;
+        if (active[q]) {
+#pragma unroll
+          for (int k = 0; k < E; ++k) {
+            const double t = v[q][k] * xv[q][k];
+            s[q] = s[q] + ((k * L + lane < len[q]) ? t : 0.0);
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < R; ++q) {
+        s[q] = 0.0;
+        if (active[q]) {
+#pragma unroll
+          for (int k = 0; k < E; ++k) s[q] = comb<MODE>(s[q], (k * L + lane < len[q]) ? fabs(v[q][k]) : 0.0);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      for (int o = L >> 1; o > 0; o >>= 1) s[q] = comb<MODE>(s[q], __shfl_xor(s[q], o, 64));
+      if (active[q] && lane == 0) {
+        double cc[Epi::N];
+        epi.row(r[q], s[q], cc);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
+      }
     }
   }
 }
 
 // wave_task with the entries per lane of the task (uniform across the wavefront).
-template <int MODE, class Epi, class G>
+template <int MODE, int R = 1, class Epi, class G>
 __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const Epi& epi,
                                             double (&acc)[Epi::N], int t, int lane64) {
   const RowDesc D = A.wave[t];
   const int64_t off = A.task_off[t];
   switch (D.aux) {
-    case 1: wave_task<MODE, 1>(A, x, epi, acc, D, off, lane64); break;
-    case 2: wave_task<MODE, 2>(A, x, epi, acc, D, off, lane64); break;
-    case 3: wave_task<MODE, 3>(A, x, epi, acc, D, off, lane64); break;
-    case 4: wave_task<MODE, 4>(A, x, epi, acc, D, off, lane64); break;
-    case 5: wave_task<MODE, 5>(A, x, epi, acc, D, off, lane64); break;
-    case 6: wave_task<MODE, 6>(A, x, epi, acc, D, off, lane64); break;
-    case 7: wave_task<MODE, 7>(A, x, epi, acc, D, off, lane64); break;
-    default: wave_task<MODE, kElemsPerLane>(A, x, epi, acc, D, off, lane64); break;
+    case 1: wave_task<MODE, 1, R>(A, x, epi, acc, D, off, lane64); break;
+    case 2: wave_task<MODE, 2, R>(A, x, epi, acc, D, off, lane64); break;
+    case 3: wave_task<MODE, 3, R>(A, x, epi, acc, D, off, lane64); break;
+    case 4: wave_task<MODE, 4, R>(A, x, epi, acc, D, off, lane64); break;
+    // one round at a time above 4 entries per lane (two would exceed the registers)
+    case 5: wave_task<MODE, 5, 1>(A, x, epi, acc, D, off, lane64); break;
+    case 6: wave_task<MODE, 6, 1>(A, x, epi, acc, D, off, lane64); break;
+    case 7: wave_task<MODE, 7, 1>(A, x, epi, acc, D, off, lane64); break;
+    default: wave_task<MODE, kElemsPerLane, 1>(A, x, epi, acc, D, off, lane64); break;
   }
 }
 
@@ -944,7 +968,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_lds_rows(CsrDev A, DevState* st, 
     for (int i = threadIdx.x; i < h; i += kLdsBlock) stage[i] = in[c0 + i];
     __syncthreads();
     const LdsGather gx{stage, in, c0, uint32_t(h)};
-    for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd>(A, gx, epi, acc, t, lane64);
+    for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd, 2>(A, gx, epi, acc, t, lane64);
   }
 }
 
