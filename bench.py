@@ -204,10 +204,12 @@ def measure_steps(P, torch, lp, W, K):
     total_bytes = [prim_products * bytes_primal + (d_att - prim_products) * bytes_primal_epi,
                    dual_products * bytes_dual]
     dom = 0 if times[0] >= times[1] else 1
-    name = ["primal step: K~^T y product fused with the primal update (k_panel_rows<1> + k_primal_combine "
-            "in XCD-panel mode, else k_primal)",
-            "dual step: K~ x' product fused with the dual update and the step rule (k_panel_rows<0> + "
-            "k_dual_combine in XCD-panel mode, else k_dual)"][dom]
+    name = ["primal step: K~^T y product fused with the primal update (first pass k_lds_rows<1> with "
+            "the operand staged in LDS, else k_panel_rows<1>, then k_primal_combine; k_primal in the "
+            "plain layout)",
+            "dual step: K~ x' product fused with the dual update and the step rule (first pass "
+            "k_lds_rows<0> with the operand staged in LDS, else k_panel_rows<0>, then k_dual_combine; "
+            "k_dual in the plain layout)"][dom]
     avg_ms = times[dom] / counts[dom]
     bpl = total_bytes[dom] / counts[dom]
     achieved = bpl / (avg_ms * 1e-3) / 1e9
