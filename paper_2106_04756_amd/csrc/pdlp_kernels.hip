@@ -477,8 +477,20 @@ __device__ void combine_rows(const CsrDev& A, const double* __restrict__ part,
     if (stored) {
       s = stored[r];
     } else {
+      // eight partial values at a time: indices clamped into the row, all loads in flight
+      // together, then added in slot order; the padding adds +0.0, which leaves s unchanged
+      // (s starts at +0.0, so it is never -0.0; the partial values of max are >= 0)
       const int64_t j1 = A.slot_ptr[r + 1];
-      for (int64_t j = A.slot_ptr[r]; j < j1; ++j) s = comb<MODE>(s, part[A.slot_idx[j]]);
+      for (int64_t j = A.slot_ptr[r]; j < j1; j += 8) {
+        int32_t k[8];
+        double p[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) k[q] = A.slot_idx[j + q < j1 ? j + q : j1 - 1];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) p[q] = part[k[q]];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) s = comb<MODE>(s, j + q < j1 ? p[q] : 0.0);
+      }
     }
     double c[Epi::N];
     epi.row(r, s, c);
