@@ -23,6 +23,8 @@ struct CsrDev {
   const int64_t* task_off;     // interleaved entries of wavefront task t from task_off[t]
   const double* vs;            // (build_interleaved); the CSR arrays serve workgroup tasks
   const int32_t* cis;
+  const uint16_t* cis16;       // slices only: the interleaved columns relative to the slice
+  const uint16_t* rlen;        // length of each row of the layout (wavefront rows: <= 512)
   const int32_t* wave_begin;   // npanel + 1 task offsets per panel
   const int32_t* block_begin;
   const int32_t* prow_row;     // panel mode: original row of each panel row

@@ -265,6 +265,15 @@ struct LdsGather {
   int32_t c0;
   uint32_t h;
 };
+// A slice wholly in LDS, addressed by columns relative to the slice.
+struct StageGather {
+  const double* stage;
+};
+template <int E>
+__device__ __forceinline__ void gather_all(const StageGather& g, const int32_t (&c)[E], double (&xv)[E]) {
+#pragma unroll
+  for (int k = 0; k < E; ++k) xv[k] = g.stage[c[k]];
+}
 template <int E>
 __device__ __forceinline__ void gather_all(const GlobalGather& g, const int32_t (&c)[E], double (&xv)[E]) {
 #pragma unroll
@@ -292,7 +301,8 @@ __device__ __forceinline__ void gather_all(const LdsGather& g, const int32_t (&c
 // R rounds of rows at a time: all their loads, then all their gathers, are in flight
 // together.  Entries past a row end are masked to +0.0, which leaves each row's sum
 // bit-identical for any E and R; rows reach the epilogue in task order for any R.
-template <int MODE, int E, int R, class Epi, class G>
+// LOCAL: columns from the 16-bit slice-relative copy (slices, gathered from the stage).
+template <int MODE, int E, int R, bool LOCAL, class Epi, class G>
 __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi& epi,
                                           double (&acc)[Epi::N], const RowDesc& D, int64_t off, int lane64) {
   const int lg = D.kind_l >> 8, L = 1 << lg;
@@ -313,11 +323,14 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
       len[q] = 0;
       if (active[q]) {
         r[q] = A.perm ? A.perm[D.a + slot] : D.a + slot;
-        len[q] = A.rp[r[q] + 1] - A.rp[r[q]];
+        len[q] = A.rlen[r[q]];
 #pragma unroll
         for (int k = 0; k < E; ++k) {
           v[q][k] = A.vs[blk + int64_t(q * E + k) * 64];
-          if constexpr (MODE == kProd) c[q][k] = A.cis[blk + int64_t(q * E + k) * 64];
+          if constexpr (MODE == kProd) {
+            if constexpr (LOCAL) c[q][k] = A.cis16[blk + int64_t(q * E + k) * 64];
+            else c[q][k] = A.cis[blk + int64_t(q * E + k) * 64];
+          }
         }
       }
     }
@@ -362,21 +375,21 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
 }
 
 // wave_task with the entries per lane of the task (uniform across the wavefront).
-template <int MODE, int R = 1, class Epi, class G>
+template <int MODE, int R = 1, bool LOCAL = false, class Epi, class G>
 __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const Epi& epi,
                                             double (&acc)[Epi::N], int t, int lane64) {
   const RowDesc D = A.wave[t];
   const int64_t off = A.task_off[t];
   switch (D.aux) {
-    case 1: wave_task<MODE, 1, R>(A, x, epi, acc, D, off, lane64); break;
-    case 2: wave_task<MODE, 2, R>(A, x, epi, acc, D, off, lane64); break;
-    case 3: wave_task<MODE, 3, R>(A, x, epi, acc, D, off, lane64); break;
-    case 4: wave_task<MODE, 4, R>(A, x, epi, acc, D, off, lane64); break;
+    case 1: wave_task<MODE, 1, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 2: wave_task<MODE, 2, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 3: wave_task<MODE, 3, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 4: wave_task<MODE, 4, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
     // one round at a time above 4 entries per lane (two would exceed the registers)
-    case 5: wave_task<MODE, 5, 1>(A, x, epi, acc, D, off, lane64); break;
-    case 6: wave_task<MODE, 6, 1>(A, x, epi, acc, D, off, lane64); break;
-    case 7: wave_task<MODE, 7, 1>(A, x, epi, acc, D, off, lane64); break;
-    default: wave_task<MODE, kElemsPerLane, 1>(A, x, epi, acc, D, off, lane64); break;
+    case 5: wave_task<MODE, 5, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 6: wave_task<MODE, 6, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 7: wave_task<MODE, 7, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    default: wave_task<MODE, kElemsPerLane, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
   }
 }
 
@@ -979,8 +992,13 @@ __global__ __launch_bounds__(kLdsBlock) void k_lds_rows(CsrDev A, DevState* st, 
     if (sg > s0) __syncthreads();        // every wavefront is done with the previous stage
     for (int i = threadIdx.x; i < h; i += kLdsBlock) stage[i] = in[c0 + i];
     __syncthreads();
-    const LdsGather gx{stage, in, c0, uint32_t(h)};
-    for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd, 2>(A, gx, epi, acc, t, lane64);
+    if (A.cis16) {            // a slice: every column is in the stage
+      const StageGather gx{stage};
+      for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd, 2, true>(A, gx, epi, acc, t, lane64);
+    } else {
+      const LdsGather gx{stage, in, c0, uint32_t(h)};
+      for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd, 2>(A, gx, epi, acc, t, lane64);
+    }
   }
 }
 

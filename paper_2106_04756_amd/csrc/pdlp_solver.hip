@@ -237,16 +237,42 @@ int upload_tasks(pdlp_solver* s, const Schedule& sc, CsrDev& A) {
   return 0;
 }
 
-// Uploads the interleaved entries of a layout's wavefront tasks (build_interleaved).
-int upload_interleaved(pdlp_solver* s, const Schedule& sc, const int64_t* rp, const int32_t* ci,
-                       const double* v, const int32_t* perm, CsrDev& A, double** vsdev) {
+// Uploads the interleaved entries of a layout's wavefront tasks (build_interleaved), the
+// 16-bit length of each of its nrows rows and, for slices (panel cuts `cut`, tasks of panel p
+// from wave_begin[p]), the interleaved columns relative to the task's slice.
+int upload_interleaved(pdlp_solver* s, const Schedule& sc, const int64_t* rp, int64_t nrows, const int32_t* ci,
+                       const double* v, const int32_t* perm, CsrDev& A, double** vsdev,
+                       const std::vector<int32_t>* cut = nullptr, const std::vector<int32_t>* wave_begin = nullptr) {
   int rc;
   std::vector<int64_t> off;
   std::vector<int32_t> cis;
   std::vector<double> vs;
   build_interleaved(sc, rp, ci, v, perm, off, cis, vs);
+  std::vector<uint16_t> rlen(static_cast<size_t>(nrows));
+  for (int64_t r = 0; r < nrows; ++r) rlen[size_t(r)] = uint16_t(std::min<int64_t>(rp[r + 1] - rp[r], 65535));
+  A.cis16 = nullptr;
+  if (cut) {
+    std::vector<uint16_t> cis16(cis.size(), 0);
+    const int P = int(cut->size()) - 1;
+    for (int p = 0; p < P; ++p) {
+      const int32_t c0 = (*cut)[size_t(p)], w = (*cut)[size_t(p) + 1] - c0;
+      if (w > 65536) {
+        s->err = "internal error: slice wider than 16-bit columns";
+        return PDLP_ERR_DEVICE;
+      }
+      for (int t = (*wave_begin)[size_t(p)]; t < (*wave_begin)[size_t(p) + 1]; ++t)
+        for (int64_t q = off[size_t(t)]; q < off[size_t(t) + 1]; ++q) {
+          const int32_t d = cis[size_t(q)] - c0;       // slots of missing rows hold column 0
+          cis16[size_t(q)] = uint16_t(d >= 0 && d < w ? d : 0);
+        }
+    }
+    const uint16_t* d16;
+    if ((rc = upload_vec(s, cis16, &d16))) return rc;
+    A.cis16 = d16;
+  }
   const double* dvs;
-  if ((rc = upload_vec(s, off, &A.task_off)) || (rc = upload_vec(s, cis, &A.cis)) || (rc = upload_vec(s, vs, &dvs)))
+  if ((rc = upload_vec(s, off, &A.task_off)) || (rc = upload_vec(s, cis, &A.cis)) || (rc = upload_vec(s, vs, &dvs)) ||
+      (rc = upload_vec(s, rlen, &A.rlen)))
     return rc;
   A.vs = dvs;
   *vsdev = const_cast<double*>(dvs);
@@ -267,6 +293,7 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
   const int G = std::max(1, s->maxG / 8);          // one LDS workgroup per CU
   PanelLayout PL;
   bool panel = false;
+  bool slices = false;
   int lds_h = 0;
   const bool want = nnz > 0 && (mode == 1 || (mode < 0 && ncols * 8 > (int64_t(4) << 20)));
   if (want && (lmode == 1 || (lmode < 0 && !hot_first))) {
@@ -279,7 +306,10 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
       for (int64_t p = 0; p <= Pw; ++p) wc[size_t(p)] = int32_t(std::min<int64_t>(p * W, ncols));
       panel = build_panels(rp, ci, nrows, ncols, int(Pw), lmode == 1 ? 1e300 : kLdsRowFrac, PL, &wc) &&
               PL.sched.block.empty();
-      if (panel) lds_h = W;
+      if (panel) {
+        lds_h = W;
+        slices = true;
+      }
     }
   }
   if (!panel && want) {
@@ -317,7 +347,8 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
       vP[size_t(k)] = v[PL.src[size_t(k)]];
     }
     std::vector<int64_t>().swap(PL.src);
-    if ((rc = upload_interleaved(s, PL.sched, PL.prow_ptr.data(), ciP.data(), vP.data(), nullptr, A, vsdev)))
+    if ((rc = upload_interleaved(s, PL.sched, PL.prow_ptr.data(), nprow, ciP.data(), vP.data(), nullptr, A, vsdev,
+                                 slices ? &PL.cut : nullptr, &PL.wave_begin)))
       return rc;
     if ((rc = upload_vec(s, PL.prow_ptr, &A.rp)) || (rc = upload_vec(s, ciP, &A.ci))) return rc;
     const double* dv;
@@ -337,7 +368,7 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
     return 0;
   }
   Schedule sc = build_schedule(rp, nrows);
-  if ((rc = upload_interleaved(s, sc, rp, ci, v, sc.perm.empty() ? nullptr : sc.perm.data(), A, vsdev)))
+  if ((rc = upload_interleaved(s, sc, rp, nrows, ci, v, sc.perm.empty() ? nullptr : sc.perm.data(), A, vsdev)))
     return rc;
   std::vector<int64_t> hrp(rp, rp + nrows + 1);
   std::vector<int32_t> hci(ci, ci + nnz);
