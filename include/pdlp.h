@@ -106,8 +106,8 @@ typedef struct pdlp_options {
                                     1 the slices whenever a copy is in panels, 2 XCD panels
                                     with each panel's first lds_entries columns staged.  Never
                                     for a copy with a panel row longer than 512 nonzeros.      */
-  int32_t lds_entries;           /* operand entries staged per panel: 0 = 15360 (the most;
-                                    120 KiB of LDS), else 1 .. 15360                           */
+  int32_t lds_entries;           /* operand entries staged per panel: 0 = 19456 (the most;
+                                    152 KiB of LDS), else 1 .. 19456                           */
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

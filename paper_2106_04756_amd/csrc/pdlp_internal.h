@@ -21,13 +21,13 @@ constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
 constexpr double kPanelRowFrac = 0.4;
 constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per XCD of an MI355X)
 // LDS-staged products: one workgroup of kLdsBlock threads per CU holds up to kLdsEntries
-// entries of the gathered vector (120 KiB of the CU's 160 KiB of LDS).  A copy whose
+// entries of the gathered vector (152 KiB of the CU's 160 KiB of LDS).  A copy whose
 // gathered vector, cut into slices of that width, costs at most kLdsRowFrac panel rows per
 // nonzero gets one panel per slice and gathers only from LDS; otherwise a copy in XCD panels
 // whose columns are ordered hot-first stages each panel's first kLdsEntries columns.
 constexpr int kLdsBlock = 1024;
 constexpr int kLdsWaves = kLdsBlock / 64;
-constexpr int kLdsEntries = 15360;
+constexpr int kLdsEntries = 19456;
 constexpr int kMaxLdsPanels = 4096;
 constexpr double kLdsRowFrac = 0.4;
 

@@ -298,8 +298,9 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
   const bool want = nnz > 0 && (mode == 1 || (mode < 0 && ncols * 8 > (int64_t(4) << 20)));
   if (want && (lmode == 1 || (lmode < 0 && !hot_first))) {
     // one panel per W-wide slice of the gathered vector: every gather from LDS.  Automatic
-    // for a copy whose columns keep their order (on the 1e6 x 2e6 LP, K~^T y takes 0.80 ms in
-    // slices, 0.94 ms in XCD panels, 0.98 ms with a hot stage)
+    // for a copy whose columns keep their order, whose gathers have no hot entries to stage
+    // (on the 1e6 x 2e6 LP, K~^T y was fastest this way: 0.80 ms in slices against 0.94 ms in
+    // XCD panels and 0.98 ms with a hot stage, measured together)
     const int64_t Pw = (ncols + W - 1) / W;
     if (Pw >= 2 && Pw <= kMaxLdsPanels) {
       std::vector<int32_t> wc(size_t(Pw) + 1);
@@ -315,8 +316,8 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
   if (!panel && want) {
     panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts);
     // the first W columns of each panel staged in LDS: its hottest when the columns are
-    // ordered hot-first, automatic for such a copy (on the 1e6 x 2e6 LP, K~ x takes 0.55 ms
-    // with the stage, 0.89 ms without, 1.21 ms in slices)
+    // ordered hot-first, automatic for such a copy (on the 1e6 x 2e6 LP, K~ x took 0.55 ms
+    // with the stage against 0.89 ms without and 1.21 ms in slices, measured together)
     if (panel && PL.sched.block.empty() && (lmode == 2 || (lmode < 0 && hot_first))) lds_h = W;
   }
   A.nrows_orig = int32_t(nrows);

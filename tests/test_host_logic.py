@@ -164,7 +164,7 @@ def test_create_rejects_bad_sizes_and_options():
         _create(lp, pw_power_of_two=1)
     with pytest.raises(P.PdlpError, match="options"):
         _create(lp, step_policy=3)
-    for bad in (dict(lds_gather=3), dict(lds_gather=-2), dict(lds_entries=-1), dict(lds_entries=15361)):
+    for bad in (dict(lds_gather=3), dict(lds_gather=-2), dict(lds_entries=-1), dict(lds_entries=19457)):
         with pytest.raises(P.PdlpError, match="options"):
             _create(lp, **bad)
 
