@@ -126,6 +126,68 @@ def bench_batched(P, lpgen, count, iter_limit, plain_sample=16):
             "speedup_vs_plain": (conv / secs) / (pconv / pdt) if pconv else None}
 
 
+def bench_step_policies(P, torch, lp, W=100, K=400):
+    """PDHG iters/s on the bench LP under the other step policies (constant step, the
+    Malitsky-Pock line search of Appendix C), each timed over K steps after W, with the
+    attempts (line-search trials) per accepted step."""
+    out = {}
+    for name, kw in (("constant", dict(step_policy=1)), ("malitsky_pock", dict(step_policy=2))):
+        s = P.Solver.from_lp(lp, **kw)
+        s.solve(1e-8, W)
+        i0 = s.info()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.solve(1e-8, W + K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        i1 = s.info()
+        s.close()
+        steps = i1["iterations"] - i0["iterations"]
+        out[name] = {"iters_per_s": steps / dt, "steps": steps, "seconds": dt,
+                     "attempts_per_step": (i1["attempts"] - i0["attempts"]) / max(steps, 1)}
+        log(f"step policy {name}: {steps / dt:.1f} iters/s, "
+            f"{out[name]['attempts_per_step']:.2f} attempts per step")
+    return out
+
+
+# The switches of the paper's ablations (Appendix C), as solver options.
+ABLATIONS = {
+    "pdlp": {},
+    "constant_step": dict(step_policy=1),
+    "no_restarts": dict(adaptive_restarts=0),
+    "no_restarts_weight_at_2j": dict(adaptive_restarts=0, pw_power_of_two=1),
+    "restart_theory": dict(beta_sufficient=0.37, beta_necessary=0.37, restart_to_current=0),
+    "fixed_weight": dict(primal_weight_update=0),
+    "no_scaling": dict(ruiz_iters=0, pock_chambolle=0),
+    "ruiz_only": dict(pock_chambolle=0),
+    "malitsky_pock": dict(step_policy=2),
+}
+
+
+def bench_ablations(P, lpgen, tol=1e-8, iter_limit=50000):
+    """The ablation switches on two synthetic LPs: PDHG steps (K~ and K~^T products) and seconds
+    to the relative KKT error tol, or the iteration limit."""
+    lps = {"tiny": lpgen.tiny_lp(),
+           "pagerank_2e4": lpgen.pagerank_lp(2, 20000, name="PageRank LP 2e4 nodes out-degree 8")}
+    out = {"tol": tol, "iter_limit": iter_limit,
+           "workloads": {k: f"{lp.name} (nnz {lp.nnz})" for k, lp in lps.items()}, "runs": {}}
+    for name, kw in ABLATIONS.items():
+        row = {}
+        for key, lp in lps.items():
+            s = P.Solver.from_lp(lp, **kw)
+            t0 = time.perf_counter()
+            st = s.solve(tol, iter_limit)
+            dt = time.perf_counter() - t0
+            inf = s.info()
+            s.close()
+            row[key] = {"status": P.STATUS_NAMES[st], "iterations": inf["iterations"],
+                        "spmv": inf["spmv_K"] + inf["spmv_KT"], "kkt": inf["kkt"][3], "seconds": dt}
+        out["runs"][name] = row
+        log(f"ablation {name}: " + ", ".join(f"{k} {v['status']} {v['iterations']} steps {v['seconds']:.2f}s"
+                                             for k, v in row.items()))
+    return out
+
+
 def bench_unroll(P, lpgen, T=500, segment=50, reps=5):
     """Unrolled PDHG on the unroll LP (m=2e4, n=5e4, 6 nonzeros per column): wall time of the
     forward pass (T fixed steps) and of the adjoint (with checkpoint recomputation), median of
@@ -269,6 +331,8 @@ def main():
     ap.add_argument("--no-unroll", action="store_true")
     ap.add_argument("--no-truncated", action="store_true",
                     help="skip the large LP with column counts truncated to [1,190]")
+    ap.add_argument("--no-policies", action="store_true", help="skip the other step policies")
+    ap.add_argument("--no-ablations", action="store_true", help="skip the ablation switches")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-iter-limit", type=int, default=20000)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -353,6 +417,10 @@ def main():
                             "kkt": i0["kkt"][3]}
     st0.close()
     log(f"tiny LP: {i0['iterations']} iterations to KKT {i0['kkt'][3]:.2e} in {t1 - t0:.3f}s")
+    if not args.no_policies:
+        out["step_policies"] = bench_step_policies(P, torch, lp)
+    if not args.no_ablations:
+        out["ablations"] = bench_ablations(P, lpgen)
     if not args.no_batched:
         out["batched"] = bench_batched(P, lpgen, args.batch_count, args.batch_iter_limit)
     if not args.no_unroll:
