@@ -377,6 +377,44 @@ int pdlp_reset_kernel_times(pdlp_solver *s);
 int pdlp_build_schedule(const int64_t *row_ptr, int64_t nrows, int32_t *desc, int64_t cap,
                         int64_t *ndesc, int64_t *nsplit, int32_t *perm);
 
+/* The column-panel form of a CSR copy as the products read it (pdlp_build_panel_layout).
+ * Counts are set by a call with prow_ptr NULL; a second call with every array allocated by
+ * the caller (the counts below give their lengths; any array may be NULL to skip it) fills
+ * them, and fails if the counts no longer match. */
+typedef struct pdlp_panel_layout {
+  int64_t nprow;        /* panel rows (row r restricted to panel p, nonempty)                */
+  int64_t nwave;        /* wavefront tasks                                                     */
+  int64_t nblock;       /* workgroup tasks (panel rows longer than 512 nonzeros)               */
+  int64_t nslots;       /* interleaved slots of the wavefront tasks                            */
+  int64_t nseg;         /* LDS segments                                                        */
+  int32_t *cut;         /* npanel + 1: column offsets of the panels                            */
+  int64_t *prow_ptr;    /* nprow + 1: offsets of each panel row's nonzeros (panel order)       */
+  int32_t *prow_row;    /* nprow: original row of each panel row                               */
+  int64_t *src;         /* nnz: index in the input CSR of each panel-ordered nonzero           */
+  int64_t *slot_ptr;    /* nrows + 1: panel rows of row r at slot_idx[slot_ptr[r] ..]          */
+  int32_t *slot_idx;    /* nprow: panel rows of each row, in panel order                       */
+  int32_t *wave;        /* 4 nwave: {first panel row, rows, log2(lanes) << 8, entries per lane} */
+  int32_t *wave_begin;  /* npanel + 1: first wavefront task of each panel                      */
+  int64_t *task_off;    /* nwave + 1: first interleaved slot of each wavefront task            */
+  int32_t *cis;         /* nslots: interleaved columns (round i of task t from task_off[t] +
+                           64 E i; entry k of lane j at 64 k + j)                             */
+  double *vs;           /* nslots: interleaved values (0 in padding slots)                     */
+  int32_t *seg_ptr;     /* groups + 1: segments of each LDS workgroup                          */
+  int32_t *seg;         /* 4 nseg: {panel, first task, end task, 0}                             */
+} pdlp_panel_layout;
+
+/*
+ * pdlp_build_panel_layout - host-only (no GPU needed): the panel layout the products use for
+ * the nrows x ncols CSR matrix (row_ptr, col_idx, val): npanel panels cut at `cuts` (npanel
+ * + 1 column offsets) or, if cuts is NULL, at about equal nonzero counts; its interleaved
+ * entries; and the split of its wavefront tasks among `groups` LDS workgroups (aligned: group
+ * b stays on panel b mod npanel, which needs groups to be a multiple of npanel).  Returns 0,
+ * or -1 on invalid arguments or mismatched counts.
+ */
+int pdlp_build_panel_layout(const int64_t *row_ptr, const int32_t *col_idx, const double *val,
+                            int64_t nrows, int64_t ncols, int32_t npanel, const int32_t *cuts,
+                            int32_t groups, int32_t aligned, pdlp_panel_layout *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,6 +8,7 @@
 #include <string>
 #include <vector>
 
+#include "../../include/pdlp.h"
 #include "pdlp_internal.h"
 #include "host_prep.h"
 
@@ -375,5 +376,57 @@ extern "C" int pdlp_build_schedule(const int64_t* row_ptr, int64_t nrows, int32_
     std::memcpy(desc, all.data(), size_t(nc) * sizeof(pdlp::RowDesc));
   }
   if (perm && !s.perm.empty()) std::memcpy(perm, s.perm.data(), s.perm.size() * sizeof(int32_t));
+  return 0;
+}
+
+extern "C" int pdlp_build_panel_layout(const int64_t* row_ptr, const int32_t* col_idx, const double* val,
+                                       int64_t nrows, int64_t ncols, int32_t npanel, const int32_t* cuts,
+                                       int32_t groups, int32_t aligned, pdlp_panel_layout* out) {
+  if (!row_ptr || !col_idx || !val || !out || nrows < 0 || ncols < 1 || npanel < 1 || groups < 1 ||
+      (aligned && groups % npanel != 0))
+    return -1;
+  std::vector<int32_t> given;
+  if (cuts) given.assign(cuts, cuts + npanel + 1);
+  pdlp::PanelLayout L;
+  if (!pdlp::build_panels(row_ptr, col_idx, nrows, ncols, npanel, 1e300, L, cuts ? &given : nullptr)) return -1;
+  const int64_t nnz = row_ptr[nrows];
+  std::vector<int32_t> ciP(static_cast<size_t>(nnz));
+  std::vector<double> vP(static_cast<size_t>(nnz));
+  for (int64_t k = 0; k < nnz; ++k) {
+    ciP[size_t(k)] = col_idx[L.src[size_t(k)]];
+    vP[size_t(k)] = val[L.src[size_t(k)]];
+  }
+  std::vector<int64_t> off;
+  std::vector<int32_t> cis;
+  std::vector<double> vs;
+  pdlp::build_interleaved(L.sched, L.prow_ptr.data(), ciP.data(), vP.data(), nullptr, off, cis, vs);
+  std::vector<pdlp::LdsSeg> seg;
+  const std::vector<int32_t> seg_ptr = pdlp::lds_segments(L, groups, aligned != 0, seg);
+  const bool fill = out->prow_ptr != nullptr;
+  if (fill && (out->nprow != int64_t(L.prow_row.size()) || out->nwave != int64_t(L.sched.wave.size()) ||
+               out->nslots != off.back() || out->nseg != int64_t(seg.size())))
+    return -1;
+  out->nprow = int64_t(L.prow_row.size());
+  out->nwave = int64_t(L.sched.wave.size());
+  out->nblock = int64_t(L.sched.block.size());
+  out->nslots = off.back();
+  out->nseg = int64_t(seg.size());
+  if (!fill) return 0;
+  auto put = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  put(out->cut, L.cut);
+  put(out->prow_ptr, L.prow_ptr);
+  put(out->prow_row, L.prow_row);
+  put(out->src, L.src);
+  put(out->slot_ptr, L.slot_ptr);
+  put(out->slot_idx, L.slot_idx);
+  put(out->wave, L.sched.wave);
+  put(out->wave_begin, L.wave_begin);
+  put(out->task_off, off);
+  put(out->cis, cis);
+  put(out->vs, vs);
+  put(out->seg_ptr, seg_ptr);
+  put(out->seg, seg);
   return 0;
 }

@@ -24,7 +24,7 @@ EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pd
             "pdlp_destroy", "pdlp_last_error", "pdlp_get_state", "pdlp_set_state",
             "pdlp_get_scaling", "pdlp_get_iterate",
             "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
-            "pdlp_build_schedule", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
+            "pdlp_build_schedule", "pdlp_build_panel_layout", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
             "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error",
             "pdlp_unroll_forward", "pdlp_unroll_backward", "pdlp_unroll_get_info"]
 
@@ -134,6 +134,9 @@ def lib() -> ctypes.CDLL:
         L.pdlp_reset_kernel_times.restype = ctypes.c_int
         L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P, P]
         L.pdlp_build_schedule.restype = ctypes.c_int
+        L.pdlp_build_panel_layout.argtypes = [P, P, P, I64, I64, ctypes.c_int32, P, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.POINTER(PanelLayoutC)]
+        L.pdlp_build_panel_layout.restype = ctypes.c_int
         L.pdlp_batch_create.argtypes = [ctypes.POINTER(P), I64, P, P, P, P, P, P, P, P, P, P,
                                         ctypes.POINTER(Options), P]
         L.pdlp_batch_create.restype = ctypes.c_int
@@ -212,6 +215,41 @@ def schedule(row_ptr):
     lib().pdlp_build_schedule(rp.ctypes.data, rp.size - 1, desc.ctypes.data, nd.value,
                               ctypes.byref(nd), ctypes.byref(ns), perm.ctypes.data)
     return desc, ns.value, perm[:rp.size - 1]
+
+
+class PanelLayoutC(ctypes.Structure):
+    _fields_ = [("nprow", ctypes.c_int64), ("nwave", ctypes.c_int64), ("nblock", ctypes.c_int64),
+                ("nslots", ctypes.c_int64), ("nseg", ctypes.c_int64)] + \
+               [(k, ctypes.c_void_p) for k in ("cut", "prow_ptr", "prow_row", "src", "slot_ptr", "slot_idx",
+                                               "wave", "wave_begin", "task_off", "cis", "vs", "seg_ptr", "seg")]
+
+
+def panel_layout(row_ptr, col_idx, val, ncols, npanel, cuts=None, groups=256, aligned=False):
+    """Host-only: the column-panel layout of a CSR matrix as the products read it, its
+    interleaved entries and the LDS workgroups' segments (pdlp_build_panel_layout), as a
+    dict of NumPy arrays."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.float64)
+    nrows = rp.size - 1
+    cu = None if cuts is None else np.ascontiguousarray(cuts, dtype=np.int32)
+    args = (rp.ctypes.data, ci.ctypes.data, v.ctypes.data, nrows, int(ncols), int(npanel),
+            None if cu is None else cu.ctypes.data, int(groups), int(bool(aligned)))
+    L = PanelLayoutC()
+    if lib().pdlp_build_panel_layout(*args, ctypes.byref(L)) != 0:
+        raise PdlpError(-1, "pdlp_build_panel_layout failed")
+    shapes = {"cut": (npanel + 1, np.int32), "prow_ptr": (L.nprow + 1, np.int64), "prow_row": (L.nprow, np.int32),
+              "src": (int(rp[-1]), np.int64), "slot_ptr": (nrows + 1, np.int64), "slot_idx": (L.nprow, np.int32),
+              "wave": ((L.nwave, 4), np.int32), "wave_begin": (npanel + 1, np.int32),
+              "task_off": (L.nwave + 1, np.int64), "cis": (L.nslots, np.int32), "vs": (L.nslots, np.float64),
+              "seg_ptr": (groups + 1, np.int32), "seg": ((L.nseg, 4), np.int32)}
+    out = {k: np.zeros(shp, dtype=dt) for k, (shp, dt) in shapes.items()}
+    for k, a in out.items():
+        setattr(L, k, a.ctypes.data if a.size else None)
+    if lib().pdlp_build_panel_layout(*args, ctypes.byref(L)) != 0:
+        raise PdlpError(-1, "pdlp_build_panel_layout failed")
+    out["nblock"] = L.nblock
+    return out
 
 
 class Solver:

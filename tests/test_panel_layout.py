@@ -1,0 +1,134 @@
+"""Host-only checks of the column-panel layout the products read (pdlp_build_panel_layout):
+the panel rows, their slots, the wavefront tasks, the interleaved entries and the LDS
+workgroups' segments, each against what it must hold, recomputed here in NumPy from the input
+CSR matrix.  No GPU is needed."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import paper_2106_04756_amd as P
+
+
+def _matrix(seed, m, n):
+    """Rows of every class: empty, 1..8 (one lane), up to 512 (a wavefront), one longer (a
+    workgroup task), with empty columns at the end."""
+    rng = np.random.default_rng(seed)
+    lens = rng.choice([0, 1, 2, 3, 5, 9, 17, 40, 130, 512], size=m,
+                      p=[.05, .25, .15, .15, .1, .1, .08, .07, .04, .01])
+    lens[rng.integers(m)] = min(n - 5, 900)
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        cs = rng.choice(n - 5, size=min(ln, n - 5), replace=False)
+        rows.append(np.full(cs.size, i))
+        cols.append(cs)
+    K = sp.csr_matrix((rng.standard_normal(int(sum(c.size for c in cols))),
+                       (np.concatenate(rows), np.concatenate(cols))), shape=(m, n))
+    K.sort_indices()
+    return K
+
+
+def _check(K, L, npanel, groups, aligned, cuts=None):
+    m, n = K.shape
+    rp, ci, v = K.indptr.astype(np.int64), K.indices, K.data
+    nnz = K.nnz
+    cut = L["cut"]
+    assert cut[0] == 0 and cut[-1] == n and np.all(np.diff(cut) >= 0)
+    if cuts is not None:
+        assert np.array_equal(cut, cuts)
+    # every nonzero once; each panel row a run of one row inside one panel
+    src = L["src"]
+    assert np.array_equal(np.sort(src), np.arange(nnz))
+    pp, prow_row = L["prow_ptr"], L["prow_row"]
+    assert pp[0] == 0 and pp[-1] == nnz and np.all(np.diff(pp) > 0)
+    nprow = prow_row.size
+    panel_of = np.empty(nprow, dtype=np.int64)
+    for k in range(nprow):
+        e = src[pp[k]:pp[k + 1]]
+        r = prow_row[k]
+        assert np.all((e >= rp[r]) & (e < rp[r + 1])) and np.all(np.diff(e) == 1)
+        p = np.searchsorted(cut, ci[e[0]], side="right") - 1
+        assert np.all((ci[e] >= cut[p]) & (ci[e] < cut[p + 1]))
+        panel_of[k] = p
+    assert np.all(np.diff(panel_of) >= 0)                       # stored panel after panel
+    # slots: row r's panel rows in panel order, covering the row
+    sptr, sidx = L["slot_ptr"], L["slot_idx"]
+    assert sptr[-1] == nprow and np.array_equal(np.sort(sidx), np.arange(nprow))
+    for r in range(m):
+        ks = sidx[sptr[r]:sptr[r + 1]]
+        assert np.all(prow_row[ks] == r) and np.all(np.diff(panel_of[ks]) > 0)
+        assert (pp[ks + 1] - pp[ks]).sum() == rp[r + 1] - rp[r]
+    # wavefront tasks: inside their panel, E L >= every row, every short panel row once
+    wave, wb = L["wave"], L["wave_begin"]
+    lens = np.diff(pp)
+    cov = np.zeros(nprow, dtype=np.int64)
+    for p in range(npanel):
+        for t in range(wb[p], wb[p + 1]):
+            a, b, kl, E = wave[t]
+            lanes = 1 << (kl >> 8)
+            assert 1 <= E <= 8 and np.all(panel_of[a:a + b] == p)
+            assert np.all(lens[a:a + b] <= E * lanes)
+            cov[a:a + b] += 1
+    assert np.array_equal(cov, (lens <= 512).astype(np.int64))
+    assert L["nblock"] == int((lens > 512).sum())
+    # interleaved entries, walked as the kernel reads them
+    off, cis, vs = L["task_off"], L["cis"], L["vs"]
+    assert off[0] == 0 and off[-1] == cis.size
+    civ = ci[src]
+    vv = v[src]
+    seen = np.zeros(nnz, dtype=np.int64)
+    for t in range(wave.shape[0]):
+        a, b, kl, E = wave[t]
+        lg = kl >> 8
+        lanes, per_round = 1 << lg, 64 >> lg
+        rounds = -(-b // per_round)
+        assert off[t + 1] - off[t] == rounds * 64 * E
+        for i in range(rounds):
+            for j in range(64):
+                slot, lane = i * per_round + (j >> lg), j & (lanes - 1)
+                for k in range(E):
+                    pos = off[t] + 64 * E * i + 64 * k + j
+                    assert 0 <= cis[pos] < n
+                    e = k * lanes + lane
+                    if slot < b and e < lens[a + slot]:
+                        q = pp[a + slot] + e
+                        assert cis[pos] == civ[q] and vs[pos] == vv[q]
+                        seen[q] += 1
+                    else:
+                        assert vs[pos] == 0.0
+    short = np.repeat(lens <= 512, lens)
+    assert np.array_equal(seen, short.astype(np.int64))
+    # LDS segments: every wavefront task once, inside its panel; aligned: group b on b mod P
+    sp_, seg = L["seg_ptr"], L["seg"]
+    tcov = np.zeros(wave.shape[0], dtype=np.int64)
+    for g in range(groups):
+        for s in range(sp_[g], sp_[g + 1]):
+            p, tb, te, _ = seg[s]
+            assert wb[p] <= tb < te <= wb[p + 1]
+            if aligned:
+                assert p == g % npanel
+            tcov[tb:te] += 1
+    assert np.all(tcov == 1)
+
+
+@pytest.mark.parametrize("npanel,groups,aligned", [(1, 7, False), (3, 24, True), (8, 256, True),
+                                                   (17, 5, False)])
+def test_panel_layout_equal_nonzero_cuts(npanel, groups, aligned):
+    K = _matrix(npanel, 400, 1500)
+    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, groups=groups, aligned=aligned)
+    _check(K, L, npanel, groups, aligned)
+
+
+def test_panel_layout_width_slices():
+    """Cuts every 128 columns: the slices the LDS-staged products use."""
+    K = _matrix(11, 300, 1000)
+    W = 128
+    npanel = -(-K.shape[1] // W)
+    cuts = np.minimum(np.arange(npanel + 1) * W, K.shape[1]).astype(np.int32)
+    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, cuts=cuts, groups=9)
+    _check(K, L, npanel, 9, False, cuts=cuts)
+
+
+def test_panel_layout_rejects_bad_arguments():
+    K = _matrix(2, 50, 200)
+    with pytest.raises(P.PdlpError):
+        P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 3, groups=7, aligned=True)
