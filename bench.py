@@ -2,12 +2,17 @@
 column counts, nnz ~1.35e8), one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                    [--no-unroll] [--calibrate-copy]
+                    [--no-unroll] [--no-truncated] [--no-policies] [--no-ablations]
+                    [--calibrate-copy]
 
 A step is one accepted PDHG iteration of Algorithm 1 on the whole LP: the K~^T product fused
 with the primal step, the K~ product fused with the dual step and the step-size rule, and
 (every 40 steps) the restart / termination check.  The LP is resident in HBM before timing
-starts.  Prints one JSON line.  Progress goes to stderr.
+starts.  Prints one JSON line.  Progress goes to stderr.  Beside the headline figures the line
+carries: the same shape with column counts truncated to [1,190]; a whole solve of the tiny LP;
+the constant-step and Malitsky-Pock policies on the large LP; the ablation switches' steps to
+KKT 1e-8 on two small LPs; the batched solver; the unrolled PDHG and its adjoint; the oracle's
+rate on the host.
 """
 from __future__ import annotations
 
