@@ -309,6 +309,51 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
   const int g = lane64 >> lg, lane = lane64 & (L - 1);
   const int per_round = 64 >> lg;
   int64_t blk = off + lane64;
+  if constexpr (R == 1) {
+    // one round at a time (fewer live registers than the general form below)
+    for (int base = 0; base < D.b; base += per_round, blk += int64_t(64) * E) {
+      const int slot = base + g;
+      const bool active = slot < D.b;
+      int r = 0;
+      double s = 0.0;
+      if (active) {
+        // the entry loads need no row length (padding slots hold valid columns), so they are
+        // issued together with it
+        r = A.perm ? A.perm[D.a + slot] : D.a + slot;
+        const int len = A.rlen[r];
+        double v[E];
+        int32_t c[E];
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+          v[k] = A.vs[blk + int64_t(k) * 64];
+          if constexpr (MODE == kProd) {
+            if constexpr (LOCAL) c[k] = A.cis16[blk + int64_t(k) * 64];
+            else c[k] = A.cis[blk + int64_t(k) * 64];
+          }
+        }
+        if constexpr (MODE == kProd) {
+          double xv[E];
+          gather_all<E>(x, c, xv);
+#pragma unroll
+          for (int k = 0; k < E; ++k) {
+            const double t = v[k] * xv[k];
+            s = s + ((k * L + lane < len) ? t : 0.0);
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < E; ++k) s = comb<MODE>(s, (k * L + lane < len) ? fabs(v[k]) : 0.0);
+        }
+      }
+      for (int o = L >> 1; o > 0; o >>= 1) s = comb<MODE>(s, __shfl_xor(s, o, 64));
+      if (active && lane == 0) {
+        double cc[Epi::N];
+        epi.row(r, s, cc);
+#pragma unroll
+        for (int k = 0; k < Epi::N; ++k) acc[k] += cc[k];
+      }
+    }
+    return;
+  }
   for (int base = 0; base < D.b; base += R * per_round, blk += int64_t(R) * 64 * E) {
     int r[R];
     int64_t len[R];
