@@ -406,14 +406,15 @@ typedef struct pdlp_panel_layout {
 /*
  * pdlp_build_panel_layout - host-only (no GPU needed): the panel layout the products use for
  * the nrows x ncols CSR matrix (row_ptr, col_idx, val): npanel panels cut at `cuts` (npanel
- * + 1 column offsets) or, if cuts is NULL, at about equal nonzero counts; its interleaved
- * entries; and the split of its wavefront tasks among `groups` LDS workgroups (aligned: group
- * b stays on panel b mod npanel, which needs groups to be a multiple of npanel).  Returns 0,
- * or -1 on invalid arguments or mismatched counts.
+ * + 1 column offsets) or, if cuts is NULL, at about equal nonzero counts; wavefront tasks of
+ * at most emax entries per lane (8, or 16 as in the layouts of the LDS-staged products); its
+ * interleaved entries; and the split of its wavefront tasks among `groups` LDS workgroups
+ * (aligned: group b stays on panel b mod npanel, which needs groups to be a multiple of
+ * npanel).  Returns 0, or -1 on invalid arguments or mismatched counts.
  */
 int pdlp_build_panel_layout(const int64_t *row_ptr, const int32_t *col_idx, const double *val,
                             int64_t nrows, int64_t ncols, int32_t npanel, const int32_t *cuts,
-                            int32_t groups, int32_t aligned, pdlp_panel_layout *out);
+                            int32_t emax, int32_t groups, int32_t aligned, pdlp_panel_layout *out);
 
 #ifdef __cplusplus
 }

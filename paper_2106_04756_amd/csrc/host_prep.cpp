@@ -16,17 +16,17 @@ namespace pdlp {
 
 namespace {
 
-// smallest p (p <= 6) with len <= kElemsPerLane * 2^p
-int lanes_log2_for(int64_t len) {
+// smallest p (p <= 6) with len <= emax * 2^p
+int lanes_log2_for(int64_t len, int emax = kElemsPerLane) {
   int p = 0;
-  while (p < 6 && (int64_t(kElemsPerLane) << p) < len) ++p;
+  while (p < 6 && (int64_t(emax) << p) < len) ++p;
   return p;
 }
 
 // entries per lane for rows of at most maxlen nonzeros on 2^p lanes: ceil(maxlen / 2^p), >= 1
-int32_t entries_per_lane(int64_t maxlen, int p) {
+int32_t entries_per_lane(int64_t maxlen, int p, int emax = kElemsPerLane) {
   const int64_t L = int64_t(1) << p;
-  return int32_t(std::max<int64_t>(1, std::min<int64_t>(kElemsPerLane, (maxlen + L - 1) / L)));
+  return int32_t(std::max<int64_t>(1, std::min<int64_t>(emax, (maxlen + L - 1) / L)));
 }
 
 }  // namespace
@@ -83,13 +83,14 @@ namespace {
 
 // Appends wavefront tasks for the panel rows [k0, k1) (all of one lane class `lg`, ordered by
 // length) with offsets prow_ptr.
-void push_wave_tasks(Schedule& s, const std::vector<int64_t>& prow_ptr, int64_t k0, int64_t k1, int lg) {
+void push_wave_tasks(Schedule& s, const std::vector<int64_t>& prow_ptr, int64_t k0, int64_t k1, int lg,
+                     int emax) {
   const int64_t per_task = int64_t((64 >> lg) * kRounds);
   for (int64_t off = k0; off < k1; off += per_task) {
     const int32_t cnt = int32_t(std::min<int64_t>(per_task, k1 - off));
     int64_t maxlen = 0;
     for (int64_t k = off; k < off + cnt; ++k) maxlen = std::max(maxlen, prow_ptr[size_t(k) + 1] - prow_ptr[size_t(k)]);
-    s.wave.push_back(RowDesc{int32_t(off), cnt, int32_t(kWaveRows | (lg << 8)), entries_per_lane(maxlen, lg)});
+    s.wave.push_back(RowDesc{int32_t(off), cnt, int32_t(kWaveRows | (lg << 8)), entries_per_lane(maxlen, lg, emax)});
   }
 }
 
@@ -123,7 +124,7 @@ std::vector<int32_t> hot_column_order(const int32_t* ci, int64_t nnz, int64_t nc
 }
 
 bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
-                  double max_prow_frac, PanelLayout& L, const std::vector<int32_t>* given_cuts) {
+                  double max_prow_frac, PanelLayout& L, const std::vector<int32_t>* given_cuts, int emax) {
   const int64_t nnz = rp[nrows];
   L = PanelLayout();
   L.P = P;
@@ -181,7 +182,7 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
     for (int64_t i = pp[size_t(p)]; i < pp[size_t(p) + 1]; ++i) {
       const int64_t k = by_panel[size_t(i)];
       const int64_t len = seg_len[size_t(k)];
-      cls_segs[(len <= kWaveMaxLen) ? lanes_log2_for(len) : 7].push_back(k);
+      cls_segs[(len <= kWaveMaxLen) ? lanes_log2_for(len, emax) : 7].push_back(k);
     }
     for (int cls = 0; cls <= 7; ++cls) {           // 0..6 lane classes, 7 = long rows
       const int64_t k0 = int64_t(L.prow_row.size());
@@ -210,7 +211,7 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
           }
         }
       }
-      if (cls < 7) push_wave_tasks(S, L.prow_ptr, k0, int64_t(L.prow_row.size()), cls);
+      if (cls < 7) push_wave_tasks(S, L.prow_ptr, k0, int64_t(L.prow_row.size()), cls, emax);
     }
     L.wave_begin.push_back(int32_t(S.wave.size()));
     L.block_begin.push_back(int32_t(S.block.size()));
@@ -381,14 +382,15 @@ extern "C" int pdlp_build_schedule(const int64_t* row_ptr, int64_t nrows, int32_
 
 extern "C" int pdlp_build_panel_layout(const int64_t* row_ptr, const int32_t* col_idx, const double* val,
                                        int64_t nrows, int64_t ncols, int32_t npanel, const int32_t* cuts,
-                                       int32_t groups, int32_t aligned, pdlp_panel_layout* out) {
+                                       int32_t emax, int32_t groups, int32_t aligned, pdlp_panel_layout* out) {
   if (!row_ptr || !col_idx || !val || !out || nrows < 0 || ncols < 1 || npanel < 1 || groups < 1 ||
-      (aligned && groups % npanel != 0))
+      (aligned && groups % npanel != 0) || (emax != pdlp::kElemsPerLane && emax != pdlp::kElemsPerLaneLds))
     return -1;
   std::vector<int32_t> given;
   if (cuts) given.assign(cuts, cuts + npanel + 1);
   pdlp::PanelLayout L;
-  if (!pdlp::build_panels(row_ptr, col_idx, nrows, ncols, npanel, 1e300, L, cuts ? &given : nullptr)) return -1;
+  if (!pdlp::build_panels(row_ptr, col_idx, nrows, ncols, npanel, 1e300, L, cuts ? &given : nullptr, emax))
+    return -1;
   const int64_t nnz = row_ptr[nrows];
   std::vector<int32_t> ciP(static_cast<size_t>(nnz));
   std::vector<double> vP(static_cast<size_t>(nnz));

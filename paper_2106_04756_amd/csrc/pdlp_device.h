@@ -31,7 +31,7 @@ struct CsrDev {
   const int64_t* slot_ptr;     // panel mode: panel rows of original row r: slot_idx[slot_ptr[r] ..]
   const int32_t* slot_idx;
   int32_t nrows_orig;
-  int32_t pad1;
+  int32_t emax;          // most entries per lane of a wavefront task (8, or 16 in LDS layouts)
   const int32_t* split_nchunks;
   const int32_t* split_base;
   int32_t nsplit;

@@ -9,6 +9,7 @@ namespace pdlp {
 constexpr int kBlock = 256;            // threads per workgroup (4 wave64)
 constexpr int kWaves = kBlock / 64;
 constexpr int kElemsPerLane = 8;       // a row of length len gets L = min pow2 with len <= 8 L lanes
+constexpr int kElemsPerLaneLds = 16;   // the same with 16 in layouts read by the LDS-staged kernel
 constexpr int kWaveMaxLen = kElemsPerLane * 64;   // longer rows are reduced by a whole workgroup
 constexpr int kRounds = 4;             // rows per lane group in one wavefront task (at most)
 constexpr int kFillWaves = 8192;       // wavefronts of a full grid: 256 CUs x 8 workgroups x 4
@@ -87,9 +88,11 @@ struct LdsSeg {
 // Builds the layout with P panels; returns false (and leaves `out` unusable) when the panel
 // rows would cost more than `max_prow_frac` of the nonzeros.
 // given_cuts: the P + 1 column cuts to use (nullptr: about nnz / P nonzeros per panel).
+// emax: most entries per lane of a wavefront task (kElemsPerLane, or kElemsPerLaneLds for a
+// layout whose products run in the LDS-staged kernel: fewer lanes per row, less padding).
 bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
                   double max_prow_frac, PanelLayout& out,
-                  const std::vector<int32_t>* given_cuts = nullptr);
+                  const std::vector<int32_t>* given_cuts = nullptr, int emax = kElemsPerLane);
 
 // Interleaved entries of the wavefront tasks (a sliced-ELL form): round i of task t, with E
 // entries per lane, owns 64 E slots from off[t] + 64 E i; entry k of lane j (row group

@@ -420,7 +420,8 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
 }
 
 // wave_task with the entries per lane of the task (uniform across the wavefront).
-template <int MODE, int R = 1, bool LOCAL = false, class Epi, class G>
+// EMAX: the most entries per lane the layout's tasks have (kElemsPerLane or kElemsPerLaneLds).
+template <int MODE, int R = 1, bool LOCAL = false, int EMAX = kElemsPerLane, class Epi, class G>
 __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const Epi& epi,
                                             double (&acc)[Epi::N], int t, int lane64) {
   const RowDesc D = A.wave[t];
@@ -434,7 +435,21 @@ __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const E
     case 5: wave_task<MODE, 5, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
     case 6: wave_task<MODE, 6, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
     case 7: wave_task<MODE, 7, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
-    default: wave_task<MODE, kElemsPerLane, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 8: wave_task<MODE, 8, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    default:
+      if constexpr (EMAX > 8) {
+        switch (D.aux) {
+          case 9: wave_task<MODE, 9, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          case 10: wave_task<MODE, 10, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          case 11: wave_task<MODE, 11, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          case 12: wave_task<MODE, 12, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          case 13: wave_task<MODE, 13, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          case 14: wave_task<MODE, 14, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          case 15: wave_task<MODE, 15, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+          default: wave_task<MODE, 16, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+        }
+      }
+      break;
   }
 }
 
@@ -444,7 +459,7 @@ __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const E
 // loading at most kElemsPerLane nonzeros at once, then an xor-butterfly across the group.
 // Contributions of ordinary rows go to acc (per thread); those of split rows go straight to
 // partial slot gridDim.x + split id (if part != nullptr).
-template <int MODE, class Epi>
+template <int MODE, int EMAX = kElemsPerLane, class Epi>
 __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Epi& epi,
                          double (&acc)[Epi::N], double* part) {
   const int lane64 = threadIdx.x & 63;
@@ -453,7 +468,7 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
   const int t1 = A.wave_begin[ps.p + 1];
   const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[ps.p] + ps.lb * kWaves + (threadIdx.x >> 6));
   const GlobalGather gx{x};
-  for (int t = w0; t < t1; t += nw) wave_task_e<MODE>(A, gx, epi, acc, t, lane64);
+  for (int t = w0; t < t1; t += nw) wave_task_e<MODE, 1, false, EMAX>(A, gx, epi, acc, t, lane64);
   csr_block_tasks<MODE>(A, x, epi, acc, part);
 }
 
@@ -999,7 +1014,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(CsrDev A, DevState* st, const d
 
 // COPY = 0 for passes over K~, 1 over K~^T (the same code; two symbols so that a kernel trace
 // tells the two products apart).
-template <int COPY>
+// (EMAX: the most entries per lane of A's tasks; 16 only in the layouts of the LDS kernel.)
+template <int COPY, int EMAX>
 __global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, const double* in0,
                                                        const double* in1, int in_parity, double* out,
                                                        int pred, int mode) {
@@ -1008,9 +1024,9 @@ __global__ __launch_bounds__(kBlock) void k_panel_rows(CsrDev A, DevState* st, c
   const double* in = (in_parity && S.parity) ? in1 : in0;
   StoreEpi epi{out};
   double acc[1] = {0.0};
-  if (mode == kProd) csr_rows<kProd>(A, in, epi, acc, nullptr);
-  else if (mode == kAbsMax) csr_rows<kAbsMax>(A, nullptr, epi, acc, nullptr);
-  else csr_rows<kAbsSum>(A, nullptr, epi, acc, nullptr);
+  if (mode == kProd) csr_rows<kProd, EMAX>(A, in, epi, acc, nullptr);
+  else if (mode == kAbsMax) csr_rows<kAbsMax, EMAX>(A, nullptr, epi, acc, nullptr);
+  else csr_rows<kAbsSum, EMAX>(A, nullptr, epi, acc, nullptr);
 }
 
 // First pass of a panel-mode product with the gathered operand staged in LDS: the panel-row
@@ -1039,10 +1055,12 @@ __global__ __launch_bounds__(kLdsBlock) void k_lds_rows(CsrDev A, DevState* st, 
     __syncthreads();
     if (A.cis16) {            // a slice: every column is in the stage
       const StageGather gx{stage};
-      for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd, 2, true>(A, gx, epi, acc, t, lane64);
+      for (int t = G.tb + wave; t < G.te; t += kLdsWaves)
+        wave_task_e<kProd, 2, true, kElemsPerLaneLds>(A, gx, epi, acc, t, lane64);
     } else {
       const LdsGather gx{stage, in, c0, uint32_t(h)};
-      for (int t = G.tb + wave; t < G.te; t += kLdsWaves) wave_task_e<kProd, 2>(A, gx, epi, acc, t, lane64);
+      for (int t = G.tb + wave; t < G.te; t += kLdsWaves)
+        wave_task_e<kProd, 2, false, kElemsPerLaneLds>(A, gx, epi, acc, t, lane64);
     }
   }
 }

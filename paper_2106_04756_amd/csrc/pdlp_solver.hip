@@ -305,7 +305,8 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
     if (Pw >= 2 && Pw <= kMaxLdsPanels) {
       std::vector<int32_t> wc(size_t(Pw) + 1);
       for (int64_t p = 0; p <= Pw; ++p) wc[size_t(p)] = int32_t(std::min<int64_t>(p * W, ncols));
-      panel = build_panels(rp, ci, nrows, ncols, int(Pw), lmode == 1 ? 1e300 : kLdsRowFrac, PL, &wc) &&
+      panel = build_panels(rp, ci, nrows, ncols, int(Pw), lmode == 1 ? 1e300 : kLdsRowFrac, PL, &wc,
+                           kElemsPerLaneLds) &&
               PL.sched.block.empty();
       if (panel) {
         lds_h = W;
@@ -314,13 +315,21 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
     }
   }
   if (!panel && want) {
-    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts);
     // the first W columns of each panel staged in LDS: its hottest when the columns are
     // ordered hot-first, automatic for such a copy (on the 1e6 x 2e6 LP, K~ x took 0.55 ms
     // with the stage against 0.89 ms without and 1.21 ms in slices, measured together)
-    if (panel && PL.sched.block.empty() && (lmode == 2 || (lmode < 0 && hot_first))) lds_h = W;
+    const bool stage = lmode == 2 || (lmode < 0 && hot_first);
+    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts,
+                         stage ? kElemsPerLaneLds : kElemsPerLane);
+    if (panel && stage) {
+      if (PL.sched.block.empty())
+        lds_h = W;
+      else      // rows too long for the LDS kernel: the tasks of the other kernels
+        panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts);
+    }
   }
   A.nrows_orig = int32_t(nrows);
+  A.emax = (panel && lds_h > 0) ? kElemsPerLaneLds : kElemsPerLane;
   A.lds_h = 0;
   if (panel && lds_h > 0) {
     std::vector<LdsSeg> seg;
@@ -401,10 +410,14 @@ void launch_panel_rows(pdlp_solver* s, const CsrDev& A, int grid, const double* 
       k_lds_rows<0><<<A.lds_grid, kLdsBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred);
     return;
   }
-  if (&A == &s->KT)
-    k_panel_rows<1><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
-  else
-    k_panel_rows<0><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+  const bool wide = A.emax > kElemsPerLane;
+  if (&A == &s->KT) {
+    if (wide) k_panel_rows<1, kElemsPerLaneLds><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+    else k_panel_rows<1, kElemsPerLane><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+  } else {
+    if (wide) k_panel_rows<0, kElemsPerLaneLds><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+    else k_panel_rows<0, kElemsPerLane><<<grid, kBlock, 0, s->stream>>>(A, s->st, in0, in1, in_par, out, pred, mode);
+  }
 }
 
 // Grid of a CSR pass: a multiple of npanel, enough workgroups for the busiest panel.

@@ -135,7 +135,7 @@ def lib() -> ctypes.CDLL:
         L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P, P]
         L.pdlp_build_schedule.restype = ctypes.c_int
         L.pdlp_build_panel_layout.argtypes = [P, P, P, I64, I64, ctypes.c_int32, P, ctypes.c_int32,
-                                              ctypes.c_int32, ctypes.POINTER(PanelLayoutC)]
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(PanelLayoutC)]
         L.pdlp_build_panel_layout.restype = ctypes.c_int
         L.pdlp_batch_create.argtypes = [ctypes.POINTER(P), I64, P, P, P, P, P, P, P, P, P, P,
                                         ctypes.POINTER(Options), P]
@@ -224,7 +224,7 @@ class PanelLayoutC(ctypes.Structure):
                                                "wave", "wave_begin", "task_off", "cis", "vs", "seg_ptr", "seg")]
 
 
-def panel_layout(row_ptr, col_idx, val, ncols, npanel, cuts=None, groups=256, aligned=False):
+def panel_layout(row_ptr, col_idx, val, ncols, npanel, cuts=None, groups=256, aligned=False, emax=8):
     """Host-only: the column-panel layout of a CSR matrix as the products read it, its
     interleaved entries and the LDS workgroups' segments (pdlp_build_panel_layout), as a
     dict of NumPy arrays."""
@@ -234,7 +234,7 @@ def panel_layout(row_ptr, col_idx, val, ncols, npanel, cuts=None, groups=256, al
     nrows = rp.size - 1
     cu = None if cuts is None else np.ascontiguousarray(cuts, dtype=np.int32)
     args = (rp.ctypes.data, ci.ctypes.data, v.ctypes.data, nrows, int(ncols), int(npanel),
-            None if cu is None else cu.ctypes.data, int(groups), int(bool(aligned)))
+            None if cu is None else cu.ctypes.data, int(emax), int(groups), int(bool(aligned)))
     L = PanelLayoutC()
     if lib().pdlp_build_panel_layout(*args, ctypes.byref(L)) != 0:
         raise PdlpError(-1, "pdlp_build_panel_layout failed")

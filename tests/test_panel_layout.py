@@ -27,7 +27,7 @@ def _matrix(seed, m, n):
     return K
 
 
-def _check(K, L, npanel, groups, aligned, cuts=None):
+def _check(K, L, npanel, groups, aligned, cuts=None, emax=8):
     m, n = K.shape
     rp, ci, v = K.indptr.astype(np.int64), K.indices, K.data
     nnz = K.nnz
@@ -65,8 +65,10 @@ def _check(K, L, npanel, groups, aligned, cuts=None):
         for t in range(wb[p], wb[p + 1]):
             a, b, kl, E = wave[t]
             lanes = 1 << (kl >> 8)
-            assert 1 <= E <= 8 and np.all(panel_of[a:a + b] == p)
+            assert 1 <= E <= emax and np.all(panel_of[a:a + b] == p)
             assert np.all(lens[a:a + b] <= E * lanes)
+            # the fewest lanes that reach each row with at most emax entries per lane
+            assert lanes == 1 or np.all(lens[a:a + b] > emax * (lanes // 2))
             cov[a:a + b] += 1
     assert np.array_equal(cov, (lens <= 512).astype(np.int64))
     assert L["nblock"] == int((lens > 512).sum())
@@ -110,25 +112,30 @@ def _check(K, L, npanel, groups, aligned, cuts=None):
     assert np.all(tcov == 1)
 
 
+@pytest.mark.parametrize("emax", [8, 16])
 @pytest.mark.parametrize("npanel,groups,aligned", [(1, 7, False), (3, 24, True), (8, 256, True),
                                                    (17, 5, False)])
-def test_panel_layout_equal_nonzero_cuts(npanel, groups, aligned):
+def test_panel_layout_equal_nonzero_cuts(npanel, groups, aligned, emax):
     K = _matrix(npanel, 400, 1500)
-    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, groups=groups, aligned=aligned)
-    _check(K, L, npanel, groups, aligned)
+    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, groups=groups, aligned=aligned,
+                       emax=emax)
+    _check(K, L, npanel, groups, aligned, emax=emax)
 
 
-def test_panel_layout_width_slices():
+@pytest.mark.parametrize("emax", [8, 16])
+def test_panel_layout_width_slices(emax):
     """Cuts every 128 columns: the slices the LDS-staged products use."""
     K = _matrix(11, 300, 1000)
     W = 128
     npanel = -(-K.shape[1] // W)
     cuts = np.minimum(np.arange(npanel + 1) * W, K.shape[1]).astype(np.int32)
-    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, cuts=cuts, groups=9)
-    _check(K, L, npanel, 9, False, cuts=cuts)
+    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, cuts=cuts, groups=9, emax=emax)
+    _check(K, L, npanel, 9, False, cuts=cuts, emax=emax)
 
 
 def test_panel_layout_rejects_bad_arguments():
     K = _matrix(2, 50, 200)
     with pytest.raises(P.PdlpError):
         P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 3, groups=7, aligned=True)
+    with pytest.raises(P.PdlpError):
+        P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 3, emax=12)
