@@ -317,8 +317,9 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
       int r = 0;
       double s = 0.0;
       if (active) {
-        // the entry loads need no row length (padding slots hold valid columns), so they are
-        // issued together with it
+        // the entry loads stay inside the task's slots, so they are issued together with the
+        // row length; the gathers wait for it (an empty row, e.g. of a copy with no columns,
+        // gathers nothing)
         r = A.perm ? A.perm[D.a + slot] : D.a + slot;
         const int len = A.rlen[r];
         double v[E];
@@ -332,12 +333,14 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
           }
         }
         if constexpr (MODE == kProd) {
-          double xv[E];
-          gather_all<E>(x, c, xv);
+          if (len > 0) {
+            double xv[E];
+            gather_all<E>(x, c, xv);
 #pragma unroll
-          for (int k = 0; k < E; ++k) {
-            const double t = v[k] * xv[k];
-            s = s + ((k * L + lane < len) ? t : 0.0);
+            for (int k = 0; k < E; ++k) {
+              const double t = v[k] * xv[k];
+              s = s + ((k * L + lane < len) ? t : 0.0);
+            }
           }
         } else {
 #pragma unroll
@@ -384,11 +387,11 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
       double xv[R][E];
 #pragma unroll
       for (int q = 0; q < R; ++q)
-        if (active[q]) gather_all<E>(x, c[q], xv[q]);
+        if (active[q] && len[q] > 0) gather_all<E>(x, c[q], xv[q]);
 #pragma unroll
       for (int q = 0; q < R; ++q) {
         s[q] = 0.0;
-        if (active[q]) {
+        if (active[q] && len[q] > 0) {
 #pragma unroll
           for (int k = 0; k < E; ++k) {
             const double t = v[q][k] * xv[q][k];

@@ -401,6 +401,22 @@ def test_edge_cases():
     assert np.all(np.isfinite(kkt))
 
 
+@pytest.mark.parametrize("panels", [0, 1])
+def test_product_over_a_copy_without_columns(panels):
+    """K~^T y of an LP without constraints (m = 0): every row of K~^T is empty and the product
+    is exactly zero, whatever the caller's buffer holds (here one NaN)."""
+    import torch
+    n = 300
+    lp = lpgen.LP(m=0, n=n, n_eq=0, c=np.ones(n), row_ptr=np.zeros(1, np.int64), col_idx=np.zeros(0, np.int32),
+                  val=np.zeros(0), q=np.zeros(0), l=np.zeros(n), u=np.ones(n))
+    say("product with no rows", "panels", panels)
+    s = make(lp, ruiz_iters=0, pock_chambolle=0, xcd_panels=panels)
+    y = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    out = torch.full((n,), 5.0, dtype=torch.float64, device="cuda")
+    s.spmv(y, out, transpose=True)
+    assert torch.equal(out.cpu(), torch.zeros(n, dtype=torch.float64))
+
+
 def test_get_before_solve_and_device_outputs():
     import torch
     lp = lpgen.tiny_lp()
