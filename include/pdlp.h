@@ -410,7 +410,9 @@ typedef struct pdlp_panel_layout {
  * at most emax entries per lane (8, or 16 as in the layouts of the LDS-staged products); its
  * interleaved entries; and the split of its wavefront tasks among `groups` LDS workgroups
  * (aligned: group b stays on panel b mod npanel, which needs groups to be a multiple of
- * npanel).  Returns 0, or -1 on invalid arguments or mismatched counts.
+ * npanel).  Returns 0, or -1 on invalid arguments (including a matrix that is not CSR with
+ * in-range, increasing columns per row, or cuts that are not non-decreasing from 0 to ncols)
+ * or mismatched counts.
  */
 int pdlp_build_panel_layout(const int64_t *row_ptr, const int32_t *col_idx, const double *val,
                             int64_t nrows, int64_t ncols, int32_t npanel, const int32_t *cuts,

@@ -386,6 +386,19 @@ extern "C" int pdlp_build_panel_layout(const int64_t* row_ptr, const int32_t* co
   if (!row_ptr || !col_idx || !val || !out || nrows < 0 || ncols < 1 || npanel < 1 || groups < 1 ||
       (aligned && groups % npanel != 0) || (emax != pdlp::kElemsPerLane && emax != pdlp::kElemsPerLaneLds))
     return -1;
+  // a valid CSR matrix (offsets from 0, non-decreasing; columns in range, increasing in a row)
+  // and valid cuts (0 = cut[0] <= cut[1] <= ... <= cut[npanel] = ncols)
+  if (row_ptr[0] != 0) return -1;
+  for (int64_t r = 0; r < nrows; ++r) {
+    if (row_ptr[r + 1] < row_ptr[r]) return -1;
+    for (int64_t e = row_ptr[r]; e < row_ptr[r + 1]; ++e)
+      if (col_idx[e] < 0 || col_idx[e] >= ncols || (e > row_ptr[r] && col_idx[e] <= col_idx[e - 1])) return -1;
+  }
+  if (cuts) {
+    if (cuts[0] != 0 || cuts[npanel] != ncols) return -1;
+    for (int p = 0; p < npanel; ++p)
+      if (cuts[p + 1] < cuts[p]) return -1;
+  }
   std::vector<int32_t> given;
   if (cuts) given.assign(cuts, cuts + npanel + 1);
   pdlp::PanelLayout L;

@@ -139,3 +139,9 @@ def test_panel_layout_rejects_bad_arguments():
         P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 3, groups=7, aligned=True)
     with pytest.raises(P.PdlpError):
         P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 3, emax=12)
+    bad = K.indices.copy()
+    bad[0] = K.shape[1]                                       # a column out of range
+    with pytest.raises(P.PdlpError):
+        P.panel_layout(K.indptr, bad, K.data, K.shape[1], 3)
+    with pytest.raises(P.PdlpError):                           # cuts not ending at ncols
+        P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 2, cuts=np.array([0, 50, 100], np.int32))
