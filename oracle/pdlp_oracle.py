@@ -14,8 +14,12 @@ Parity status (what pins each part, other than this code itself):
   * precondition()           - Ruiz norm convergence, Pock-Chambolle spectral bound, same optimum.
   * normalized_gap()         - closed form when the ball lies inside the box, zero at an optimum,
                                brute-force sampling on tiny cases, independent bisection.
-  * pdhg step / adaptive rule- a hand-worked 2x2 step, the optimum as a fixed point,
-                               eta_bar >= 1/||K||_2 on every attempt.
+  * pdhg step / adaptive rule- a hand-worked 2x2 step with its Eq. (5) limit and Algorithm 2
+                               proposals (k = 1, 7, both branches) worked in exact decimals,
+                               the optimum as a fixed point, eta_bar >= 1/||K||_2 on every
+                               attempt.
+  * power_iteration_norm()   - numpy.linalg.norm(., 2) of the dense matrix, the closed forms of
+                               diagonal and rank-one matrices, monotone and bounded estimates.
   * restart / primal weight  - table-driven cases with hand-written gap sequences, closed form.
   * solve()                  - optimum matches vertex enumeration and HiGHS, KKT <= tol,
                                scale invariance (Proposition 1), PageRank fixed point.
@@ -308,6 +312,10 @@ def restart_mask(mu_c, mu_anchor, mu_prev, t, k, n_outer, opts: Options) -> int:
     (ii) implies (i) and can never decide a restart.  (ii) only acts when
     beta_necessary > beta_sufficient, so the defaults are read transposed: (i) needs the gap to
     fall to 0.1 of the anchor's, (ii) to 0.9 of it plus no progress since the previous check.
+    The paper's own text supports this: Appendix C describes its "adaptive restart (theory)"
+    variant, with both parameters set to exp(-1), as the default with criterion (ii) taken
+    away.  That distinction is only real if (ii) can decide a restart under the defaults,
+    i.e. if beta_necessary exceeds beta_sufficient there.
 
     Reading Z9: mu(z^{n,0}, z^{n-1,0}) is undefined in the first outer loop (n = 0), so
     (i) and (ii) are false there; (iii) t >= beta_art * k holds anyway because t = k.

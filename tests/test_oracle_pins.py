@@ -193,11 +193,92 @@ def test_eta_bar_at_least_inverse_spectral_norm():
             assert eta <= eta_bar
 
 
-def test_step_size_update_formula():
-    assert O.next_step_size(10.0, 1.0, 1) == min((1 - 2 ** -0.3) * 10.0, (1 + 2 ** -0.6) * 1.0)
-    assert O.next_step_size(1.0, 5.0, 7) == (1 - 8 ** -0.3) * 1.0
+def _step_2x2():
+    """The hand-worked 2x2 step of pdhg_step_2x2.txt: (dx, dy, omega, K)."""
+    K = sp.csr_matrix(np.array([[1.0, 2.0], [3.0, 4.0]]))
+    x, y = np.array([1.0, 1.0]), np.array([0.5, -1.0])
+    xp, yp = O.pdhg_step(x, y, 0.1, 2.0, np.array([1.0, 1.0]), K, K.T.tocsr(), np.array([1.0, 2.0]),
+                         np.zeros(2), np.full(2, 10.0), 1)
+    return xp - x, yp - y, 2.0, K
+
+
+def test_step_size_limit_hand_worked():
+    """Eq. (5): eta_bar = ||dz||_omega^2 / (2 |dy^T K dx|), against the value worked by hand in
+    exact decimals (tests/golden/step_size_rule_2x2.txt)."""
+    g = _golden("step_size_rule_2x2.txt")
+    dx, dy, omega, K = _step_2x2()
+    assert O.step_size_limit(dx, dy, omega, K) == pytest.approx(g["eta_bar"], rel=1e-14, abs=0)
+    # the same limit with the roles of the two updates exchanged (dy^T K dx is symmetric in
+    # the pair only through K; a transposed operand changes it)
+    assert O.step_size_limit(dx, dy, omega, sp.csr_matrix(K.T)) != pytest.approx(g["eta_bar"], rel=1e-3)
+
+
+def test_next_step_size_hand_worked():
+    """Algorithm 2's proposal eta' at steps k = 1 and k = 7 (both branches of the min), against
+    values worked by hand in exact decimals."""
+    g = _golden("step_size_rule_2x2.txt")
+    eb = g["eta_bar"]
+    assert O.next_step_size(eb, 0.1, 1) == pytest.approx(g["eta_next_k1"], rel=1e-14, abs=0)
+    assert O.next_step_size(eb, 0.1, 7) == pytest.approx(g["eta_next_k7"], rel=1e-14, abs=0)
+    assert O.next_step_size(1.0, 0.1, 7) == pytest.approx(g["eta_next_k7_cap"], rel=1e-14, abs=0)
     # first step never collapses to zero (reading R3)
     assert O.next_step_size(3.0, 1.0, 1) > 0.0
+
+
+def test_step_rule_pins_reject_planted_mistakes():
+    """The hand-worked values above tell apart the plausible slips in Algorithm 2: each variant
+    below plants one in a copy of the rule, and must miss a golden value by far more than the
+    tolerance the pins use."""
+    g = _golden("step_size_rule_2x2.txt")
+    dx, dy, omega, K = _step_2x2()
+    nx, ny, cross = float(dx @ dx), float(dy @ dy), float(dy @ (K @ dx))
+    limits = {
+        "omega swapped": (nx / omega + ny * omega) / (2 * abs(cross)),
+        "factor 2 dropped": (omega * nx + ny / omega) / abs(cross),
+        "unweighted norm": (nx + ny) / (2 * abs(cross)),
+    }
+    for name, v in limits.items():
+        assert abs(v - g["eta_bar"]) > 1e-6 * g["eta_bar"], name
+    eb = g["eta_bar"]
+
+    def rule(eta_bar, eta, k, e1, e2, shift):
+        k1 = float(k + shift)
+        return min((1.0 - k1 ** -e1) * eta_bar, (1.0 + k1 ** -e2) * eta)
+
+    variants = {
+        "exponents swapped": lambda eb_, eta, k: rule(eb_, eta, k, 0.6, 0.3, 1),
+        "0-based counter": lambda eb_, eta, k: rule(eb_, eta, k, 0.3, 0.6, 0) if k > 0 else 0.0,
+        "counter one ahead": lambda eb_, eta, k: rule(eb_, eta, k, 0.3, 0.6, 2),
+    }
+    for name, f in variants.items():
+        miss = [abs(f(eb, 0.1, 1) - g["eta_next_k1"]) / g["eta_next_k1"],
+                abs(f(eb, 0.1, 7) - g["eta_next_k7"]) / g["eta_next_k7"],
+                abs(f(1.0, 0.1, 7) - g["eta_next_k7_cap"]) / g["eta_next_k7_cap"]]
+        assert max(miss) > 1e-6, name
+
+
+def test_power_iteration_norm_against_numpy():
+    """||K~||_2 by power iteration (the constant step of the baseline PDHG, Section 2) against
+    numpy.linalg.norm(., 2) of the dense matrix; the estimate never exceeds the norm (it is
+    sqrt(||K^T K v||) with ||v|| = 1) and does not decrease from one iteration to the next."""
+    lp = lpgen.tiny_lp()
+    K = lp.K()
+    Kt = O.precondition(K, lp.c, lp.q, lp.l, lp.u)[0]
+    for A, iters, rel in ((K, 200, 1e-10), (Kt, 1000, 1e-9)):
+        ref = float(np.linalg.norm(A.toarray(), 2))
+        est = O.power_iteration_norm(A, iters)
+        assert abs(est - ref) <= rel * ref, (est, ref)
+        prev = 0.0
+        for it in (1, 2, 5, 20, 100):
+            e = O.power_iteration_norm(A, it)
+            assert prev <= e * (1 + 1e-15) and e <= ref * (1 + 1e-14)
+            prev = e
+    # diagonal and rank-one matrices: the norm is known in closed form
+    D = sp.csr_matrix(np.diag([0.5, -3.0, 2.0]))
+    assert O.power_iteration_norm(D, 200) == pytest.approx(3.0, rel=1e-12)
+    # (rank one: the second iterate is already the top right singular vector v / ||v||)
+    u, v = np.array([1.0, 2.0, 2.0]), np.array([3.0, 4.0])
+    assert O.power_iteration_norm(sp.csr_matrix(np.outer(u, v)), 2) == pytest.approx(15.0, rel=1e-14)
 
 
 # ------------------------------------------------------------------------------------------
