@@ -229,7 +229,9 @@ typedef struct pdlp_batch pdlp_batch;
  *   row_ptr      members' CSR row offsets concatenated (sum of m + 1 values; each member's
  *                offsets start at 0 and index that member's nonzeros).
  *   col_idx, val members' nonzeros concatenated (member-local column indices).
- *   opts         as in pdlp_create; step_policy must be 0 (adaptive); traces are not kept.
+ *   opts         as in pdlp_create (the same ranges are checked), with step_policy 0 (adaptive)
+ *                and pw_power_of_two 0 (the "no restart" weight events are not implemented
+ *                here); traces, kernel timing, panels and graphs do not apply.
  * Inputs are deep-copied; host or device pointers.  Errors as pdlp_create (the message names
  * the first invalid member).
  */

@@ -46,6 +46,18 @@ bool is_device_ptr(const void* p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged || a.isManaged;
 }
 
+// The option ranges pdlp_create accepts (include/pdlp.h).
+bool options_valid(const pdlp_options& o) {
+  return !(o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || o.trace_iters < 0 ||
+           o.trace_capacity < 0 || !(o.theta >= 0.0 && o.theta <= 1.0) || !(o.primal_importance > 0.0) ||
+           !(o.eps_zero >= 0.0) || !(o.beta_sufficient > 0.0) || !(o.beta_necessary > 0.0) ||
+           !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 2 || o.power_iters < 1 ||
+           !(o.mp_breaking_factor > 0.0) || !(o.mp_downscaling > 0.0 && o.mp_downscaling < 1.0) ||
+           !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0) || o.column_order < -1 ||
+           o.column_order > 1 || (o.pw_power_of_two != 0 && (o.pw_power_of_two != 1 || o.adaptive_restarts)) ||
+           o.lds_gather < -1 || o.lds_gather > 2 || o.lds_entries < 0 || o.lds_entries > kLdsEntries);
+}
+
 double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -1247,15 +1259,7 @@ int pdlp_create(pdlp_solver** out, int64_t m, int64_t n, int64_t n_eq, const dou
   }
   if (opts) s->opts = *opts;
   else pdlp_default_options(&s->opts);
-  const pdlp_options& o = s->opts;
-  if (o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || o.trace_iters < 0 ||
-      o.trace_capacity < 0 || !(o.theta >= 0.0 && o.theta <= 1.0) || !(o.primal_importance > 0.0) ||
-      !(o.eps_zero >= 0.0) || !(o.beta_sufficient > 0.0) || !(o.beta_necessary > 0.0) ||
-      !(o.beta_artificial > 0.0) || o.step_policy < 0 || o.step_policy > 2 || o.power_iters < 1 ||
-      !(o.mp_breaking_factor > 0.0) || !(o.mp_downscaling > 0.0 && o.mp_downscaling < 1.0) ||
-      !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0) || o.column_order < -1 ||
-      o.column_order > 1 || (o.pw_power_of_two != 0 && (o.pw_power_of_two != 1 || o.adaptive_restarts)) ||
-      o.lds_gather < -1 || o.lds_gather > 2 || o.lds_entries < 0 || o.lds_entries > kLdsEntries) {
+  if (!options_valid(s->opts)) {
     g_create_error = "invalid options";
     delete s;
     return PDLP_ERR_INVALID_ARGUMENT;
@@ -1838,10 +1842,9 @@ int pdlp_batch_create(pdlp_batch** out, int64_t count, const int64_t* m, const i
   }
   if (opts) b->opts = *opts;
   else pdlp_default_options(&b->opts);
-  const pdlp_options& o = b->opts;
-  if (o.ruiz_iters < 0 || o.check_every < 1 || o.max_retries < 1 || !(o.theta >= 0.0 && o.theta <= 1.0) ||
-      !(o.primal_importance > 0.0) || !(o.eps_zero >= 0.0) || o.step_policy != 0) {
-    g_batch_error = "invalid options (the batched solver uses the adaptive step policy)";
+  if (!options_valid(b->opts) || b->opts.step_policy != 0 || b->opts.pw_power_of_two != 0) {
+    g_batch_error = "invalid options (the batched solver takes the options of pdlp_create with the "
+                    "adaptive step policy and pw_power_of_two = 0)";
     delete b;
     return PDLP_ERR_INVALID_ARGUMENT;
   }

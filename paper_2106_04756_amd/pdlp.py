@@ -190,6 +190,24 @@ def _ptr(a, dtype):
     return ctypes.c_void_p(arr.ctypes.data), arr
 
 
+def _out_ptr(a):
+    """Pointer of a caller's float64 output buffer (NumPy array or torch tensor).  The library
+    writes through this pointer, so a buffer it cannot write in place (another dtype, not
+    contiguous, read-only) is refused instead of being replaced by a temporary copy."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr") and hasattr(a, "is_cuda"):          # torch tensor
+        import torch
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise ValueError("output tensor must be contiguous torch.float64 "
+                             f"(got {a.dtype}, contiguous={a.is_contiguous()})")
+        return ctypes.c_void_p(a.data_ptr())
+    if not isinstance(a, np.ndarray) or a.dtype != np.float64 or not a.flags.c_contiguous \
+            or not a.flags.writeable:
+        raise ValueError("output array must be a writeable C-contiguous numpy.float64 array")
+    return ctypes.c_void_p(a.ctypes.data)
+
+
 def _default_stream():
     try:
         import torch
@@ -301,9 +319,7 @@ class Solver:
 
     def get_into(self, x=None, y=None):
         """Write the returned point into caller tensors / arrays (host or device)."""
-        px, kx = _ptr(x, np.float64) if x is not None else (None, None)
-        py, ky = _ptr(y, np.float64) if y is not None else (None, None)
-        self._check(lib().pdlp_get(self._h, px, py, None))
+        self._check(lib().pdlp_get(self._h, _out_ptr(x), _out_ptr(y), None))
 
     def info(self) -> dict:
         inf = Info()
@@ -375,8 +391,7 @@ class Solver:
     def spmv(self, x, out, transpose=False):
         """out = K~ x (or K~^T x) on device tensors."""
         px, kx = _ptr(x, np.float64)
-        po, ko = _ptr(out, np.float64)
-        self._check(lib().pdlp_spmv(self._h, 1 if transpose else 0, px, po))
+        self._check(lib().pdlp_spmv(self._h, 1 if transpose else 0, px, _out_ptr(out)))
 
     # ---- unrolled PDHG (frozen eta, omega, D1, D2) and its adjoint ----
 
@@ -389,8 +404,7 @@ class Solver:
         pq, kq = _ptr(q, np.float64)
         xo = np.empty(self.n) if x_out is None else x_out
         yo = np.empty(self.m) if y_out is None else y_out
-        px, kx = _ptr(xo, np.float64)
-        py, ky = _ptr(yo, np.float64)
+        px, py = _out_ptr(xo), _out_ptr(yo)
         self._check(lib().pdlp_unroll_forward(self._h, pc, pq, int(steps), int(segment), float(eta),
                                               float(omega), px, py if self.m else None))
         self.unroll_id = getattr(self, "unroll_id", 0) + 1
@@ -402,8 +416,7 @@ class Solver:
         pgy, kgy = _ptr(gy, np.float64)
         gc = np.empty(self.n) if gc_out is None else gc_out
         gq = np.empty(self.m) if gq_out is None else gq_out
-        pc, kc = _ptr(gc, np.float64)
-        pq, kq = _ptr(gq, np.float64)
+        pc, pq = _out_ptr(gc), _out_ptr(gq)
         self._check(lib().pdlp_unroll_backward(self._h, pgx, pgy if self.m else None, pc,
                                                pq if self.m else None))
         return gc, gq

@@ -176,3 +176,33 @@ def test_schedule_rounds_follow_matrix_size():
         rp = np.arange(nrows + 1, dtype=np.int64)           # rows of one nonzero: 64 per round
         desc, _, _ = P.schedule(rp)
         assert desc[:, 1].max() == want, (nrows, desc[:, 1].max())
+
+
+def test_batch_create_checks_the_options_of_pdlp_create():
+    # the batched solver accepts the option ranges of pdlp_create, with the adaptive step policy
+    # and without the "no restart" weight events (rejected before any device work)
+    lps = [lpgen.tiny_lp()]
+    for bad in (dict(adaptive_restarts=0, pw_power_of_two=1), dict(step_policy=1), dict(beta_sufficient=0.0),
+                dict(beta_artificial=-1.0), dict(check_every=0), dict(lds_entries=19457)):
+        with pytest.raises(P.PdlpError, match="options") as ei:
+            P.Batch(lps, **bad)
+        assert ei.value.code == B.ERR_INVALID_ARGUMENT, bad
+
+
+def test_outputs_must_be_writable_float64_in_place():
+    # an output the library cannot write in place is refused, not silently copied
+    with pytest.raises(ValueError):
+        B._out_ptr(np.zeros(4, dtype=np.float32))
+    with pytest.raises(ValueError):
+        B._out_ptr(np.zeros(8)[::2])
+    ro = np.zeros(4)
+    ro.setflags(write=False)
+    with pytest.raises(ValueError):
+        B._out_ptr(ro)
+    a = np.zeros(4)
+    assert B._out_ptr(a).value == a.ctypes.data
+    import torch
+    with pytest.raises(ValueError):
+        B._out_ptr(torch.zeros(4, dtype=torch.float32))
+    t = torch.zeros(4, dtype=torch.float64)
+    assert B._out_ptr(t).value == t.data_ptr()
