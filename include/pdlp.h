@@ -269,7 +269,8 @@ typedef struct pdlp_unroll_info {
   double omega;                  /* frozen primal weight used                                  */
   double forward_seconds;        /* host wall time of the last forward / backward call         */
   double backward_seconds;
-  double device_bytes;           /* device memory held by the unroll buffers                   */
+  double device_bytes;           /* device memory the solver allocated for its own unroll buffers
+                                    (0 while only pdlp_unroll_forward_noalloc has run)          */
   int32_t ready;                 /* 1 if a forward pass can be differentiated                  */
   int32_t pad;
 } pdlp_unroll_info;
@@ -308,6 +309,27 @@ int pdlp_unroll_forward(pdlp_solver *s, const double *c, const double *q, int64_
  */
 int pdlp_unroll_backward(pdlp_solver *s, const double *gx_T, const double *gy_T, double *gc,
                          double *gq);
+
+/*
+ * pdlp_unroll_forward_noalloc - pdlp_unroll_forward for callers that cannot allocate device
+ * memory (tight serving loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * errors as pdlp_unroll_forward, and the same kernels; it calls no hipMalloc, hipFree or other
+ * allocating routine.  The unroll's buffers (staging of c and q, the running iterate, the
+ * ceil(T/segment) checkpoints of n + 2m values, segment * (n + m) bytes of projection masks,
+ * the adjoints) are carved from a per-GPU scratch array of 64 MiB that the library holds from
+ * its load until the process ends, instead of the solver's own buffers.  Requests whose
+ * buffers exceed 64 MiB (about 8 (7 (n + m) + nseg (n + 2m)) + segment (n + m) bytes) fail with
+ * PDLP_ERR_INVALID_ARGUMENT before any device work.  The solver itself must exist (its
+ * pdlp_create allocates, once).
+ * Sharing: every no-alloc call on one GPU uses the same array and leaves its contents there.
+ * pdlp_unroll_backward after this call reads them, and fails with PDLP_ERR_INVALID_STATE if
+ * another no-alloc forward on that GPU (on any solver) has claimed the array since.  Calls
+ * that overlap in time on one GPU (from several host threads) race and must be serialized by
+ * the caller.
+ */
+int pdlp_unroll_forward_noalloc(pdlp_solver *s, const double *c, const double *q, int64_t steps,
+                                int64_t segment, double eta, double omega, double *x_T,
+                                double *y_T);
 
 /* pdlp_unroll_get_info - see pdlp_unroll_info. */
 int pdlp_unroll_get_info(const pdlp_solver *s, pdlp_unroll_info *info);

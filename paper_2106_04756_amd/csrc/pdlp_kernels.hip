@@ -1887,6 +1887,11 @@ __global__ __launch_bounds__(kBlock) void k_pow_scale(const DevState* st, const 
     v[j] = (nw > 0.0) ? w[j] / nw : 0.0;
 }
 
+// v[j] = value for j < n (start vector of the power iteration).
+__global__ __launch_bounds__(kBlock) void k_fill(double* v, double value, int n) {
+  for (int j = blockIdx.x * kBlock + threadIdx.x; j < n; j += gridDim.x * kBlock) v[j] = value;
+}
+
 // eta = 0.9 / ||K~||_2 with ||K~||_2 = sqrt(||K~^T K~ v||) of the last power iteration.
 __global__ void k_pow_set_step(DevState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,7 @@ double now_s() {
 
 struct pdlp_solver {
   hipStream_t stream = nullptr;
+  int device = 0;                      // the GPU current at pdlp_create
   int64_t m = 0, n = 0, n_eq = 0, nnz = 0;
   pdlp_options opts{};
   std::vector<void*> allocs;
@@ -115,17 +117,24 @@ struct pdlp_solver {
     std::vector<void*> allocs;
     int64_t T = 0, S = 1, nseg = 0, cap_seg = -1, cap_S = -1;
     double eta = 0.0, omega = 0.0;
-    double* ct = nullptr;      // c~, q~ of the forward call
-    double* qt = nullptr;
-    double* gin = nullptr;     // staging of the caller's c, q (forward) or gx, gy (backward)
-    double* z = nullptr;       // x (n) | y (m) | K~ x (m) of the running step
-    double* ck = nullptr;      // nseg checkpoints with the layout of z
-    double* xb = nullptr;      // adjoints
-    double* ub = nullptr;
-    double* vb = nullptr;
-    double* cb = nullptr;      // cb (n) | qb (m), contiguous
-    double* out = nullptr;     // n + m outputs in the user's units
-    uint8_t* mask = nullptr;   // S steps x (n + m) bytes
+    struct Buf {
+      double* ct = nullptr;      // c~, q~ of the forward call
+      double* qt = nullptr;
+      double* gin = nullptr;     // staging of the caller's c, q (forward) or gx, gy (backward)
+      double* z = nullptr;       // x (n) | y (m) | K~ x (m) of the running step
+      double* ck = nullptr;      // nseg checkpoints with the layout of z
+      double* xb = nullptr;      // adjoints
+      double* ub = nullptr;
+      double* vb = nullptr;
+      double* cb = nullptr;      // cb (n) | qb (m), contiguous
+      double* out = nullptr;     // n + m outputs in the user's units
+      uint8_t* mask = nullptr;   // S steps x (n + m) bytes
+    };
+    Buf own;                     // the solver's own buffers (pdlp_unroll_forward)
+    Buf b;                       // the buffers of the last forward call: `own`, or carved from
+                                 // the per-GPU scratch array (pdlp_unroll_forward_noalloc)
+    bool in_scratch = false;     // b lies in the scratch array, claimed with scratch_gen
+    uint64_t scratch_gen = 0;
     bool ready = false, masks_last = false;
     double fwd_s = 0.0, bwd_s = 0.0, bytes = 0.0;
     int64_t recomputed = 0;
@@ -164,6 +173,49 @@ struct pdlp_solver {
   } while (0)
 
 #define PDLP_LAUNCH(s) PDLP_HIP(s, hipGetLastError())
+
+// ------------------------------------------------------------------------------------------
+// The scratch array of pdlp_unroll_forward_noalloc: device memory for the checkpoints,
+// projection masks, adjoints and staging of an unrolled pass, for callers that cannot
+// allocate.  Each GPU holds its own copy (at its own address) from the module load until the
+// process ends.  Host code never passes `scratch` itself to a kernel or a copy: on the host
+// the name only stands in for the symbol.  Its device address on each GPU is looked up once
+// (hipGetSymbolAddress, with that GPU current, at the first pdlp_create on it) and every use
+// goes through that address.  Every no-alloc call on a GPU shares the array: a call claims
+// it by bumping the GPU's generation, and a backward pass checks that its forward still owns
+// it.  Calls that overlap on one GPU race.
+// ------------------------------------------------------------------------------------------
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxScratchDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+struct ScratchSlot {
+  unsigned char* ptr;      // device address of `scratch` on this GPU (nullptr until looked up)
+  uint64_t gen;            // claims so far
+  hipError_t err;          // result of the lookup
+  bool tried;
+};
+std::mutex g_scratch_mu;
+ScratchSlot g_scratch[kMaxScratchDevices] = {};
+
+// Looks up the scratch array's address on GPU `dev`, which must be current; once per GPU.
+void scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxScratchDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  ScratchSlot& sl = g_scratch[dev];
+  if (sl.tried) return;
+  sl.tried = true;
+  void* p = nullptr;
+  sl.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (sl.err == hipSuccess) sl.ptr = static_cast<unsigned char*>(p);
+  else (void)hipGetLastError();
+}
+
+}  // namespace
 
 namespace {
 
@@ -485,11 +537,9 @@ int launch_spmv(pdlp_solver* s, const CsrDev& A, const double* in0, const double
 int power_iterate(pdlp_solver* s, double* v, double* t, double* w) {
   int rc;
   const int64_t n = s->n;
-  {
-    std::vector<double> ones(static_cast<size_t>(n), 1.0 / std::sqrt(double(n)));
-    PDLP_HIP(s, hipMemcpy(v, ones.data(), size_t(n) * 8, hipMemcpyHostToDevice));
-  }
   const int gn = grid_rows(n, s->maxG);
+  k_fill<<<gn, kBlock, 0, s->stream>>>(v, 1.0 / std::sqrt(double(n)), int(n));
+  PDLP_LAUNCH(s);
   for (int it = 0; it < s->opts.power_iters; ++it) {
     if ((rc = launch_spmv(s, s->K, v, nullptr, 0, t, nullptr, 0, kPredAlways, 0))) return rc;
     if ((rc = launch_spmv(s, s->KT, t, nullptr, 0, w, nullptr, 0, kPredAlways, 0))) return rc;
@@ -851,6 +901,8 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
 
   int dev = 0;
   PDLP_HIP(s, hipGetDevice(&dev));
+  s->device = dev;
+  scratch_setup(dev);
   int ncu = 0;
   PDLP_HIP(s, hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   s->maxG = std::max(1, ncu * 8);
@@ -1013,38 +1065,99 @@ int unroll_reserve(pdlp_solver* s, int64_t nseg, int64_t S) {
   const size_t N = size_t(s->n), M = size_t(s->m);
   int rc;
   if (U.cap_seg < 0) {
-    if ((rc = unroll_alloc(s, &U.ct, N)) || (rc = unroll_alloc(s, &U.qt, M)) ||
-        (rc = unroll_alloc(s, &U.gin, N + M)) || (rc = unroll_alloc(s, &U.z, N + 2 * M)) ||
-        (rc = unroll_alloc(s, &U.xb, N)) || (rc = unroll_alloc(s, &U.ub, N)) ||
-        (rc = unroll_alloc(s, &U.vb, M)) || (rc = unroll_alloc(s, &U.cb, N + M)) ||
-        (rc = unroll_alloc(s, &U.out, N + M)))
+    if ((rc = unroll_alloc(s, &U.own.ct, N)) || (rc = unroll_alloc(s, &U.own.qt, M)) ||
+        (rc = unroll_alloc(s, &U.own.gin, N + M)) || (rc = unroll_alloc(s, &U.own.z, N + 2 * M)) ||
+        (rc = unroll_alloc(s, &U.own.xb, N)) || (rc = unroll_alloc(s, &U.own.ub, N)) ||
+        (rc = unroll_alloc(s, &U.own.vb, M)) || (rc = unroll_alloc(s, &U.own.cb, N + M)) ||
+        (rc = unroll_alloc(s, &U.own.out, N + M)))
       return rc;
     U.cap_seg = 0;
     U.cap_S = 0;
   }
   if (nseg > U.cap_seg) {
-    if (U.ck) {
+    if (U.own.ck) {
       PDLP_HIP(s, hipStreamSynchronize(s->stream));
-      PDLP_HIP(s, hipFree(U.ck));
-      U.allocs.erase(std::find(U.allocs.begin(), U.allocs.end(), static_cast<void*>(U.ck)));
+      PDLP_HIP(s, hipFree(U.own.ck));
+      U.allocs.erase(std::find(U.allocs.begin(), U.allocs.end(), static_cast<void*>(U.own.ck)));
       U.bytes -= double(std::max<int64_t>(U.cap_seg, 1)) * double(N + 2 * M) * 8.0;
-      U.ck = nullptr;
+      U.own.ck = nullptr;
     }
-    if ((rc = unroll_alloc(s, &U.ck, size_t(nseg) * (N + 2 * M)))) return rc;
+    if ((rc = unroll_alloc(s, &U.own.ck, size_t(nseg) * (N + 2 * M)))) return rc;
     U.cap_seg = nseg;
   }
   if (S > U.cap_S) {
-    if (U.mask) {
+    if (U.own.mask) {
       PDLP_HIP(s, hipStreamSynchronize(s->stream));
-      PDLP_HIP(s, hipFree(U.mask));
-      U.allocs.erase(std::find(U.allocs.begin(), U.allocs.end(), static_cast<void*>(U.mask)));
+      PDLP_HIP(s, hipFree(U.own.mask));
+      U.allocs.erase(std::find(U.allocs.begin(), U.allocs.end(), static_cast<void*>(U.own.mask)));
       U.bytes -= double(std::max<int64_t>(U.cap_S, 1)) * double(N + M);
-      U.mask = nullptr;
+      U.own.mask = nullptr;
     }
-    if ((rc = unroll_alloc(s, &U.mask, size_t(S) * (N + M)))) return rc;
+    if ((rc = unroll_alloc(s, &U.own.mask, size_t(S) * (N + M)))) return rc;
     U.cap_S = S;
   }
   return 0;
+}
+
+// The buffers of an unrolled pass with nseg checkpoints and segments of S steps, carved from
+// the per-GPU scratch array instead of allocated.  Fails (nothing enqueued, nothing claimed)
+// when they exceed the array.
+int unroll_carve_scratch(pdlp_solver* s, int64_t nseg, int64_t S) {
+  auto& U = s->U;
+  const double N = double(s->n), M = double(s->m);
+  // 256-byte aligned pieces: nine vectors of n and m values, the checkpoints, the masks
+  const double lens[11] = {N, M, N + M, N + 2 * M, N, N, M, N + M, N + M, double(nseg) * (N + 2 * M),
+                           0.0};
+  double need = 0.0;
+  for (int i = 0; i < 10; ++i) need += std::ceil(lens[i] * 8.0 / 256.0) * 256.0;
+  need += std::ceil(double(S) * (N + M) / 256.0) * 256.0;
+  if (need > double(kScratchBytes)) {
+    s->err = "unroll (no-alloc): the buffers need " + std::to_string(int64_t(need)) +
+             " bytes, more than the " + std::to_string(kScratchBytes) +
+             "-byte scratch array (fewer checkpoints or a shorter segment need less)";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  unsigned char* base = nullptr;
+  {
+    const int dev = s->device;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ScratchSlot* sl = (dev >= 0 && dev < kMaxScratchDevices) ? &g_scratch[dev] : nullptr;
+    if (!sl || !sl->ptr) {
+      s->err = std::string("unroll (no-alloc): no scratch array on this GPU: ") +
+               (sl && sl->tried ? hipGetErrorString(sl->err) : "device index out of range");
+      return PDLP_ERR_DEVICE;
+    }
+    sl->gen += 1;
+    U.scratch_gen = sl->gen;
+    base = sl->ptr;
+  }
+  size_t off = 0;
+  auto take = [&](double len_bytes) {
+    unsigned char* p = base + off;
+    off += size_t(std::ceil(len_bytes / 256.0) * 256.0);
+    return p;
+  };
+  auto takev = [&](double len) { return reinterpret_cast<double*>(take(len * 8.0)); };
+  U.b.ct = takev(lens[0]);
+  U.b.qt = takev(lens[1]);
+  U.b.gin = takev(lens[2]);
+  U.b.z = takev(lens[3]);
+  U.b.xb = takev(lens[4]);
+  U.b.ub = takev(lens[5]);
+  U.b.vb = takev(lens[6]);
+  U.b.cb = takev(lens[7]);
+  U.b.out = takev(lens[8]);
+  U.b.ck = takev(lens[9]);
+  U.b.mask = take(double(S) * (N + M));
+  U.in_scratch = true;
+  return 0;
+}
+
+// The scratch array still holds the buffers of this solver's last no-alloc forward pass.
+bool unroll_scratch_owned(const pdlp_solver* s) {
+  const int dev = s->device;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return dev >= 0 && dev < kMaxScratchDevices && g_scratch[dev].gen == s->U.scratch_gen;
 }
 
 // One fused CSR pass: out rows of A from the product with `in`, then epi.row per row.
@@ -1071,16 +1184,16 @@ int unroll_copy(pdlp_solver* s, const double* src, double* dst, int64_t len) {
   return 0;
 }
 
-// Forward step t -> t + 1 on U.z, recording the projection masks into `slot` (n + m bytes).
+// Forward step t -> t + 1 on U.b.z, recording the projection masks into `slot` (n + m bytes).
 int unroll_fwd_step(pdlp_solver* s, uint8_t* slot) {
   auto& U = s->U;
   int rc;
-  double* x = U.z;
-  double* y = U.z + s->n;
-  double* kx = U.z + s->n + s->m;
-  const UFwdPrimal ep{U.ct, s->B.l, s->B.u, x, slot, U.eta / U.omega};
+  double* x = U.b.z;
+  double* y = U.b.z + s->n;
+  double* kx = U.b.z + s->n + s->m;
+  const UFwdPrimal ep{U.b.ct, s->B.l, s->B.u, x, slot, U.eta / U.omega};
   if ((rc = launch_fused(s, s->KT, y, ep))) return rc;
-  const UFwdDual ed{U.qt, y, kx, slot + s->n, U.eta * U.omega, s->B.m1};
+  const UFwdDual ed{U.b.qt, y, kx, slot + s->n, U.eta * U.omega, s->B.m1};
   return launch_fused(s, s->K, x, ed);
 }
 
@@ -1093,7 +1206,7 @@ int stage_in(pdlp_solver* s, const double* src, double* dst, int64_t len) {
 }
 
 int unroll_forward_impl(pdlp_solver* s, const double* c, const double* q, int64_t T, int64_t segment,
-                        double eta, double omega, double* x_T, double* y_T) {
+                        double eta, double omega, double* x_T, double* y_T, bool noalloc) {
   auto& U = s->U;
   int rc;
   if (T < 0 || segment < 0 || !(std::isfinite(eta) && std::isfinite(omega))) {
@@ -1105,10 +1218,16 @@ int unroll_forward_impl(pdlp_solver* s, const double* c, const double* q, int64_
   const int64_t nseg = (T + S - 1) / S;
   const double t0 = now_s();
   U.ready = false;
-  if ((rc = unroll_reserve(s, std::max<int64_t>(nseg, 1), S))) return rc;
+  if (noalloc) {
+    if ((rc = unroll_carve_scratch(s, std::max<int64_t>(nseg, 1), S))) return rc;
+  } else {
+    if ((rc = unroll_reserve(s, std::max<int64_t>(nseg, 1), S))) return rc;
+    U.b = U.own;
+    U.in_scratch = false;
+  }
   if (eta <= 0.0) {
     if (s->eta_pow <= 0.0) {
-      if ((rc = power_iterate(s, U.xb, U.vb, U.ub))) return rc;
+      if ((rc = power_iterate(s, U.b.xb, U.b.vb, U.b.ub))) return rc;
       double pn2 = 0.0;
       PDLP_HIP(s, hipMemcpyAsync(&pn2, &s->st->pow_norm2, sizeof(double), hipMemcpyDeviceToHost, s->stream));
       PDLP_HIP(s, hipStreamSynchronize(s->stream));
@@ -1125,25 +1244,25 @@ int unroll_forward_impl(pdlp_solver* s, const double* c, const double* q, int64_
   U.nseg = nseg;
   // c~ = D2 c, q~ = D1 q (the LP's own c, q when null), z0 = (proj_X(0), 0, K~ proj_X(0))
   if (c) {
-    if ((rc = read_n(s, c, U.gin))) return rc;
-  } else if ((rc = stage_in(s, s->B.c0, U.gin, n))) {
+    if ((rc = read_n(s, c, U.b.gin))) return rc;
+  } else if ((rc = stage_in(s, s->B.c0, U.b.gin, n))) {
     return rc;
   }
-  if ((rc = stage_in(s, q ? q : s->B.q0, U.gin + n, m))) return rc;
+  if ((rc = stage_in(s, q ? q : s->B.q0, U.b.gin + n, m))) return rc;
   const int gE = s->gE;
-  k_unroll_start<<<gE, kBlock, 0, s->stream>>>(U.gin, U.gin + n, s->B.D1, s->B.D2, s->B.l, s->B.u, U.ct,
-                                               U.qt, U.z, U.z + n, int(n), int(m));
+  k_unroll_start<<<gE, kBlock, 0, s->stream>>>(U.b.gin, U.b.gin + n, s->B.D1, s->B.D2, s->B.l, s->B.u, U.b.ct,
+                                               U.b.qt, U.b.z, U.b.z + n, int(n), int(m));
   PDLP_LAUNCH(s);
-  if ((rc = launch_spmv(s, s->K, U.z, nullptr, 0, U.z + n + m, nullptr, 0, kPredAlways, 0))) return rc;
+  if ((rc = launch_spmv(s, s->K, U.b.z, nullptr, 0, U.b.z + n + m, nullptr, 0, kPredAlways, 0))) return rc;
   const int64_t zlen = n + 2 * m;
   for (int64_t t = 0; t < T; ++t) {
-    if (t % S == 0 && (rc = unroll_copy(s, U.z, U.ck + (t / S) * zlen, zlen))) return rc;
-    if ((rc = unroll_fwd_step(s, U.mask + (t % S) * (n + m)))) return rc;
+    if (t % S == 0 && (rc = unroll_copy(s, U.b.z, U.b.ck + (t / S) * zlen, zlen))) return rc;
+    if ((rc = unroll_fwd_step(s, U.b.mask + (t % S) * (n + m)))) return rc;
   }
-  k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.z, s->B.D2, int(n), U.z + n, s->B.D1, int(m), U.out);
+  k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.b.z, s->B.D2, int(n), U.b.z + n, s->B.D1, int(m), U.b.out);
   PDLP_LAUNCH(s);
-  if ((rc = write_n(s, x_T, U.out))) return rc;
-  if ((rc = write_output(s, y_T, U.out + n, size_t(m) * 8))) return rc;
+  if ((rc = write_n(s, x_T, U.b.out))) return rc;
+  if ((rc = write_output(s, y_T, U.b.out + n, size_t(m) * 8))) return rc;
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
   U.ready = true;
   U.masks_last = true;
@@ -1158,49 +1277,55 @@ int unroll_backward_impl(pdlp_solver* s, const double* gx, const double* gy, dou
     s->err = "unroll backward: no forward pass to differentiate";
     return PDLP_ERR_INVALID_STATE;
   }
+  if (U.in_scratch && !unroll_scratch_owned(s)) {
+    U.ready = false;
+    s->err = "unroll backward: another pdlp_unroll_forward_noalloc call on this GPU has reused the "
+             "scratch array since the forward pass";
+    return PDLP_ERR_INVALID_STATE;
+  }
   const int64_t n = s->n, m = s->m, nm = n + m, zlen = n + 2 * m;
   const double t0 = now_s();
   const double tau = U.eta / U.omega, sigma = U.eta * U.omega;
   const int gE = s->gE;
-  if (gx && (rc = read_n(s, gx, U.gin))) return rc;
-  if (gy && (rc = stage_in(s, gy, U.gin + n, m))) return rc;
+  if (gx && (rc = read_n(s, gx, U.b.gin))) return rc;
+  if (gy && (rc = stage_in(s, gy, U.b.gin + n, m))) return rc;
   U.recomputed = 0;
   if (U.nseg == 0) {
     // x_0 = proj_X(0) does not depend on (c, q)
-    k_unroll_seed<<<gE, kBlock, 0, s->stream>>>(nullptr, nullptr, s->B.D1, s->B.D2, U.mask, U.xb, U.vb,
-                                                U.cb, U.cb + n, int(n), int(m), s->B.m1);
+    k_unroll_seed<<<gE, kBlock, 0, s->stream>>>(nullptr, nullptr, s->B.D1, s->B.D2, U.b.mask, U.b.xb, U.b.vb,
+                                                U.b.cb, U.b.cb + n, int(n), int(m), s->B.m1);
     PDLP_LAUNCH(s);
   }
   for (int64_t seg = U.nseg - 1; seg >= 0; --seg) {
     const int64_t ta = seg * U.S, tb = std::min(U.T, ta + U.S);
     const bool last = seg == U.nseg - 1;
     if (!(last && U.masks_last)) {
-      if ((rc = unroll_copy(s, U.ck + seg * zlen, U.z, zlen))) return rc;
+      if ((rc = unroll_copy(s, U.b.ck + seg * zlen, U.b.z, zlen))) return rc;
       for (int64_t t = ta; t < tb; ++t)
-        if ((rc = unroll_fwd_step(s, U.mask + (t - ta) * nm))) return rc;
+        if ((rc = unroll_fwd_step(s, U.b.mask + (t - ta) * nm))) return rc;
       U.recomputed += tb - ta;
     }
     if (last) {
-      k_unroll_seed<<<gE, kBlock, 0, s->stream>>>(gx ? U.gin : nullptr, gy ? U.gin + n : nullptr, s->B.D1,
-                                                  s->B.D2, U.mask + (tb - 1 - ta) * nm + n, U.xb, U.vb, U.cb,
-                                                  U.cb + n, int(n), int(m), s->B.m1);
+      k_unroll_seed<<<gE, kBlock, 0, s->stream>>>(gx ? U.b.gin : nullptr, gy ? U.b.gin + n : nullptr, s->B.D1,
+                                                  s->B.D2, U.b.mask + (tb - 1 - ta) * nm + n, U.b.xb, U.b.vb, U.b.cb,
+                                                  U.b.cb + n, int(n), int(m), s->B.m1);
       PDLP_LAUNCH(s);
     }
     for (int64_t t = tb - 1; t >= ta; --t) {
-      const uint8_t* slot = U.mask + (t - ta) * nm;
-      const UBwdPrimal ep{slot, U.xb, U.ub, U.cb, tau, sigma};
-      if ((rc = launch_fused(s, s->KT, U.vb, ep))) return rc;
+      const uint8_t* slot = U.b.mask + (t - ta) * nm;
+      const UBwdPrimal ep{slot, U.b.xb, U.b.ub, U.b.cb, tau, sigma};
+      if ((rc = launch_fused(s, s->KT, U.b.vb, ep))) return rc;
       const uint8_t* my_prev = (t > ta) ? slot - nm + n : nullptr;
-      const double* y_prev = (t == ta && t > 0) ? U.ck + seg * zlen + n : nullptr;
-      const UBwdDual ed{U.vb, U.cb + n, my_prev, y_prev, tau, sigma, s->B.m1};
-      if ((rc = launch_fused(s, s->K, U.ub, ed))) return rc;
+      const double* y_prev = (t == ta && t > 0) ? U.b.ck + seg * zlen + n : nullptr;
+      const UBwdDual ed{U.b.vb, U.b.cb + n, my_prev, y_prev, tau, sigma, s->B.m1};
+      if ((rc = launch_fused(s, s->K, U.b.ub, ed))) return rc;
     }
   }
   U.masks_last = U.nseg == 1;
-  k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.cb, s->B.D2, int(n), U.cb + n, s->B.D1, int(m), U.out);
+  k_unroll_unscale<<<gE, kBlock, 0, s->stream>>>(U.b.cb, s->B.D2, int(n), U.b.cb + n, s->B.D1, int(m), U.b.out);
   PDLP_LAUNCH(s);
-  if ((rc = write_n(s, gc, U.out))) return rc;
-  if ((rc = write_output(s, gq, U.out + n, size_t(m) * 8))) return rc;
+  if ((rc = write_n(s, gc, U.b.out))) return rc;
+  if ((rc = write_output(s, gq, U.b.out + n, size_t(m) * 8))) return rc;
   PDLP_HIP(s, hipStreamSynchronize(s->stream));
   U.bwd_s = now_s() - t0;
   return 0;
@@ -1564,10 +1689,21 @@ int pdlp_unroll_forward(pdlp_solver* s, const double* c, const double* q, int64_
                         int64_t segment, double eta, double omega, double* x_T, double* y_T) {
   if (!s) return PDLP_ERR_INVALID_ARGUMENT;
   try {
-    return unroll_forward_impl(s, c, q, steps, segment, eta, omega, x_T, y_T);
+    return unroll_forward_impl(s, c, q, steps, segment, eta, omega, x_T, y_T, false);
   } catch (const std::bad_alloc&) {
     s->err = "host out of memory";
     return PDLP_ERR_OUT_OF_MEMORY;
+  } catch (...) {
+    s->err = "unexpected host exception";
+    return PDLP_ERR_DEVICE;
+  }
+}
+
+int pdlp_unroll_forward_noalloc(pdlp_solver* s, const double* c, const double* q, int64_t steps,
+                                int64_t segment, double eta, double omega, double* x_T, double* y_T) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  try {
+    return unroll_forward_impl(s, c, q, steps, segment, eta, omega, x_T, y_T, true);
   } catch (...) {
     s->err = "unexpected host exception";
     return PDLP_ERR_DEVICE;

@@ -26,7 +26,8 @@ EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pd
             "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
             "pdlp_build_schedule", "pdlp_build_panel_layout", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
             "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error",
-            "pdlp_unroll_forward", "pdlp_unroll_backward", "pdlp_unroll_get_info"]
+            "pdlp_unroll_forward", "pdlp_unroll_forward_noalloc", "pdlp_unroll_backward",
+            "pdlp_unroll_get_info"]
 
 
 class Options(ctypes.Structure):
@@ -152,6 +153,8 @@ def lib() -> ctypes.CDLL:
         L.pdlp_batch_last_error.restype = ctypes.c_char_p
         L.pdlp_unroll_forward.argtypes = [P, P, P, I64, I64, ctypes.c_double, ctypes.c_double, P, P]
         L.pdlp_unroll_forward.restype = ctypes.c_int
+        L.pdlp_unroll_forward_noalloc.argtypes = [P, P, P, I64, I64, ctypes.c_double, ctypes.c_double, P, P]
+        L.pdlp_unroll_forward_noalloc.restype = ctypes.c_int
         L.pdlp_unroll_backward.argtypes = [P, P, P, P, P]
         L.pdlp_unroll_backward.restype = ctypes.c_int
         L.pdlp_unroll_get_info.argtypes = [P, ctypes.POINTER(UnrollInfo)]
@@ -407,6 +410,20 @@ class Solver:
         px, py = _out_ptr(xo), _out_ptr(yo)
         self._check(lib().pdlp_unroll_forward(self._h, pc, pq, int(steps), int(segment), float(eta),
                                               float(omega), px, py if self.m else None))
+        self.unroll_id = getattr(self, "unroll_id", 0) + 1
+        return xo, yo
+
+    def unroll_forward_noalloc(self, c=None, q=None, steps=500, segment=50, eta=0.0, omega=0.0,
+                               x_out=None, y_out=None):
+        """unroll_forward with the unroll's buffers in the library's per-GPU scratch array
+        (pdlp_unroll_forward_noalloc: no device allocation)."""
+        pc, kc = _ptr(c, np.float64)
+        pq, kq = _ptr(q, np.float64)
+        xo = np.empty(self.n) if x_out is None else x_out
+        yo = np.empty(self.m) if y_out is None else y_out
+        px, py = _out_ptr(xo), _out_ptr(yo)
+        self._check(lib().pdlp_unroll_forward_noalloc(self._h, pc, pq, int(steps), int(segment), float(eta),
+                                                      float(omega), px, py if self.m else None))
         self.unroll_id = getattr(self, "unroll_id", 0) + 1
         return xo, yo
 
