@@ -127,6 +127,10 @@ typedef struct pdlp_info {
   double create_seconds;         /* host wall time of pdlp_create (copy, transpose, scaling)  */
   double solve_seconds;          /* host wall time of the last pdlp_solve                     */
   double step_bytes;             /* algorithmic HBM bytes of one accepted PDHG step           */
+  int32_t layout_K, layout_KT;   /* layout of the K~ and K~^T copies: 0 plain rows, 1 XCD column
+                                    panels, 2 LDS slices (every gather from LDS), 3 XCD panels
+                                    with each panel's first columns staged in LDS              */
+  int32_t panels_K, panels_KT;   /* column panels of each copy (1 in the plain layout)         */
 } pdlp_info;
 
 /* Scalars of a checkpoint (pdlp_get_state / pdlp_set_state). */
@@ -381,9 +385,24 @@ int pdlp_get_trace(const pdlp_solver *s, pdlp_attempt_rec *att, int64_t att_cap,
 int pdlp_spmv(pdlp_solver *s, int transpose, const double *x, double *out);
 
 /* pdlp_kernel_times - with options.time_kernels set, the summed HIP-event time in ms and
- * the launch count of the primal step kernel (K~^T product, times[0], counts[0]) and of the
- * dual step kernel (K~ product, times[1], counts[1]) over all solves so far. */
+ * the count of the attempt slots that ran, for the primal step (K~^T product fused with the
+ * primal update: times[0], counts[0]) and the dual step (K~ product fused with the dual update
+ * and the step-size rule: times[1], counts[1]) over all solves since the last reset.  A slot
+ * runs when its attempt does; slots left idle by a pending check, the end of the solve or
+ * the iteration limit are not counted.  With time_kernels the solver runs one block at a
+ * time and without graphs, and a block stops at the iteration limit instead of idling. */
 int pdlp_kernel_times(const pdlp_solver *s, double *times_ms, int64_t *counts);
+
+/* pdlp_set_kernel_timing - turn kernel timing (options.time_kernels) on (1) or off (0) for
+ * the next solves of s.  The arithmetic is the same either way; with it off, whole blocks
+ * replay as captured graphs again (options.use_graphs). */
+int pdlp_set_kernel_timing(pdlp_solver *s, int on);
+
+/* pdlp_pass_times - the same split into four passes (times_ms[4], counts[4]): the primal
+ * first pass (the K~^T product, or its panel pass), the primal combine (the panel partials
+ * added and the primal update; 0 in the plain layout, where one kernel does both), the dual
+ * first pass and the dual combine (with the step-size tail). */
+int pdlp_pass_times(const pdlp_solver *s, double *times_ms, int64_t *counts);
 
 /* pdlp_reset_kernel_times - zero the counters of pdlp_kernel_times. */
 int pdlp_reset_kernel_times(pdlp_solver *s);

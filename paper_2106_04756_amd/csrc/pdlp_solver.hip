@@ -99,9 +99,14 @@ struct pdlp_solver {
   const int32_t* d_col_user = nullptr;
   const int32_t* d_col_int = nullptr;
   double* permbuf = nullptr;           // n values of staging for the reordering gathers
+  // kernel timing (options.time_kernels): 5 events per attempt slot of a block, around the
+  // primal first pass, the primal combine, the dual first pass and the dual combine + tail
   std::vector<hipEvent_t> tev[2];
-  double t_ms[2] = {0.0, 0.0};
-  int64_t t_cnt[2] = {0, 0};
+  int blk_slots[2] = {0, 0};           // attempt slots of the block last enqueued at each parity
+  double t_ms[4] = {0.0, 0.0, 0.0, 0.0};
+  int64_t t_cnt[4] = {0, 0, 0, 0};
+  int64_t timed_attempts = 0;          // attempts counted before the block being timed
+  bool kkt_stale = false;              // the returned point's KKT error is not evaluated yet
   std::string err;
   bool solved = false;
   bool initial_checked = false;
@@ -612,7 +617,7 @@ int enqueue_mp_trial(pdlp_solver* s) {
   return 0;
 }
 
-int enqueue_block(pdlp_solver* s, int par) {
+int enqueue_block(pdlp_solver* s, int par, int slots) {
   const pdlp_options& o = s->opts;
   unsigned* tk = s->tickets;
   Bufs& B = s->B;
@@ -622,20 +627,28 @@ int enqueue_block(pdlp_solver* s, int par) {
   const int nslotB = panK ? s->gBc : s->gB + s->K.nsplit;
   unsigned* tkDual = ticket_for(s, gDual, kTkDual);
   int rc;
-  for (int i = 0; i < o.check_every; ++i) {
-    if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i], s->stream));
+  hipEvent_t* ev = o.time_kernels ? s->tev[par].data() : nullptr;
+  auto mark = [&](int i, int j) -> int {
+    if (ev) PDLP_HIP(s, hipEventRecord(ev[5 * i + j], s->stream));
+    return 0;
+  };
+  for (int i = 0; i < slots; ++i) {
+    if ((rc = mark(i, 0))) return rc;
     if (panT) {
       launch_panel_rows(s, s->KT, s->gA, B.Y[0], B.Y[1], 1, s->partPT, kPredAttemptKty, kProd);
       PDLP_LAUNCH(s);
+      if ((rc = mark(i, 1))) return rc;
       k_primal_combine<<<s->gAc, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partPT, s->partA);
     } else {
+      if ((rc = mark(i, 1))) return rc;
       k_primal<<<s->gA, kBlock, 0, s->stream>>>(s->KT, s->st, B, s->partA);
     }
     PDLP_LAUNCH(s);
-    if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 1], s->stream));
+    if ((rc = mark(i, 2))) return rc;
     if (o.step_policy == 2) {
+      if ((rc = mark(i, 3))) return rc;
       if ((rc = enqueue_mp_trial(s))) return rc;
-      if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 2], s->stream));
+      if ((rc = mark(i, 4))) return rc;
       if (o.trace_iters > 0) {
         k_snapshot<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkSnap);
         PDLP_LAUNCH(s);
@@ -645,14 +658,16 @@ int enqueue_block(pdlp_solver* s, int par) {
     if (panK) {
       launch_panel_rows(s, s->K, s->gB, B.X[1], B.X[0], 1, s->partPK, kPredAttempt, kProd);
       PDLP_LAUNCH(s);
+      if ((rc = mark(i, 3))) return rc;
       k_dual_combine<<<s->gBc, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partPK, s->partA, nslotA,
                                                        s->partB, tkDual);
     } else {
+      if ((rc = mark(i, 3))) return rc;
       k_dual<<<s->gB, kBlock, 0, s->stream>>>(s->K, s->st, B, s->partA, nslotA, s->partB, tkDual);
     }
     PDLP_LAUNCH(s);
     if ((rc = launch_tail(s, gDual, kTailAttempt, 0, s->partB, nslotB, s->partA, nslotA))) return rc;
-    if (o.time_kernels) PDLP_HIP(s, hipEventRecord(s->tev[par][3 * i + 2], s->stream));
+    if ((rc = mark(i, 4))) return rc;
     if (o.trace_iters > 0) {
       k_snapshot<<<s->gE, kBlock, 0, s->stream>>>(s->st, B, tk + kTkSnap);
       PDLP_LAUNCH(s);
@@ -684,7 +699,7 @@ int enqueue_block(pdlp_solver* s, int par) {
 // block of the solve.  On any failure the solver keeps launching kernel by kernel.
 void capture_block_graphs(pdlp_solver* s) {
   s->graphs_tried = true;
-  if (!s->opts.use_graphs || s->opts.time_kernels) return;
+  if (!s->opts.use_graphs) return;
   if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipGetLastError();
     s->cap_stream = nullptr;
@@ -695,7 +710,7 @@ void capture_block_graphs(pdlp_solver* s) {
   for (int par = 0; par < 2 && ok; ++par) {
     s->stream = s->cap_stream;
     ok = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-    const int rc = ok ? enqueue_block(s, par) : 0;
+    const int rc = ok ? enqueue_block(s, par, s->opts.check_every) : 0;
     hipGraph_t g = nullptr;
     const bool ended = ok && hipStreamEndCapture(s->cap_stream, &g) == hipSuccess;
     ok = ok && rc == 0 && ended && g &&
@@ -715,30 +730,47 @@ void capture_block_graphs(pdlp_solver* s) {
   }
 }
 
-// Enqueues block `par` (graph replay or kernel by kernel) and the event the host waits on.
-int launch_block(pdlp_solver* s, int par) {
-  if (s->gexec[par]) {
+// Enqueues block `par` of `slots` attempt slots and its check (the captured graph when the
+// block is whole, else kernel by kernel) and the event the host waits on.
+int launch_block(pdlp_solver* s, int par, int slots) {
+  s->blk_slots[par] = slots;
+  if (s->gexec[par] && slots == s->opts.check_every && !s->opts.time_kernels) {
     PDLP_HIP(s, hipGraphLaunch(s->gexec[par], s->stream));
   } else {
     int rc;
-    if ((rc = enqueue_block(s, par))) return rc;
+    if ((rc = enqueue_block(s, par, slots))) return rc;
   }
   PDLP_HIP(s, hipEventRecord(s->blk_ev[par], s->stream));
+  return 0;
+}
+
+// Waits for block `par`.  With kernel timing (blocks run one at a time) it adds the event
+// times of the slots whose attempt ran: the first (attempts after - attempts before) slots of
+// the block, since a slot that does not run (a check pending, the solve over, the iteration
+// limit reached) is followed only by slots that do not run either.
+// The events of kernel timing: 5 per attempt slot of each of the two block parities.
+int make_timing_events(pdlp_solver* s) {
+  for (int b = 0; b < 2; ++b) {
+    if (!s->tev[b].empty()) continue;
+    s->tev[b].assign(size_t(5 * s->opts.check_every), nullptr);
+    for (auto& e : s->tev[b]) PDLP_HIP(s, hipEventCreate(&e));
+  }
   return 0;
 }
 
 int wait_block(pdlp_solver* s, int par) {
   PDLP_HIP(s, hipEventSynchronize(s->blk_ev[par]));
   if (s->opts.time_kernels) {
-    for (int i = 0; i < s->opts.check_every; ++i) {
-      float a = 0.f, b = 0.f;
-      PDLP_HIP(s, hipEventElapsedTime(&a, s->tev[par][3 * i], s->tev[par][3 * i + 1]));
-      PDLP_HIP(s, hipEventElapsedTime(&b, s->tev[par][3 * i + 1], s->tev[par][3 * i + 2]));
-      s->t_ms[0] += a;
-      s->t_ms[1] += b;
+    const int64_t ran = std::min<int64_t>(s->h_st[par].attempts - s->timed_attempts, s->blk_slots[par]);
+    s->timed_attempts = s->h_st[par].attempts;
+    for (int i = 0; i < ran; ++i) {
+      for (int j = 0; j < 4; ++j) {
+        float t = 0.f;
+        PDLP_HIP(s, hipEventElapsedTime(&t, s->tev[par][5 * i + j], s->tev[par][5 * i + j + 1]));
+        s->t_ms[j] += t;
+      }
     }
-    s->t_cnt[0] += s->opts.check_every;
-    s->t_cnt[1] += s->opts.check_every;
+    for (int j = 0; j < 4; ++j) s->t_cnt[j] += std::max<int64_t>(ran, 0);
   }
   return 0;
 }
@@ -1013,13 +1045,8 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
   PDLP_HIP(s, s->alloc(&s->st, 1));
   PDLP_HIP(s, hipMemcpy(s->st, &h, sizeof(DevState), hipMemcpyHostToDevice));
   PDLP_HIP(s, hipHostMalloc(reinterpret_cast<void**>(&s->h_st), 2 * sizeof(DevState), hipHostMallocDefault));
-  for (int b = 0; b < 2; ++b) {
-    PDLP_HIP(s, hipEventCreate(&s->blk_ev[b]));
-    if (s->opts.time_kernels) {
-      s->tev[b].resize(size_t(3 * s->opts.check_every));
-      for (auto& e : s->tev[b]) PDLP_HIP(s, hipEventCreate(&e));
-    }
-  }
+  for (int b = 0; b < 2; ++b) PDLP_HIP(s, hipEventCreate(&s->blk_ev[b]));
+  if (s->opts.time_kernels && (rc = make_timing_events(s))) return rc;
 
   // preconditioning, then x0 = proj_X(0), y0 = 0 and K x0
   if ((rc = precondition(s))) return rc;
@@ -1331,6 +1358,17 @@ int unroll_backward_impl(pdlp_solver* s, const double* gx, const double* gy, dou
   return 0;
 }
 
+// The KKT error of the returned point when the solve ended without a terminating check: the
+// current iterate, which needs K~^T y of the current y.
+int settle_kkt(pdlp_solver* s) {
+  if (!s->kkt_stale) return 0;
+  int rc;
+  if ((rc = launch_spmv(s, s->KT, s->B.Y[0], s->B.Y[1], 1, s->B.KTy, nullptr, 0, kPredKty, 2))) return rc;
+  if ((rc = enqueue_kkt(s, 2))) return rc;
+  s->kkt_stale = false;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1426,28 +1464,46 @@ int pdlp_solve(pdlp_solver* s, double tol, int64_t iter_limit) {
   }
   DevState h;
   if ((rc = read_state(s, &h))) return rc;
+  s->timed_attempts = h.attempts;
   if (!block_stops(h)) {
-    if (!s->graphs_tried) capture_block_graphs(s);
-    int b = 0;
-    for (;;) {
-      if ((rc = launch_block(s, b & 1))) return rc;
-      if (b > 0) {
-        if ((rc = wait_block(s, (b - 1) & 1))) return rc;
-        if (block_stops(s->h_st[(b - 1) & 1])) break;
+    if (!s->graphs_tried && !s->opts.time_kernels) capture_block_graphs(s);
+    // Blocks of check_every attempt slots, two in flight (one at a time with kernel timing).
+    // k_hi bounds k from above once every enqueued slot has run (a slot takes at most one
+    // step); a block is cut to iter_limit - k_hi slots when fewer remain, and when k_hi has
+    // reached the limit the host waits for the running block before enqueueing another.
+    const bool pipelined = !s->opts.time_kernels;
+    int64_t k_hi = h.k;
+    int inflight = -1;
+    for (int b = 0;; ++b) {
+      const int par = b & 1;
+      if (inflight >= 0 && (!pipelined || k_hi >= iter_limit)) {
+        if ((rc = wait_block(s, inflight))) return rc;
+        const DevState& hb = s->h_st[inflight];
+        inflight = -1;
+        if (block_stops(hb)) break;
+        k_hi = hb.k;
       }
-      ++b;
+      const int64_t room = iter_limit - k_hi;
+      const int slots = int(std::max<int64_t>(1, std::min<int64_t>(s->opts.check_every, room)));
+      if ((rc = launch_block(s, par, slots))) return rc;
+      k_hi += slots;
+      if (inflight >= 0) {
+        if ((rc = wait_block(s, inflight))) return rc;
+        if (block_stops(s->h_st[inflight])) {
+          inflight = par;
+          break;
+        }
+      }
+      inflight = par;
     }
-    if ((rc = wait_block(s, b & 1))) return rc;
+    if (inflight >= 0 && (rc = wait_block(s, inflight))) return rc;
   }
   k_mark_limit<<<1, 1, 0, s->stream>>>(s->st);
   PDLP_LAUNCH(s);
   if ((rc = read_state(s, &h))) return rc;
-  if (h.status != PDLP_OPTIMAL) {
-    // KKT error of the returned (current) point, which needs K~^T y of the current y
-    if ((rc = launch_spmv(s, s->KT, s->B.Y[0], s->B.Y[1], 1, s->B.KTy, nullptr, 0, kPredKty, 2))) return rc;
-    if ((rc = enqueue_kkt(s, 2))) return rc;
-    if ((rc = read_state(s, &h))) return rc;
-  }
+  // the KKT error of a returned current iterate (not a terminating check's candidate) is
+  // evaluated when first asked for (pdlp_get, pdlp_get_info)
+  s->kkt_stale = h.status != PDLP_OPTIMAL;
   s->solved = true;
   s->last_status = h.status;
   s->solve_seconds = now_s() - t0;
@@ -1470,6 +1526,7 @@ int pdlp_get(const pdlp_solver* cs, double* x, double* y, double* kkt) {
   }
   if (kkt) {
     DevState h;
+    if ((rc = settle_kkt(s))) return rc;
     if ((rc = read_state(s, &h))) return rc;
     if (is_device_ptr(kkt)) PDLP_HIP(s, hipMemcpy(kkt, h.kkt, 4 * 8, hipMemcpyHostToDevice));
     else std::memcpy(kkt, h.kkt, 4 * 8);
@@ -1481,6 +1538,7 @@ int pdlp_get_info(const pdlp_solver* cs, pdlp_info* info) {
   if (!cs || !info) return PDLP_ERR_INVALID_ARGUMENT;
   DevState h;
   int rc;
+  if ((rc = settle_kkt(const_cast<pdlp_solver*>(cs)))) return rc;
   if ((rc = read_state(cs, &h))) return rc;
   std::memset(info, 0, sizeof(*info));
   info->status = cs->last_status;
@@ -1501,6 +1559,15 @@ int pdlp_get_info(const pdlp_solver* cs, pdlp_info* info) {
   info->create_seconds = cs->create_seconds;
   info->solve_seconds = cs->solve_seconds;
   info->step_bytes = cs->bytes_A + cs->bytes_B;
+  auto layout = [](const CsrDev& A) {
+    if (A.npanel <= 1) return 0;
+    if (A.lds_h <= 0) return 1;
+    return A.cis16 ? 2 : 3;
+  };
+  info->layout_K = layout(cs->K);
+  info->layout_KT = layout(cs->KT);
+  info->panels_K = std::max(1, cs->K.npanel);
+  info->panels_KT = std::max(1, cs->KT.npanel);
   return 0;
 }
 
@@ -1568,6 +1635,10 @@ int pdlp_set_state(pdlp_solver* s, const double* x, const double* y, const doubl
       !(v->omega > 0.0) || !(v->s_eta >= 0.0) || !std::isfinite(v->eta_hat) || !std::isfinite(v->omega)) {
     s->err = "invalid checkpoint scalars";
     return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  {
+    const int rc0 = settle_kkt(s);      // the last solve's returned point keeps its KKT error
+    if (rc0) return rc0;
   }
   const size_t M = size_t(s->m);
   auto get = [&](double* dst, const double* src, size_t cnt) -> int {
@@ -1668,20 +1739,41 @@ int pdlp_spmv(pdlp_solver* s, int transpose, const double* x, double* out) {
 int pdlp_kernel_times(const pdlp_solver* s, double* times_ms, int64_t* counts) {
   if (!s) return PDLP_ERR_INVALID_ARGUMENT;
   if (times_ms) {
-    times_ms[0] = s->t_ms[0];
-    times_ms[1] = s->t_ms[1];
+    times_ms[0] = s->t_ms[0] + s->t_ms[1];
+    times_ms[1] = s->t_ms[2] + s->t_ms[3];
   }
   if (counts) {
     counts[0] = s->t_cnt[0];
-    counts[1] = s->t_cnt[1];
+    counts[1] = s->t_cnt[2];
+  }
+  return 0;
+}
+
+int pdlp_set_kernel_timing(pdlp_solver* s, int on) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  if (on) {
+    const int rc = make_timing_events(s);
+    if (rc) return rc;
+  }
+  s->opts.time_kernels = on ? 1 : 0;
+  return 0;
+}
+
+int pdlp_pass_times(const pdlp_solver* s, double* times_ms, int64_t* counts) {
+  if (!s) return PDLP_ERR_INVALID_ARGUMENT;
+  for (int j = 0; j < 4; ++j) {
+    if (times_ms) times_ms[j] = s->t_ms[j];
+    if (counts) counts[j] = s->t_cnt[j];
   }
   return 0;
 }
 
 int pdlp_reset_kernel_times(pdlp_solver* s) {
   if (!s) return PDLP_ERR_INVALID_ARGUMENT;
-  s->t_ms[0] = s->t_ms[1] = 0.0;
-  s->t_cnt[0] = s->t_cnt[1] = 0;
+  for (int j = 0; j < 4; ++j) {
+    s->t_ms[j] = 0.0;
+    s->t_cnt[j] = 0;
+  }
   return 0;
 }
 

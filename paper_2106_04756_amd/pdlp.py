@@ -23,7 +23,8 @@ STATUS_NAMES = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "NUMERICAL_ERROR", 3: "NO
 EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_get_info",
             "pdlp_destroy", "pdlp_last_error", "pdlp_get_state", "pdlp_set_state",
             "pdlp_get_scaling", "pdlp_get_iterate",
-            "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_reset_kernel_times",
+            "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_pass_times", "pdlp_set_kernel_timing",
+            "pdlp_reset_kernel_times",
             "pdlp_build_schedule", "pdlp_build_panel_layout", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
             "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error",
             "pdlp_unroll_forward", "pdlp_unroll_forward_noalloc", "pdlp_unroll_backward",
@@ -55,7 +56,9 @@ class Info(ctypes.Structure):
                 ("checks", ctypes.c_int64), ("spmv_K", ctypes.c_int64), ("spmv_KT", ctypes.c_int64),
                 ("omega", ctypes.c_double), ("eta_hat", ctypes.c_double),
                 ("kkt", ctypes.c_double * 4), ("create_seconds", ctypes.c_double),
-                ("solve_seconds", ctypes.c_double), ("step_bytes", ctypes.c_double)]
+                ("solve_seconds", ctypes.c_double), ("step_bytes", ctypes.c_double),
+                ("layout_K", ctypes.c_int32), ("layout_KT", ctypes.c_int32),
+                ("panels_K", ctypes.c_int32), ("panels_KT", ctypes.c_int32)]
 
 
 class State(ctypes.Structure):
@@ -131,6 +134,10 @@ def lib() -> ctypes.CDLL:
         L.pdlp_spmv.restype = ctypes.c_int
         L.pdlp_kernel_times.argtypes = [P, P, P]
         L.pdlp_kernel_times.restype = ctypes.c_int
+        L.pdlp_set_kernel_timing.argtypes = [P, ctypes.c_int]
+        L.pdlp_set_kernel_timing.restype = ctypes.c_int
+        L.pdlp_pass_times.argtypes = [P, P, P]
+        L.pdlp_pass_times.restype = ctypes.c_int
         L.pdlp_reset_kernel_times.argtypes = [P]
         L.pdlp_reset_kernel_times.restype = ctypes.c_int
         L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P, P]
@@ -447,6 +454,19 @@ class Solver:
         t = np.zeros(2)
         c = np.zeros(2, dtype=np.int64)
         self._check(lib().pdlp_kernel_times(self._h, t.ctypes.data, c.ctypes.data))
+        return t, c
+
+    def set_kernel_timing(self, on: bool):
+        """Kernel timing (options.time_kernels) on or off for the next solves."""
+        self._check(lib().pdlp_set_kernel_timing(self._h, 1 if on else 0))
+        self.options.time_kernels = 1 if on else 0
+
+    def pass_times(self):
+        """(times_ms[4], counts[4]) of the primal first pass, primal combine, dual first pass
+        and dual combine over the slots that ran (options.time_kernels)."""
+        t = np.zeros(4)
+        c = np.zeros(4, dtype=np.int64)
+        self._check(lib().pdlp_pass_times(self._h, t.ctypes.data, c.ctypes.data))
         return t, c
 
     def reset_kernel_times(self):

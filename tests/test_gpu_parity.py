@@ -370,6 +370,37 @@ def test_graph_replay_equals_kernel_by_kernel(kw):
             assert va == vb or (isinstance(va, float) and math.isnan(va) and math.isnan(vb)), key
 
 
+@pytest.mark.parametrize("kw", [dict(), dict(LDS_MODES["slices"])])
+def test_kernel_timing_counts_the_slots_that_ran(kw):
+    """With kernel timing the solver runs one block at a time, cuts a block at the iteration
+    limit instead of idling, and counts the attempt slots that ran, in each of the four
+    passes; the iterates equal those of a graph-replayed solve bit for bit."""
+    lp = lpgen.tiny_lp()
+    say("kernel timing counts", kw)
+    a = make(lp, time_kernels=1, **kw)
+    b = make(lp, **kw)
+    for lim in (5, 25, 40, 41, 97, 160):        # inside a block, at and across checks
+        a.reset_kernel_times()
+        ia0, ib0 = a.info(), b.info()
+        a.solve(1e-30, lim)
+        b.solve(1e-30, lim)
+        ia1, ib1 = a.info(), b.info()
+        assert ia1["iterations"] == ib1["iterations"] == lim
+        d = ia1["attempts"] - ia0["attempts"]
+        assert d == ib1["attempts"] - ib0["attempts"] and d >= lim - ia0["iterations"]
+        t, c = a.pass_times()
+        assert list(c) == [d] * 4 and np.all(t >= 0), (lim, c, d)
+        tk, ck = a.kernel_times()
+        assert list(ck) == [d, d] and np.allclose(tk, [t[0] + t[1], t[2] + t[3]])
+    a.set_kernel_timing(False)                  # graphs again from here on
+    a.solve(1e-30, 240)
+    b.solve(1e-30, 240)
+    xa, ya = a.iterate()
+    xb, yb = b.iterate()
+    assert np.array_equal(xa, xb) and np.array_equal(ya, yb)
+    assert a.info()["checks"] == b.info()["checks"] >= 6
+
+
 def test_edge_cases():
     # no constraints at all: min c^T x over a box
     n = 7

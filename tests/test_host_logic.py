@@ -40,7 +40,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(B.Options) == 10 * 4 + 6 * 8 + 4 * 4 + 3 * 8 + 4 * 4
     assert ctypes.sizeof(B.AttemptRec) == 32
     assert ctypes.sizeof(B.CheckRec) == 8 + 5 * 8 + 4 * 4
-    assert ctypes.sizeof(B.Info) == 2 * 4 + 10 * 8 + 2 * 8 + 4 * 8 + 3 * 8
+    assert ctypes.sizeof(B.Info) == 2 * 4 + 10 * 8 + 2 * 8 + 4 * 8 + 3 * 8 + 4 * 4
     assert ctypes.sizeof(B.UnrollInfo) == 4 * 8 + 5 * 8 + 2 * 4
 
 
