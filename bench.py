@@ -2,22 +2,36 @@
 column counts, nnz ~1.35e8), one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
-                    [--no-unroll] [--no-truncated] [--no-policies] [--no-ablations]
-                    [--calibrate-copy]
+                    [--no-unroll] [--no-truncated] [--no-pagerank] [--no-policies]
+                    [--no-ablations] [--only-large] [--calibrate-copy]
+    python bench.py --summarize-profile DIR     # text summary of the rocprofv3 runs in DIR
 
 A step is one accepted PDHG iteration of Algorithm 1 on the whole LP: the K~^T product fused
 with the primal step, the K~ product fused with the dual step and the step-size rule, and
 (every 40 steps) the restart / termination check.  The LP is resident in HBM before timing
-starts.  Prints one JSON line.  Progress goes to stderr.  Beside the headline figures the line
-carries: the same shape with column counts truncated to [1,190]; a whole solve of the tiny LP;
-the constant-step and Malitsky-Pock policies on the large LP; the ablation switches' steps to
-KKT 1e-8 on two small LPs; the batched solver; the unrolled PDHG and its adjoint; the oracle's
-rate on the host.
+starts.  Prints one JSON line.  Progress goes to stderr.
+
+Three timed windows per LP, one after the other on the same solver:
+  * the headline: W warmup steps, then exactly K steps as pdlp_solve runs them (whole blocks of
+    40 attempt slots replayed as HIP graphs, a block cut short at the iteration limit), wall
+    clock bracketed by device synchronisation; `value` = K / seconds;
+  * kernel timing: the next K steps with HIP events around every pass of every attempt slot
+    (kernel by kernel, one block at a time), giving each pass's average duration over the
+    slots that ran: the `roofline` of the dominant kernel;
+  * whole check blocks: from the next multiple of 40, max(5, ceil(K / 40)) blocks of 40 steps,
+    each ending with its restart / termination check: `check_inclusive`.
+Beside the headline the line carries the same figures for the same shape with column counts
+truncated to [1,190] and for the PageRank LP on 5e6 nodes, a whole solve of the tiny LP, the
+constant-step and Malitsky-Pock policies, the ablation switches' steps to KKT 1e-8 on two
+small LPs, the batched solver, the unrolled PDHG and its adjoint, and the oracle's rate on
+the host.
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import json
+import math
 import os
 import sys
 import time
@@ -26,19 +40,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, vendor figure
+CHECK_EVERY = 40
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "pdlp_step_large_plain_lp.txt")
-
+PROFILE = os.path.join(ROOT, "profiles", "pdlp_step_passes_large_plain_lp.txt")
 
 # Sources that define the timed step kernels and their launches (the batched solver and the
 # unrolled adjoint live in files of their own and do not take part in the timed step).
 STEP_SOURCES = ["pdlp_kernels.hip", "pdlp_solver.hip", "pdlp_device.h", "pdlp_internal.h",
                 "host_prep.cpp", "host_prep.h"]
+
+PASS_NAMES = ["primal_pass1", "primal_combine", "dual_pass1", "dual_combine"]
+PASS_DOC = {
+    "primal_pass1": "K~^T y product, first pass (k_lds_rows<1>: panel rows of LDS slices of y; "
+                    "k_panel_rows<1> without the stage)",
+    "primal_combine": "panel partials of K~^T y added per row, primal update of Eq. (3) and its "
+                      "reductions (k_primal_combine; k_primal in the plain layout does both passes)",
+    "dual_pass1": "K~ x' product, first pass (k_lds_rows<0>: XCD panels, hottest x' entries staged "
+                  "in LDS; k_panel_rows<0> without the stage)",
+    "dual_combine": "panel partials of K~ x' added per row, dual update of Eq. (3), the Eq. (5) "
+                    "reductions and the step-size tail (k_dual_combine + k_tail; k_dual in the plain "
+                    "layout does both passes)",
+}
+# kernel symbol of each pass per copy layout (1 panels, 2 slices, 3 panels with a stage)
+PASS_KERNELS = {
+    "primal_pass1": {1: "k_panel_rows<1>", 2: "k_lds_rows<1>", 3: "k_lds_rows<1>"},
+    "primal_combine": {0: "k_primal", 1: "k_primal_combine", 2: "k_primal_combine", 3: "k_primal_combine"},
+    "dual_pass1": {1: "k_panel_rows<0>", 2: "k_lds_rows<0>", 3: "k_lds_rows<0>"},
+    "dual_combine": {0: "k_dual", 1: "k_dual_combine", 2: "k_dual_combine", 3: "k_dual_combine"},
+}
 
 
 def kernel_sources_digest():
@@ -52,21 +86,34 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def profiled_traffic(steps, warmup):
-    """HBM bytes per step slot (primal, dual) that the rocprofv3 byte counters gave for this
-    very source tree and bench configuration, read from the committed profile summary; None
-    when the kernels or the configuration differ from the profiled ones."""
+def profiled_bytes():
+    """HBM bytes per product dispatch of each step kernel on the large plain LP, from the
+    rocprofv3 byte counters in the committed profile summary; None when the summary was taken
+    on other kernel sources."""
     try:
         with open(PROFILE) as fh:
             for line in fh:
                 if line.startswith("bench-traffic: "):
                     d = json.loads(line[len("bench-traffic: "):])
-                    if (d["sources_sha256"] == kernel_sources_digest() and d["steps"] == steps
-                            and d["warmup"] == warmup):
-                        return d["bytes_per_launch"]
+                    if d["sources_sha256"] == kernel_sources_digest():
+                        return d["bytes_per_dispatch"]
     except (OSError, ValueError, KeyError):
         pass
     return None
+
+
+def host_cpu():
+    """CPU model and the cores this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cores": len(os.sched_getaffinity(0))}
 
 
 def cpu_baseline(lp, budget_s=20.0):
@@ -97,24 +144,155 @@ def cpu_baseline(lp, budget_s=20.0):
             el = time.perf_counter() - t0
             if el >= budget_s or iters >= 50:
                 break
-    return dict(value=iters / el, unit="PDHG iters/s", cores=1, kind="oracle",
-                sample=f"{iters} accepted oracle PDHG steps (Eq. (3) + Algorithm 2, unpreconditioned, "
-                       f"scipy CSR products, 1 thread) on the same LP, {el:.1f} s")
+    out = dict(value=iters / el, unit="PDHG iters/s", cores=1, kind="oracle",
+               sample=f"{iters} accepted oracle PDHG steps (Eq. (3) + Algorithm 2, unpreconditioned, "
+                      f"scipy CSR products, 1 thread; the step-size limit forms K dx as a third "
+                      f"product) on the same LP, {el:.1f} s")
+    out.update(host_cpu())
+    return out
 
 
-def bench_batched(P, lpgen, count, iter_limit, plain_sample=16):
-    """LPs/s to KKT 1e-8 of the batched solver (one launch, one workgroup per LP) on the
-    batched workload, against a loop of single-LP solves on an evenly spaced sample."""
+def pass_bytes(lp):
+    """Algorithmic bytes of one launch of each pass when it forms its product (int64 row
+    offsets, int32 columns and float64 values of the CSR copy, the gathered vector once, each
+    other vector once): the first passes move the matrix and the gathered vector, the combines
+    the vectors of the update (primal: read x, c, l, u, S_x, write x', S_x, K~^T y; dual: read
+    y, q, K~x, S_y, write y', K~x', S_y)."""
+    m, n, nnz = lp.m, lp.n, lp.nnz
+    return {"primal_pass1": 12.0 * nnz + 8.0 * (n + 1) + 8.0 * m, "primal_combine": 64.0 * n,
+            "dual_pass1": 12.0 * nnz + 8.0 * (m + 1) + 8.0 * n, "dual_combine": 56.0 * m}
+
+
+def measure_lp(P, torch, lp, W, K, tol=1e-8, label="lp"):
+    """The three timed windows of the module docstring on one LP.  Returns a dict."""
+    t = time.time()
+    s = P.Solver.from_lp(lp)
+    inf = s.info()
+    log(f"{label}: created solver in {time.time() - t:.1f}s (library create {inf['create_seconds']:.1f}s); "
+        f"layouts K~ {inf['layout_K']} ({inf['panels_K']} panels), K~^T {inf['layout_KT']} ({inf['panels_KT']} panels)")
+    s.solve(tol, W)
+    # 1. headline window: exactly K steps as a solve runs them
+    i0 = s.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = s.solve(tol, i0["iterations"] + K)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    i1 = s.info()
+    steps = i1["iterations"] - i0["iterations"]
+    log(f"{label}: headline {steps} steps in {dt:.4f}s = {steps / dt:.1f} iters/s "
+        f"(status {P.STATUS_NAMES[st]}, checks {i1['checks'] - i0['checks']})")
+    # 2. kernel timing over the next K steps
+    s.set_kernel_timing(True)
+    s.reset_kernel_times()
+    j0 = s.info()
+    s.solve(tol, j0["iterations"] + K)
+    j1 = s.info()
+    s.set_kernel_timing(False)
+    tms, cnt = s.pass_times()
+    d_att = j1["attempts"] - j0["attempts"]
+    d_chk = j1["checks"] - j0["checks"]
+    # products formed by the timed slots: a check forms two K~^T products (of the average and
+    # of the current y) and one K~ product; the primal step skips its product when y has not
+    # changed since it was formed (after a rejected attempt, and after a check)
+    prim_products = (j1["spmv_KT"] - j0["spmv_KT"]) - 2 * d_chk
+    dual_products = (j1["spmv_K"] - j0["spmv_K"]) - d_chk
+    pb = pass_bytes(lp)
+    plain_T, plain_K = inf["layout_KT"] == 0, inf["layout_K"] == 0
+    alg = {"primal_pass1": 0.0 if plain_T else prim_products * pb["primal_pass1"],
+           "primal_combine": cnt[1] * pb["primal_combine"] + (prim_products * pb["primal_pass1"] if plain_T else 0.0),
+           "dual_pass1": 0.0 if plain_K else dual_products * pb["dual_pass1"],
+           "dual_combine": cnt[3] * pb["dual_combine"] + (dual_products * pb["dual_pass1"] if plain_K else 0.0)}
+    passes = {}
+    for j, name in enumerate(PASS_NAMES):
+        launches = int(cnt[j])
+        ms = float(tms[j]) / max(launches, 1)
+        bpl = alg[name] / max(launches, 1)
+        passes[name] = {"avg_us": 1e3 * ms, "launches": launches, "algorithmic_bytes_per_launch": bpl,
+                        "achieved_gbs": bpl / (ms * 1e-3) / 1e9 if ms > 0 else None}
+    slots = {}
+    for slot, (a, b) in (("primal", ("primal_pass1", "primal_combine")), ("dual", ("dual_pass1", "dual_combine"))):
+        ms = (tms[PASS_NAMES.index(a)] + tms[PASS_NAMES.index(b)]) / max(int(cnt[0]), 1)
+        by = (alg[a] + alg[b]) / max(int(cnt[0]), 1)
+        slots[slot] = {"avg_us": 1e3 * ms, "algorithmic_bytes_per_launch": by,
+                       "achieved_gbs": by / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                       "frac": (by / (ms * 1e-3) / 1e9) / HBM_PEAK_GBS if ms > 0 else None}
+    dom = max(PASS_NAMES, key=lambda nm: tms[PASS_NAMES.index(nm)])
+    lay = inf["layout_KT"] if dom.startswith("primal") else inf["layout_K"]
+    roof = {"bound": "hbm", "kernel": PASS_KERNELS[dom].get(lay, "?") + ": " + PASS_DOC[dom],
+            "achieved": passes[dom]["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (passes[dom]["achieved_gbs"] or 0.0) / HBM_PEAK_GBS, "traffic": None,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
+            "avg_launch_ms": passes[dom]["avg_us"] * 1e-3, "launches": passes[dom]["launches"],
+            "algorithmic_bytes_per_launch": passes[dom]["algorithmic_bytes_per_launch"],
+            "pass": dom, "timing": f"HIP events on the solver's stream around each pass of the {d_att} attempt "
+                                   f"slots that ran in the {K} steps after the headline window"}
+    log(f"{label}: passes " + ", ".join(f"{k} {v['avg_us']:.1f}us" for k, v in passes.items())
+        + f"; dominant {dom} at {roof['frac'] * 100:.1f}% of HBM peak")
+    # 3. whole check blocks
+    k = s.info()["iterations"]
+    start = -(-k // CHECK_EVERY) * CHECK_EVERY
+    s.solve(tol, start)
+    nb = max(5, -(-K // CHECK_EVERY))
+    c0 = s.info()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.solve(tol, c0["iterations"] + nb * CHECK_EVERY)
+    torch.cuda.synchronize()
+    cdt = time.perf_counter() - t0
+    c1 = s.info()
+    csteps = c1["iterations"] - c0["iterations"]
+    check_incl = {"iters_per_s": csteps / cdt, "steps": csteps, "checks": c1["checks"] - c0["checks"],
+                  "seconds": cdt, "first_step": c0["iterations"] + 1}
+    log(f"{label}: {csteps} steps with {check_incl['checks']} checks in {cdt:.4f}s = {csteps / cdt:.1f} iters/s")
+    kkt = c1["kkt"][3]
+    s.close()
+    return {"steps_taken": steps, "seconds": dt, "iters_per_s": steps / dt, "roofline": roof,
+            "passes": passes, "slots": slots, "check_inclusive": check_incl,
+            "step_gbs_algorithmic": inf["step_bytes"] * steps / dt / 1e9, "kkt_at_end": kkt,
+            "attempts_per_step_timed": d_att / max(j1["iterations"] - j0["iterations"], 1),
+            "create_seconds": inf["create_seconds"],
+            "layouts": {"K": inf["layout_K"], "KT": inf["layout_KT"]}}
+
+
+def attach_traffic(r, lp):
+    """roofline.traffic of the dominant pass: the HBM bytes per product dispatch of its kernel
+    in the committed profile, scaled to the timed launches (a first pass after a rejected
+    attempt returns at once: it moves no matrix); null when the profile was taken on other
+    kernel sources or does not cover the kernel."""
+    prof = profiled_bytes()
+    roof = r["roofline"]
+    kern = roof["kernel"].split(":")[0]
+    if not prof or kern not in prof:
+        return
+    name = roof["pass"]
+    full = pass_bytes(lp)[name]
+    per_launch = r["passes"][name]["algorithmic_bytes_per_launch"]
+    frac = per_launch / full if name.endswith("pass1") else 1.0
+    roof["traffic"] = prof[kern] * frac
+    roof["traffic_over_algorithmic"] = roof["traffic"] / per_launch if per_launch else None
+
+
+def bench_batched(P, lpgen, count, iter_limit, sample=32, oracle_budget_s=20.0, tune_steps=200):
+    """LPs/s to KKT 1e-8 of the batched solver (one persistent launch per size class, one
+    workgroup per LP, the workgroup size of each class picked by pdlp_batch_tune) on the
+    batched workload; a loop of single-LP solves and the oracle on stratified samples of the
+    same members, extrapolated to the whole workload."""
     import numpy as np
     t = time.time()
     lps = [lpgen.batched_instance(i) for i in range(count)]
     log(f"generated {count} batched members in {time.time() - t:.1f}s")
     b = P.Batch(lps)
+    default_sizes, members = b.schedule()
+    sizes = b.tune(tune_steps)
+    log(f"batched: tuned workgroup sizes {sizes} for classes of {members} members in {b.tune_seconds():.2f}s")
     secs = b.solve(1e-8, iter_limit)
     _, _, st, it, kkt = b.get()
     b.close()
     conv = int((st == P.OPTIMAL).sum())
-    idx = list(range(0, count, max(1, count // plain_sample)))[:plain_sample]
+    # stratified sample: evenly spaced in the order of m
+    order = np.argsort([lp.m for lp in lps], kind="stable")
+    idx = [int(order[int(i)]) for i in np.linspace(0, count - 1, sample)]
     t0 = time.perf_counter()
     pconv = 0
     for i in idx:
@@ -122,13 +300,63 @@ def bench_batched(P, lpgen, count, iter_limit, plain_sample=16):
         pconv += s.solve(1e-8, iter_limit) == P.OPTIMAL
         s.close()
     pdt = time.perf_counter() - t0
-    log(f"batched: {conv}/{count} at KKT 1e-8 in {secs:.2f}s; plain loop {pconv}/{len(idx)} in {pdt:.2f}s")
-    return {"workload": f"{count} LPs, m log-uniform in [50,2000], n = U[2,3] m, 3-8 nonzeros per "
-                        f"column, seeds 3000+i", "tol": 1e-8, "iter_limit": iter_limit,
-            "seconds": secs, "converged": conv, "count": count, "lps_per_s": conv / secs,
-            "median_iterations": float(np.median(it)), "max_kkt_converged": float(kkt[st == 0, 3].max()) if conv else None,
-            "plain_loop_lps_per_s": pconv / pdt, "plain_sample": len(idx), "plain_converged": pconv,
-            "speedup_vs_plain": (conv / secs) / (pconv / pdt) if pconv else None}
+    plain_est = pdt / len(idx) * count
+    log(f"batched: {conv}/{count} at KKT 1e-8 in {secs:.2f}s; plain loop on {len(idx)} members "
+        f"{pdt:.2f}s ({pconv} converged), {plain_est:.0f}s estimated for all {count}")
+    out = {"workload": f"{count} LPs, m log-uniform in [50,2000], n = U[2,3] m, 3-8 nonzeros per "
+                       f"column, seeds 3000+i", "tol": 1e-8, "iter_limit": iter_limit,
+           "schedule": {"class_nonzeros": ["<2^11", "2^11..2^13", "2^13..2^15", ">=2^15"],
+                        "members": members, "workgroup_sizes": sizes, "untuned_sizes": default_sizes,
+                        "tune_steps": tune_steps, "tune_seconds": b.tune_seconds()},
+           "seconds": secs, "count": count, "converged": conv, "not_converged": count - conv,
+           "lps_per_s": count / secs if conv == count else None,
+           "converged_per_s": conv / secs,
+           "median_iterations": float(np.median(it)), "max_iterations": int(it.max()),
+           "max_kkt_converged": float(kkt[st == 0, 3].max()) if conv else None,
+           "plain_loop": {"sample": len(idx), "seconds": pdt, "converged": pconv,
+                          "seconds_per_lp": pdt / len(idx), "estimated_seconds_all": plain_est},
+           "speedup_vs_plain_loop_estimate": plain_est / secs}
+    out["oracle"] = batched_oracle(lps, idx, oracle_budget_s, count)
+    return out
+
+
+def _oracle_member(lp):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import pdlp_oracle as O
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        r = O.solve_lp(lp, tol=1e-8, iter_limit=20000)
+        return time.perf_counter() - t0, int(r.status == O.OPTIMAL), int(r.k)
+
+
+def batched_oracle(lps, idx, budget_s, count):
+    """The oracle on members of the stratified sample: one thread (members in turn, within
+    the budget) and a process pool over all host cores (one member per process)."""
+    import multiprocessing as mp
+    cpu = host_cpu()
+    one = []
+    t0 = time.perf_counter()
+    for i in idx[::-1]:                                  # small members last
+        if time.perf_counter() - t0 > budget_s and one:
+            break
+        one.append(_oracle_member(lps[i]))
+    secs1 = sum(a for a, _, _ in one)
+    cores = cpu["host_cores"]
+    sub = [lps[i] for i in idx[: max(cores, 1) * 2]]
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_member, sub, chunksize=1)
+    secsN = time.perf_counter() - t0
+    out = {"one_thread": {"members": len(one), "seconds": secs1, "converged": sum(c for _, c, _ in one),
+                          "lps_per_s": len(one) / secs1 if secs1 > 0 else None},
+           "all_cores": {"members": len(sub), "seconds": secsN, "processes": cores,
+                         "converged": sum(c for _, c, _ in res), "lps_per_s": len(sub) / secsN},
+           "note": "members from the stratified sample (largest first for one thread, smallest first "
+                   "on all cores); iteration limit 20000", **cpu}
+    log(f"batched oracle: 1 thread {len(one)} members in {secs1:.1f}s; {cores} processes {len(sub)} "
+        f"members in {secsN:.1f}s")
+    return out
 
 
 def bench_step_policies(P, torch, lp, W=100, K=400):
@@ -165,6 +393,7 @@ ABLATIONS = {
     "fixed_weight": dict(primal_weight_update=0),
     "no_scaling": dict(ruiz_iters=0, pock_chambolle=0),
     "ruiz_only": dict(pock_chambolle=0),
+    "pock_chambolle_only": dict(ruiz_iters=0),
     "malitsky_pock": dict(step_policy=2),
 }
 
@@ -233,66 +462,6 @@ def bench_unroll(P, lpgen, T=500, segment=50, reps=5):
             "oracle_adjoint_ms": 1e3 * (t2 - t1), "oracle_cores": 1}
 
 
-def measure_steps(P, torch, lp, W, K):
-    """Warm up W accepted steps, then time K more of Algorithm 1 (HIP events around every step
-    kernel) and account the algorithmic bytes of the timed step kernels.  Returns (dict, solver)."""
-    t = time.time()
-    s = P.Solver.from_lp(lp, time_kernels=1)
-    info = s.info()
-    log(f"created solver in {time.time() - t:.1f}s (library create {info['create_seconds']:.1f}s)")
-    st = s.solve(1e-8, W)
-    log(f"warmup {W} steps: status {P.STATUS_NAMES[st]}")
-    s.reset_kernel_times()
-    i0 = s.info()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = s.solve(1e-8, W + K)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    info = s.info()
-    steps = info["iterations"] - i0["iterations"]
-    dt = t1 - t0
-    log(f"timed {steps} steps in {dt:.3f}s: status {P.STATUS_NAMES[st]}, attempts {info['attempts']}, "
-        f"restarts {info['restarts']}, kkt {info['kkt'][3]:.3e}")
-    # Algorithmic bytes of the timed step kernels.  The primal step skips its K~^T y product
-    # when y is unchanged since that product was last formed (after a rejected attempt, and
-    # after a check, which forms it), and a slot whose attempt does not run (a check pending)
-    # does nothing; so count the products from the solver's counters: each check forms two
-    # K~^T products (of the average and of the current y) and one K~ product.
-    times, counts = s.kernel_times()
-    m, n, nnz = lp.m, lp.n, lp.nnz
-    d_att = info["attempts"] - i0["attempts"]
-    d_chk = info["checks"] - i0["checks"]
-    prim_products = (info["spmv_KT"] - i0["spmv_KT"]) - 2 * d_chk
-    dual_products = (info["spmv_K"] - i0["spmv_K"]) - d_chk
-    bytes_primal = 8.0 * (n + 1) + 12.0 * nnz + 8.0 * m + 64.0 * n     # K~^T y, then 8 n-vectors
-    bytes_primal_epi = 64.0 * n                                         # the same without the product
-    bytes_dual = 8.0 * (m + 1) + 12.0 * nnz + 8.0 * n + 56.0 * m        # K~ x', then 7 m-vectors
-    total_bytes = [prim_products * bytes_primal + (d_att - prim_products) * bytes_primal_epi,
-                   dual_products * bytes_dual]
-    dom = 0 if times[0] >= times[1] else 1
-    name = ["primal step: K~^T y product fused with the primal update (first pass k_lds_rows<1> with "
-            "the operand staged in LDS, else k_panel_rows<1>, then k_primal_combine; k_primal in the "
-            "plain layout)",
-            "dual step: K~ x' product fused with the dual update and the step rule (first pass "
-            "k_lds_rows<0> with the operand staged in LDS, else k_panel_rows<0>, then k_dual_combine; "
-            "k_dual in the plain layout)"][dom]
-    avg_ms = times[dom] / counts[dom]
-    bpl = total_bytes[dom] / counts[dom]
-    achieved = bpl / (avg_ms * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": name, "achieved": achieved, "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled)",
-            "avg_launch_ms": avg_ms, "launches": int(counts[dom]),
-            "products": int([prim_products, dual_products][dom]), "attempts": int(d_att),
-            "algorithmic_bytes_per_launch": bpl, "slot": ["primal", "dual"][dom]}
-    return ({"steps_taken": steps, "seconds": dt, "roofline": roof,
-             "step_gbs_algorithmic": info["step_bytes"] * steps / dt / 1e9,
-             "step_avg_ms": {"primal": times[0] / counts[0], "dual": times[1] / counts[1]},
-             "algorithmic_bytes_per_slot": {"primal": total_bytes[0] / counts[0],
-                                            "dual": total_bytes[1] / counts[1]}}, s)
-
-
 def measure_copy_gbs(torch, nbytes=2 << 30, reps=10):
     """Device-to-device copy bandwidth (bytes read + written per second) on this GPU."""
     a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
@@ -325,6 +494,103 @@ def calibrate_copy(nbytes=1 << 30):
                       "launches": 3}), flush=True)
 
 
+# ---------------------------------------------------------------------------------------------
+# rocprofv3 summaries (text for profiles/)
+# ---------------------------------------------------------------------------------------------
+
+def _short_kernel(name):
+    """'void pdlp::k_lds_rows<1>(pdlp::CsrDev, ...)' -> 'k_lds_rows<1>'."""
+    import re
+    n = name.strip().strip('"')
+    n = re.sub(r"^void\s+", "", n)
+    n = n.split("(")[0]
+    n = re.sub(r"pdlp::(\(anonymous namespace\)::)?", "", n)
+    n = re.sub(r"<(\d+), (\d+)>", r"<\1, \2>", n)
+    return n
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profile(d):
+    """Summary of the rocprofv3 runs under d: d/trace (kernel trace + stats), d/fetch and
+    d/write (FETCH_SIZE / WRITE_SIZE of the bench run), d/copy_fetch and d/copy_write (the same
+    counters on the calibration copy).  Prints text; its last line is machine-readable."""
+    import numpy as np
+
+    def find(sub, suffix):
+        hits = sorted(glob.glob(os.path.join(d, sub, "**", f"*{suffix}"), recursive=True))
+        return hits[0] if hits else None
+
+    print("rocprofv3 profile: PDLP step passes on the large plain LP (m=1e6, n=2e6, nnz=1.354e8), one MI355X")
+    print(f"step-kernel sources sha256 {kernel_sources_digest()} (bench.STEP_SOURCES under paper_2106_04756_amd/csrc)")
+    print()
+    trace = find("trace", "kernel_trace.csv")
+    if trace:
+        rows = _read_csv(trace)
+        per = {}
+        for r in rows:
+            k = _short_kernel(r["Kernel_Name"])
+            per.setdefault(k, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3)
+        print("1. Kernel trace of the run (durations in us; 'ran' = dispatches longer than 20% of the kernel's")
+        print("   longest, i.e. those that formed a product or ran their update rather than returning at once)")
+        print(f"{'kernel':34s} {'calls':>7s} {'avg_us':>9s} {'ran':>7s} {'ran_avg_us':>11s} {'total_ms':>9s}")
+        tot = sum(sum(v) for v in per.values())
+        for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:18]:
+            a = np.array(v)
+            ran = a[a > 0.2 * a.max()]
+            print(f"{k:34s} {a.size:7d} {a.mean():9.1f} {ran.size:7d} {ran.mean():11.1f} {a.sum() * 1e-3:9.2f}")
+        print(f"   all kernels: {tot * 1e-3:.1f} ms")
+        print()
+    cal = {}
+    for cnt in ("FETCH_SIZE", "WRITE_SIZE"):
+        f = find(f"copy_{cnt.split('_')[0].lower()}", "counter_collection.csv")
+        if f:
+            vals = [float(r["Counter_Value"]) for r in _read_csv(f)
+                    if r["Counter_Name"].startswith(cnt) and "copy" in r["Kernel_Name"].lower()]
+            if vals:
+                cal[cnt] = float(np.median(vals))
+    nbytes = 1 << 30
+    scale = {c: (nbytes / (cal[c] * 1024.0) if cal.get(c) else None) for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    print("2. Counter calibration: a 1 GiB device copy (1 GiB read, 1 GiB written) gives "
+          + ", ".join(f"{c} {cal.get(c, float('nan')):.0f} KiB" for c in ("FETCH_SIZE", "WRITE_SIZE"))
+          + " per dispatch,")
+    print("   so HBM bytes = " + " + ".join(f"{c} x {scale[c]:.3f} KiB" for c in scale if scale[c]))
+    print()
+    byk = {}
+    for cnt, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        f = find(sub, "counter_collection.csv")
+        if not f or not scale[cnt]:
+            continue
+        for r in _read_csv(f):
+            if not r["Counter_Name"].startswith(cnt):
+                continue
+            k = _short_kernel(r["Kernel_Name"])
+            byk.setdefault(k, {}).setdefault(cnt, []).append(float(r["Counter_Value"]) * 1024.0 * scale[cnt])
+    print("3. HBM bytes per dispatch that formed its product (dispatches above 20% of the kernel's largest")
+    print("   fetch; the median of those), scaled by the calibration:")
+    print(f"{'kernel':34s} {'dispatches':>10s} {'fetch_MB':>9s} {'write_MB':>9s} {'total_MB':>9s}")
+    per_dispatch = {}
+    for k in sorted(byk):
+        fe = np.array(byk[k].get("FETCH_SIZE", [0.0]))
+        wr = np.array(byk[k].get("WRITE_SIZE", [0.0]))
+        if fe.max() <= 0:
+            continue
+        sel = fe > 0.2 * fe.max()
+        fmed = float(np.median(fe[sel]))
+        wmed = float(np.median(wr[: fe.size][sel[: wr.size]])) if wr.size == fe.size else float(np.median(wr))
+        per_dispatch[k] = fmed + wmed
+        if fmed + wmed > 1e6:
+            print(f"{k:34s} {int(sel.sum()):10d} {fmed / 1e6:9.1f} {wmed / 1e6:9.1f} {(fmed + wmed) / 1e6:9.1f}")
+    print()
+    print("bench-traffic: " + json.dumps({"sources_sha256": kernel_sources_digest(),
+                                         "bytes_per_dispatch": {k: round(v) for k, v in per_dispatch.items()
+                                                                if v > 1e6}}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,12 +602,18 @@ def main():
     ap.add_argument("--no-unroll", action="store_true")
     ap.add_argument("--no-truncated", action="store_true",
                     help="skip the large LP with column counts truncated to [1,190]")
+    ap.add_argument("--no-pagerank", action="store_true", help="skip the PageRank LP on 5e6 nodes")
     ap.add_argument("--no-policies", action="store_true", help="skip the other step policies")
     ap.add_argument("--no-ablations", action="store_true", help="skip the ablation switches")
+    ap.add_argument("--only-large", action="store_true", help="only the large plain LP (profiling runs)")
     ap.add_argument("--batch-count", type=int, default=4096)
-    ap.add_argument("--batch-iter-limit", type=int, default=20000)
+    ap.add_argument("--batch-iter-limit", type=int, default=100000)
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--summarize-profile", metavar="DIR")
     args = ap.parse_args()
+    if args.summarize_profile:
+        summarize_profile(args.summarize_profile)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU layout is described in the design notes, not built).", file=sys.stderr)
@@ -349,6 +621,9 @@ def main():
     if args.calibrate_copy:
         calibrate_copy()
         return
+    if args.only_large:
+        args.no_truncated = args.no_pagerank = args.no_policies = args.no_ablations = True
+        args.no_batched = args.no_unroll = args.no_cpu_baseline = True
 
     import torch
 
@@ -360,23 +635,21 @@ def main():
     lp = lpgen.large_lp(args.seed)
     log(f"generated {lp.name}: m={lp.m} n={lp.n} nnz={lp.nnz} in {time.time() - t:.1f}s")
     W, K = args.warmup, args.steps
-    r, s = measure_steps(P, torch, lp, W, K)
-    steps, dt = r["steps_taken"], r["seconds"]
-    m, n, nnz = lp.m, lp.n, lp.nnz
-    traffic = profiled_traffic(K, W)
-    roof = r["roofline"]
-    roof["traffic"] = (traffic or {}).get(roof.pop("slot"))
+    r = measure_lp(P, torch, lp, W, K, label="large LP")
+    attach_traffic(r, lp)
     copy_gbs = measure_copy_gbs(torch)
+    roof = r["roofline"]
     roof["measured_copy_gbs"] = copy_gbs
-    roof["frac_of_measured_copy"] = roof["achieved"] / copy_gbs
+    roof["frac_of_measured_copy"] = (roof["achieved"] or 0.0) / copy_gbs
+    m, n, nnz = lp.m, lp.n, lp.nnz
     out = {
         "metric": "PDHG iters/s",
-        "value": steps / dt,
+        "value": r["iters_per_s"],
         "unit": "iters/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": dt / max(steps, 1) * 1e3,
+        "ms_per_step": r["seconds"] / max(r["steps_taken"], 1) * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -384,27 +657,30 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"large plain LP m={m} n={n} nnz={nnz} (Zipf(1.5) column counts, "
                                f"30% equality rows, mixed bounds), seed {args.seed}",
-                   "tol": 1e-8, "steps_taken": steps},
+                   "tol": 1e-8, "steps_taken": r["steps_taken"],
+                   "timed": "exactly K steps of pdlp_solve after W warmup steps (captured HIP graphs per "
+                            "block of 40 attempt slots; checks fall where k is a multiple of 40)"},
         "roofline": roof,
+        "check_inclusive": r["check_inclusive"],
+        "passes": r["passes"],
+        "slots": r["slots"],
         "step_gbs_algorithmic": r["step_gbs_algorithmic"],
-        "step_avg_ms": r["step_avg_ms"],
-        "algorithmic_bytes_per_slot": r["algorithmic_bytes_per_slot"],
+        "create_seconds": r["create_seconds"],
     }
-    s.close()
     if not args.no_truncated:
-        # the same shape with column counts truncated to [1, 190] (nnz ~2.1e7)
         lpb = lpgen.large_lp_truncated(args.seed)
         log(f"generated {lpb.name}: nnz={lpb.nnz}")
-        rb, sb = measure_steps(P, torch, lpb, W, K)
-        sb.close()
-        rb["roofline"].pop("slot")
+        rb = measure_lp(P, torch, lpb, W, K, label="truncated LP")
         out["large_lp_truncated"] = {
             "workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
-                        f"counts truncated to [1,190]), seed {args.seed}",
-            "iters_per_s": rb["steps_taken"] / rb["seconds"], "steps": rb["steps_taken"],
-            "roofline": rb["roofline"], "step_gbs_algorithmic": rb["step_gbs_algorithmic"]}
-        log(f"large_lp_truncated: {out['large_lp_truncated']['iters_per_s']:.1f} iters/s, "
-            f"{rb['roofline']['frac'] * 100:.1f}% of HBM peak")
+                        f"counts truncated to [1,190]), seed {args.seed}", **rb}
+    if not args.no_pagerank:
+        t = time.time()
+        lpr = lpgen.pagerank_5m()
+        log(f"generated {lpr.name}: nnz={lpr.nnz} in {time.time() - t:.1f}s")
+        rp = measure_lp(P, torch, lpr, W, K, label="PageRank LP")
+        out["pagerank_5m"] = {"workload": f"{lpr.name}, m={lpr.m} n={lpr.n} nnz={lpr.nnz}", **rp}
+        del lpr
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
     tiny = lpgen.tiny_lp()
     st0 = P.Solver.from_lp(tiny)
@@ -432,7 +708,6 @@ def main():
         out["unroll"] = bench_unroll(P, lpgen)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host")
-        s.close()
         out["cpu_baseline"] = cpu_baseline(lp)
     print(json.dumps(out), flush=True)
 

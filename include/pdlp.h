@@ -246,8 +246,32 @@ int pdlp_batch_create(pdlp_batch **out, int64_t count, const int64_t *m, const i
                       void *hip_stream);
 
 /* pdlp_batch_solve - solve every member to relative KKT error tol or iter_limit accepted
- * steps (each member separately).  One call per batch; PDLP_ERR_INVALID_STATE on a second. */
+ * steps (each member separately).  Every call starts from the members' data as created (a
+ * later call repeats the solve, with its own tol and iter_limit).
+ * The members fall into PDLP_BATCH_CLASSES size classes by nonzeros ([0, 2^11), [2^11, 2^13),
+ * [2^13, 2^15), [2^15, ...)); each class runs as one persistent launch, members largest first,
+ * with the workgroup size (threads per member: 64, 128, 256, 512 or 1024) set for that class
+ * (256 until pdlp_batch_tune or pdlp_batch_set_block_sizes), the classes concurrently. */
+#define PDLP_BATCH_CLASSES 4
 int pdlp_batch_solve(pdlp_batch *b, double tol, int64_t iter_limit);
+
+/* pdlp_batch_tune - pick each class's workgroup size: every candidate size runs the class's
+ * members for `steps` accepted steps (tol 0, so none stops early; the run is timed with HIP
+ * events after one untimed run) and the fastest is kept.  block_size (may be NULL) receives
+ * the PDLP_BATCH_CLASSES choices.  The timing runs leave no solve behind (pdlp_batch_get needs
+ * a pdlp_batch_solve after it).  Errors: PDLP_ERR_INVALID_ARGUMENT for steps < 1. */
+int pdlp_batch_tune(pdlp_batch *b, int64_t steps, int32_t *block_size);
+
+/* pdlp_batch_set_block_sizes - set the PDLP_BATCH_CLASSES workgroup sizes (each 64, 128, 256,
+ * 512 or 1024; else PDLP_ERR_INVALID_ARGUMENT). */
+int pdlp_batch_set_block_sizes(pdlp_batch *b, const int32_t *block_size);
+
+/* pdlp_batch_schedule - the current workgroup size and the member count of each class
+ * (PDLP_BATCH_CLASSES values each; either pointer may be NULL). */
+int pdlp_batch_schedule(const pdlp_batch *b, int32_t *block_size, int64_t *members);
+
+/* pdlp_batch_tune_seconds - host wall time of the last pdlp_batch_tune. */
+double pdlp_batch_tune_seconds(const pdlp_batch *b);
 
 /* pdlp_batch_get - returned points, unscaled and concatenated like the inputs (x: sum of n,
  * y: sum of m), and per member the pdlp_status, accepted steps and kkt[4] (4 * count values).
@@ -451,7 +475,9 @@ typedef struct pdlp_panel_layout {
  * the nrows x ncols CSR matrix (row_ptr, col_idx, val): npanel panels cut at `cuts` (npanel
  * + 1 column offsets) or, if cuts is NULL, at about equal nonzero counts; wavefront tasks of
  * at most emax entries per lane (8, or 16 as in the layouts of the LDS-staged products); its
- * interleaved entries; and the split of its wavefront tasks among `groups` LDS workgroups
+ * interleaved entries (with emax 16, the layouts of the LDS-staged kernel, a row's run of 513 to
+ * 16384 entries inside one panel is cut into consecutive panel rows of at most 512 entries);
+ * and the split of its wavefront tasks among `groups` LDS workgroups
  * (aligned: group b stays on panel b mod npanel, which needs groups to be a multiple of
  * npanel).  Returns 0, or -1 on invalid arguments (including a matrix that is not CSR with
  * in-range, increasing columns per row, or cuts that are not non-decreasing from 0 to ncols)

@@ -130,30 +130,54 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
   L.P = P;
   L.cut = given_cuts ? *given_cuts : panel_cuts(ci, nnz, ncols, P);
   const std::vector<int32_t>& cut = L.cut;
-  // Row segments: the nonempty panel rows of row r are segments sp[r] .. sp[r + 1], in panel
-  // order, with their panel and length (a sparse form of the rows x panels length table).
+  // Layouts for the LDS-staged kernel (emax = kElemsPerLaneLds) hold wavefront tasks: a row's
+  // run inside a panel of kWaveMaxLen + 1 .. kVectorMax entries is cut into pieces of
+  // kWaveMaxLen entries (the last one shorter), each a panel row of its own, added in order by
+  // the combine.  Longer runs stay whole (a workgroup task): the combine adds a row's panel
+  // rows one thread at a time, and thousands of pieces would serialize it.
+  const bool cut_runs = emax == kElemsPerLaneLds;
+  auto pieces = [&](int64_t len) -> int64_t {
+    return (cut_runs && len > kWaveMaxLen && len <= kVectorMax) ? (len + kWaveMaxLen - 1) / kWaveMaxLen : 1;
+  };
+  // Row segments: the panel rows of row r are segments sp[r] .. sp[r + 1], in panel order,
+  // with their panel and length (a sparse form of the rows x panels length table).
   std::vector<int64_t> sp(size_t(nrows) + 1, 0);
   for (int64_t r = 0; r < nrows; ++r) {
-    int64_t cntr = 0;
+    int64_t cntr = 0, run = 0;
     int p = -1;
     for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
       int q = p < 0 ? 0 : p;
       while (ci[e] >= cut[size_t(q) + 1]) ++q;
-      if (q != p) { ++cntr; p = q; }
+      if (q != p) {
+        if (p >= 0) cntr += pieces(run);
+        p = q;
+        run = 0;
+      }
+      ++run;
     }
+    if (p >= 0) cntr += pieces(run);
     sp[size_t(r) + 1] = sp[size_t(r)] + cntr;
   }
   const int64_t nprow = sp[size_t(nrows)];
   if (double(nprow) > max_prow_frac * double(std::max<int64_t>(nnz, 1))) return false;
   std::vector<int32_t> seg_p(static_cast<size_t>(nprow)), seg_len(static_cast<size_t>(nprow));
   for (int64_t r = 0; r < nrows; ++r) {
-    int64_t k = sp[size_t(r)] - 1;
-    int p = -1;
-    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
-      int q = p < 0 ? 0 : p;
+    int64_t k = sp[size_t(r)];
+    int64_t e = rp[r];
+    int q = 0;
+    while (e < rp[r + 1]) {
+      // the run of panel q starting at e, then its pieces
       while (ci[e] >= cut[size_t(q) + 1]) ++q;
-      if (q != p) { ++k; p = q; seg_p[size_t(k)] = q; seg_len[size_t(k)] = 0; }
-      seg_len[size_t(k)]++;
+      int64_t e1 = e + 1;
+      while (e1 < rp[r + 1] && ci[e1] < cut[size_t(q) + 1]) ++e1;
+      const int64_t np = pieces(e1 - e);
+      for (int64_t i = 0; i < np; ++i) {
+        const int64_t a = e + i * kWaveMaxLen;
+        seg_p[size_t(k)] = q;
+        seg_len[size_t(k)] = int32_t(np > 1 ? std::min<int64_t>(kWaveMaxLen, e1 - a) : e1 - e);
+        ++k;
+      }
+      e = e1;
     }
   }
   // segments of each panel in row order (counting sort by panel)

@@ -9,6 +9,11 @@
 // same element functions.  Products: one thread per row of K~ or K~^T (the member LPs have
 // short rows), summing in index order.  No atomics; every sum has a fixed order.
 //
+// The workgroup size BS (64 .. 1024 threads) is a template parameter: the host launches one
+// kernel per size class of the members, with the size its tuner picked for that class.  A
+// launch starts from the members' original matrix values (copied into the work arrays it
+// scales), so solving again, or timing a candidate size, repeats the same computation.
+//
 // Included into the solver's translation unit after pdlp_kernels.hip.
 
 namespace pdlp {
@@ -27,10 +32,12 @@ struct BatchDev {
   const int32_t* order;  // member run by workgroup b (largest members first)
   const int64_t* rp;
   const int32_t* ci;
-  double* v;
+  double* v;             // work copies of the values, preconditioned in place by each launch
+  const double* v0;      // the members' original values
   const int64_t* rpT;
   const int32_t* ciT;
   double* vT;
+  const double* vT0;
   double *c, *l, *u, *c0, *l0, *u0, *D2, *X0, *X1, *KTy, *Sx, *XB, *KTYB, *XA;
   double *q, *q0, *D1, *Y0, *Y1, *KX0, *KX1, *Sy, *YB, *KXB, *YA;
   double *GA0, *GA1, *GB0, *GB1;
@@ -88,12 +95,12 @@ struct LocalCsr {
   int32_t nrows;
 };
 
-// Row r of A times x, summed in index order.  The nonzeros are taken 8 at a time with the
+// Row r of A times x, summed in index order.  The nonzeros are taken C at a time with the
 // index clamped into the row and the extra products masked to +0.0, so the loads of a chunk
 // (and then its gathers) are all in flight together; the sum is bit-identical to the plain
-// left-to-right loop.
+// left-to-right loop for any C.
+template <int C>
 __device__ __forceinline__ double local_row_dot(const LocalCsr& A, int r, const double* __restrict__ x) {
-  constexpr int C = 8;
   double s = 0.0;
   const int64_t p0 = A.rp[r], p1 = A.rp[r + 1];
   for (int64_t base = p0; base < p1; base += C) {
@@ -113,13 +120,64 @@ __device__ __forceinline__ double local_row_dot(const LocalCsr& A, int r, const 
   return s;
 }
 
-#define PDLP_BLOCK_LOOP(idx, total) for (int64_t idx = threadIdx.x; idx < (total); idx += kBlock)
+#define PDLP_BLOCK_LOOP(idx, total) for (int64_t idx = threadIdx.x; idx < (total); idx += BS)
 
-// out = A x, one thread per row.
-__device__ void local_spmv(const LocalCsr& A, const double* x, double* out) {
-  PDLP_BLOCK_LOOP(r, A.nrows) out[r] = local_row_dot(A, int(r), x);
+// Sum over a workgroup of BS threads of N values per thread, valid in thread 0: wave sums,
+// then the waves' sums added in wave order (for BS = 256 the order of block_sum).
+template <int N, int BS>
+__device__ void bsum(double (&a)[N]) {
+  constexpr int NW = BS / 64;
+  __shared__ double lds[NW * N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) a[k] = wave_sum(a[k]);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) lds[w * N + k] = a[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double t = lds[k];
+      for (int q = 1; q < NW; ++q) t = t + lds[q * N + k];
+      a[k] = t;
+    }
+  }
+  __syncthreads();
 }
 
+template <int BS>
+__device__ double bmax(double v) {
+  constexpr int NW = BS / 64;
+  __shared__ double lds[NW];
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) lds[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = lds[0];
+    for (int q = 1; q < NW; ++q) t = fmax(t, lds[q]);
+    v = t;
+  }
+  __syncthreads();
+  return v;
+}
+
+// out = A x, one thread per row.
+// Chunk of a row's nonzeros in flight together: 8, or 4 with 1024 threads per member (whose
+// 16 waves per CU allow 128 registers per thread).
+template <int BS>
+constexpr int kRowChunk = BS >= 1024 ? 4 : 8;
+
+template <int BS>
+__device__ void local_spmv(const LocalCsr& A, const double* x, double* out) {
+  PDLP_BLOCK_LOOP(r, A.nrows) out[r] = local_row_dot<kRowChunk<BS>>(A, int(r), x);
+}
+
+template <int BS>
 __device__ void batch_gap(DevState& S, const Bufs& B, int mode) {
   PointPtrs pt[2];
   gap_points_of(S, B, mode, pt);
@@ -129,34 +187,46 @@ __device__ void batch_gap(DevState& S, const Bufs& B, int mode) {
   {
     double acc[6] = {0, 0, 0, 0, 0, 0};
     PDLP_BLOCK_LOOP(idx, NM) gap_setup_elem(B, pt, ns, sw, idx, acc);
-    block_sum<6>(acc);
+    bsum<6, BS>(acc);
     if (threadIdx.x == 0) gap_setup_decide(S, mode, acc);
     __syncthreads();
   }
-  // bisection, one slot at a time, points recomputed from the bracket (few registers)
+  // bisection, one slot at a time, the 32 points of a pass in four groups of 8 (few
+  // registers; each point's sum is the one a single group of 32 would form)
+  __shared__ double tot[kGapPts];
   for (int pass = 0; pass < 13; ++pass) {
     bool any = false;
     for (int s = 0; s < ns; ++s) {
       if (S.gap_state[s] != 0) continue;
       any = true;
       const uint64_t lo = S.gap_lo[s], hi = S.gap_hi[s];
-      double acc[kGapPts];
-#pragma unroll
-      for (int i = 0; i < kGapPts; ++i) acc[i] = 0.0;
       const double* GA = s ? B.GA[1] : B.GA[0];
       const double* GB = s ? B.GB[1] : B.GB[0];
-      PDLP_BLOCK_LOOP(idx, NM) {
-        const double aa = GA[idx], b = GB[idx];
-        if (aa != 0.0) {
+      for (int g0 = 0; g0 < kGapPts; g0 += 8) {
+        double acc[8];
+        double pt8[8];
 #pragma unroll
-          for (int i = 0; i < kGapPts; ++i) {
-            const double e = fmin(__longlong_as_double((long long)gap_point(lo, hi, i + 1)) * aa, b);
-            acc[i] += e * e;
+        for (int i = 0; i < 8; ++i) {
+          acc[i] = 0.0;
+          pt8[i] = __longlong_as_double((long long)gap_point(lo, hi, g0 + i + 1));
+        }
+        PDLP_BLOCK_LOOP(idx, NM) {
+          const double aa = GA[idx], b = GB[idx];
+          if (aa != 0.0) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              const double e = fmin(pt8[i] * aa, b);
+              acc[i] += e * e;
+            }
           }
         }
+        bsum<8, BS>(acc);
+        if (threadIdx.x == 0) {
+#pragma unroll
+          for (int i = 0; i < 8; ++i) tot[g0 + i] = acc[i];
+        }
       }
-      block_sum<kGapPts>(acc);
-      if (threadIdx.x == 0) gap_bisect_decide_slot(S, s, acc);
+      if (threadIdx.x == 0) gap_bisect_decide_slot(S, s, tot);
       __syncthreads();
     }
     if (!any) break;
@@ -167,28 +237,34 @@ __device__ void batch_gap(DevState& S, const Bufs& B, int mode) {
       sstar[s] = (S.gap_state[s] == 1) ? INFINITY : __longlong_as_double((long long)S.gap_hi[s]);
     double acc[2] = {0.0, 0.0};
     PDLP_BLOCK_LOOP(idx, NM) gap_final_elem(B, S, ns, sstar, idx, acc);
-    block_sum<2>(acc);
+    bsum<2, BS>(acc);
     if (threadIdx.x == 0) gap_final_decide(S, mode, acc, nullptr);
     __syncthreads();
   }
 }
 
+template <int BS>
 __device__ void batch_kkt(DevState& S, const Bufs& B, int mode) {
   const PointPtrs pt = kkt_point_is_average(S, mode) ? average_point(B) : current_point(B, S.parity);
   double a[7] = {0, 0, 0, 0, 0, 0, 0};
   PDLP_BLOCK_LOOP(idx, int64_t(B.n) + B.m) kkt_elem(B, pt, idx, a);
-  block_sum<7>(a);
+  bsum<7, BS>(a);
   if (threadIdx.x == 0) kkt_decide(S, mode, a, nullptr);
   __syncthreads();
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmpl, double tol,
-                                                        int64_t iter_limit, int ruiz_iters,
-                                                        int pock_chambolle, double primal_importance) {
+template <int BS>
+__global__ __launch_bounds__(BS) void k_batch_solve(BatchDev D, DevState tmpl, double tol,
+                                                    int64_t iter_limit, int ruiz_iters,
+                                                    int pock_chambolle, double primal_importance) {
   __shared__ DevState S;
+  // the member's buffers live in LDS (read after each barrier) rather than in registers
+  __shared__ Bufs sB;
   const int mb = D.order[blockIdx.x];
   const BatchInst I = D.inst[mb];
-  const Bufs B = batch_bufs(D, I);
+  if (threadIdx.x == 0) sB = batch_bufs(D, I);
+  __syncthreads();
+  const Bufs& B = sB;
   const LocalCsr K{D.rp + I.rp, D.ci + I.nz, D.v + I.nz, I.m};
   const LocalCsr KT{D.rpT + I.rpT, D.ciT + I.nz, D.vT + I.nz, I.n};
   const int n = I.n, m = I.m;
@@ -202,6 +278,15 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
   double* D2 = const_cast<double*>(B.D2);
   PDLP_BLOCK_LOOP(i, m) D1[i] = 1.0;
   PDLP_BLOCK_LOOP(j, n) D2[j] = 1.0;
+  {
+    const int64_t nnz = K.rp[m];
+    const double* v0 = D.v0 + I.nz;
+    const double* vT0 = D.vT0 + I.nz;
+    PDLP_BLOCK_LOOP(e, nnz) {
+      K.v[e] = v0[e];
+      KT.v[e] = vT0[e];
+    }
+  }
   __syncthreads();
 
   // ---- diagonal preconditioning (Section 3.5): Ruiz passes, then Pock-Chambolle
@@ -273,8 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
     }
     const int64_t nnz = K.rp[m];
     PDLP_BLOCK_LOOP(e, nnz) vmax = fmax(vmax, fabs(K.v[e]));
-    block_sum<4>(a);
-    vmax = block_max(vmax);
+    bsum<4, BS>(a);
+    vmax = bmax<BS>(vmax);
     if (threadIdx.x == 0) {
       S.c_norm = sqrt(a[0]);
       S.q_norm = sqrt(a[1]);
@@ -284,12 +369,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
       S.eta = S.eta_hat;
     }
     __syncthreads();
-    local_spmv(K, B.X[0], B.KX[0]);
+    local_spmv<BS>(K, B.X[0], B.KX[0]);
     __syncthreads();
   }
 
   // ---- termination check before the first step
-  batch_kkt(S, B, 1);
+  batch_kkt<BS>(S, B, 1);
 
   // ---- Algorithm 1
   while (!S.done) {
@@ -310,20 +395,20 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
       double ax[1] = {0.0};
       double c1[1];
       PDLP_BLOCK_LOOP(j, n) {
-        const double s = kty_valid ? B.KTy[j] : local_row_dot(KT, int(j), pick(B.Y, P));
+        const double s = kty_valid ? B.KTy[j] : local_row_dot<kRowChunk<BS>>(KT, int(j), pick(B.Y, P));
         pe.row(int(j), s, c1);
         ax[0] += c1[0];
       }
-      block_sum<1>(ax);     // its barriers also publish x' to the whole workgroup
+      bsum<1, BS>(ax);      // its barriers also publish x' to the whole workgroup
       const DualEpi de{B.q, pick(B.Y, P), pick(B.KX, P), pick(B.Y, P ^ 1), pick(B.KX, P ^ 1), B.Sy, S.eta * S.omega, S.w_pending, B.m1};
       double ay[2] = {0.0, 0.0};
       double c2[2];
       PDLP_BLOCK_LOOP(i, m) {
-        de.row(int(i), local_row_dot(K, int(i), pick(B.X, P ^ 1)), c2);
+        de.row(int(i), local_row_dot<kRowChunk<BS>>(K, int(i), pick(B.X, P ^ 1)), c2);
         ay[0] += c2[0];
         ay[1] += c2[1];
       }
-      block_sum<2>(ay);
+      bsum<2, BS>(ay);
       if (threadIdx.x == 0) {
         if (!kty_valid) S.spmv_KT += 1;
         attempt_decide(S, ax[0], ay[0], ay[1], nullptr);
@@ -339,10 +424,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
       __syncthreads();
       if (threadIdx.x == 0) S.w_pending = 0.0;
       if (S.restarts_on) {
-        local_spmv(KT, B.YB, B.KTYB);
-        local_spmv(K, B.XB, B.KXB);
+        local_spmv<BS>(KT, B.YB, B.KTYB);
+        local_spmv<BS>(K, B.XB, B.KXB);
       }
-      if (!S.kty_valid) local_spmv(KT, pick(B.Y, P), B.KTy);
+      if (!S.kty_valid) local_spmv<BS>(KT, pick(B.Y, P), B.KTy);
       __syncthreads();
       if (threadIdx.x == 0) {
         if (S.restarts_on) {
@@ -354,10 +439,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
       }
       __syncthreads();
     }
-    if (S.restarts_on) batch_gap(S, B, 0);
-    batch_kkt(S, B, 0);
+    if (S.restarts_on) batch_gap<BS>(S, B, 0);
+    batch_kkt<BS>(S, B, 0);
     if (S.done) break;
-    if (S.restarts_on && S.restart) batch_gap(S, B, 1);
+    if (S.restarts_on && S.restart) batch_gap<BS>(S, B, 1);
     if (S.restart) {
       const bool avg = S.use_avg != 0;
       const int P = S.parity;
@@ -371,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
   // ---- KKT error of the returned point when the solve did not end at a passing check
   if (S.status != PDLP_OPTIMAL) {
     if (!S.kty_valid) {
-      local_spmv(KT, pick(B.Y, S.parity), B.KTy);
+      local_spmv<BS>(KT, pick(B.Y, S.parity), B.KTy);
       __syncthreads();
       if (threadIdx.x == 0) {
         S.kty_valid = 1;
@@ -379,13 +464,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_solve(BatchDev D, DevState tmp
       }
       __syncthreads();
     }
-    batch_kkt(S, B, 2);
+    batch_kkt<BS>(S, B, 2);
   }
   if (threadIdx.x == 0) D.out_state[mb] = S;
 }
 
 // x = D2 x~, y = D1 y~ of every member's returned point into packed outputs.
 __global__ __launch_bounds__(kBlock) void k_batch_output(BatchDev D, double* xo, double* yo) {
+  constexpr int BS = kBlock;
   const BatchInst I = D.inst[blockIdx.x];
   const Bufs B = batch_bufs(D, I);
   const DevState& S = D.out_state[blockIdx.x];

@@ -90,7 +90,8 @@ enum Pred : int {
   kPredCheckRestart = 4,
   kPredAttempt = 5,
   kPredAttemptKty = 6,
-  kPredMpNew = 7         // an attempt runs and starts a Malitsky-Pock iteration
+  kPredMpNew = 7,        // an attempt runs and starts a Malitsky-Pock iteration
+  kPredKtyPeek = 8       // K~^T y is not valid: form it for a KKT evaluation, leave it unmarked
 };
 
 }  // namespace pdlp

@@ -423,6 +423,7 @@ __device__ __forceinline__ void wave_task(const CsrDev& A, const G& x, const Epi
 }
 
 // wave_task with the entries per lane of the task (uniform across the wavefront).
+// R: rounds in flight for tasks of 1 or 2 entries per lane (at most 2 from 3 entries, 1 from 5).
 // EMAX: the most entries per lane the layout's tasks have (kElemsPerLane or kElemsPerLaneLds).
 template <int MODE, int R = 1, bool LOCAL = false, int EMAX = kElemsPerLane, class Epi, class G>
 __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const Epi& epi,
@@ -432,8 +433,9 @@ __device__ __forceinline__ void wave_task_e(const CsrDev& A, const G& x, const E
   switch (D.aux) {
     case 1: wave_task<MODE, 1, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
     case 2: wave_task<MODE, 2, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
-    case 3: wave_task<MODE, 3, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
-    case 4: wave_task<MODE, 4, R, LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    // at most two rounds at a time from 3 entries per lane
+    case 3: wave_task<MODE, 3, (R > 2 ? 2 : R), LOCAL>(A, x, epi, acc, D, off, lane64); break;
+    case 4: wave_task<MODE, 4, (R > 2 ? 2 : R), LOCAL>(A, x, epi, acc, D, off, lane64); break;
     // one round at a time above 4 entries per lane (two would exceed the registers)
     case 5: wave_task<MODE, 5, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
     case 6: wave_task<MODE, 6, 1, LOCAL>(A, x, epi, acc, D, off, lane64); break;
@@ -602,6 +604,7 @@ __device__ bool pred_ok(const DevState& S, int pred) {
     case kPredAttempt: return attempt_runs(S);
     case kPredAttemptKty: return primal_runs(S) && !S.kty_valid;
     case kPredMpNew: return primal_runs(S);
+    case kPredKtyPeek: return !S.kty_valid;
     default: return false;
   }
 }
@@ -1059,11 +1062,11 @@ __global__ __launch_bounds__(kLdsBlock) void k_lds_rows(CsrDev A, DevState* st, 
     if (A.cis16) {            // a slice: every column is in the stage
       const StageGather gx{stage};
       for (int t = G.tb + wave; t < G.te; t += kLdsWaves)
-        wave_task_e<kProd, 2, true, kElemsPerLaneLds>(A, gx, epi, acc, t, lane64);
+        wave_task_e<kProd, 4, true, kElemsPerLaneLds>(A, gx, epi, acc, t, lane64);
     } else {
       const LdsGather gx{stage, in, c0, uint32_t(h)};
       for (int t = G.tb + wave; t < G.te; t += kLdsWaves)
-        wave_task_e<kProd, 2, false, kElemsPerLaneLds>(A, gx, epi, acc, t, lane64);
+        wave_task_e<kProd, 4, false, kElemsPerLaneLds>(A, gx, epi, acc, t, lane64);
     }
   }
 }

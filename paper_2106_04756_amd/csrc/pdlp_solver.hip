@@ -1359,11 +1359,13 @@ int unroll_backward_impl(pdlp_solver* s, const double* gx, const double* gy, dou
 }
 
 // The KKT error of the returned point when the solve ended without a terminating check: the
-// current iterate, which needs K~^T y of the current y.
+// current iterate, which needs K~^T y of the current y.  That product is formed for the
+// evaluation only: it is not counted as a product of the iteration and leaves K~^T y marked
+// as not formed, so the next step of a later solve forms it as if nothing had been asked.
 int settle_kkt(pdlp_solver* s) {
   if (!s->kkt_stale) return 0;
   int rc;
-  if ((rc = launch_spmv(s, s->KT, s->B.Y[0], s->B.Y[1], 1, s->B.KTy, nullptr, 0, kPredKty, 2))) return rc;
+  if ((rc = launch_spmv(s, s->KT, s->B.Y[0], s->B.Y[1], 1, s->B.KTy, nullptr, 0, kPredKtyPeek, 0))) return rc;
   if ((rc = enqueue_kkt(s, 2))) return rc;
   s->kkt_stale = false;
   return 0;
@@ -1839,6 +1841,15 @@ int pdlp_unroll_get_info(const pdlp_solver* s, pdlp_unroll_info* info) {
 // batched solver
 // ------------------------------------------------------------------------------------------
 
+// Size classes of the batched solve, by member nonzeros: [0, 2^11), [2^11, 2^13), [2^13, 2^15),
+// [2^15, ..).  Each class runs as one launch with its own workgroup size.
+constexpr int kBatchClasses = PDLP_BATCH_CLASSES;
+constexpr int kBatchSizes[] = {64, 128, 256, 512, 1024};
+
+int batch_class_of(int64_t nnz) {
+  return nnz < (int64_t(1) << 11) ? 0 : nnz < (int64_t(1) << 13) ? 1 : nnz < (int64_t(1) << 15) ? 2 : 3;
+}
+
 struct pdlp_batch {
   hipStream_t stream = nullptr;
   int64_t count = 0, total_n = 0, total_m = 0;
@@ -1851,10 +1862,25 @@ struct pdlp_batch {
   double* yout = nullptr;
   std::string err;
   bool solved = false;
-  double create_seconds = 0.0, solve_seconds = 0.0;
+  double create_seconds = 0.0, solve_seconds = 0.0, tune_seconds = 0.0;
+  // members of each size class, largest first, and the workgroup size of each class
+  int64_t cls_count[kBatchClasses] = {0, 0, 0, 0};
+  const int32_t* cls_order[kBatchClasses] = {nullptr, nullptr, nullptr, nullptr};
+  int32_t cls_bs[kBatchClasses] = {256, 256, 256, 256};
+  hipStream_t cls_stream[kBatchClasses] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_start = nullptr;
+  hipEvent_t cls_ev[kBatchClasses] = {nullptr, nullptr, nullptr, nullptr};
 
   ~pdlp_batch() {
     if (stream) (void)hipStreamSynchronize(stream);
+    for (int c = 0; c < kBatchClasses; ++c) {
+      if (cls_stream[c]) {
+        (void)hipStreamSynchronize(cls_stream[c]);
+        (void)hipStreamDestroy(cls_stream[c]);
+      }
+      if (cls_ev[c]) (void)hipEventDestroy(cls_ev[c]);
+    }
+    if (ev_start) (void)hipEventDestroy(ev_start);
     for (void* p : allocs) (void)hipFree(p);
   }
   template <class T>
@@ -1869,6 +1895,44 @@ struct pdlp_batch {
 namespace {
 
 thread_local std::string g_batch_error;
+
+// One launch of the batched kernel over the members of size class c, with bs threads each.
+int batch_launch(pdlp_batch* b, int c, int bs, double tol, int64_t iter_limit, hipStream_t st) {
+  const unsigned g = unsigned(b->cls_count[c]);
+  if (g == 0) return 0;
+  BatchDev D = b->D;
+  D.order = b->cls_order[c];
+  const int ri = b->opts.ruiz_iters, pc = b->opts.pock_chambolle;
+  const double pi = b->opts.primal_importance;
+  switch (bs) {
+    case 64: k_batch_solve<64><<<g, 64, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
+    case 128: k_batch_solve<128><<<g, 128, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
+    case 256: k_batch_solve<256><<<g, 256, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
+    case 512: k_batch_solve<512><<<g, 512, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
+    case 1024: k_batch_solve<1024><<<g, 1024, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
+    default:
+      b->err = "internal error: unknown workgroup size";
+      return PDLP_ERR_DEVICE;
+  }
+  PDLP_LAUNCH(b);
+  return 0;
+}
+
+// Every class's launch on a stream of its own (largest class first), all after the work
+// already on the batch's stream and all waited for on it.
+int batch_run(pdlp_batch* b, double tol, int64_t iter_limit) {
+  PDLP_HIP(b, hipEventRecord(b->ev_start, b->stream));
+  for (int c = kBatchClasses - 1; c >= 0; --c) {
+    if (b->cls_count[c] == 0) continue;
+    PDLP_HIP(b, hipStreamWaitEvent(b->cls_stream[c], b->ev_start, 0));
+    int rc;
+    if ((rc = batch_launch(b, c, b->cls_bs[c], tol, iter_limit, b->cls_stream[c]))) return rc;
+    PDLP_HIP(b, hipEventRecord(b->cls_ev[c], b->cls_stream[c]));
+    PDLP_HIP(b, hipStreamWaitEvent(b->stream, b->cls_ev[c], 0));
+  }
+  PDLP_HIP(b, hipStreamSynchronize(b->stream));
+  return 0;
+}
 
 template <class T>
 int batch_fetch(pdlp_batch* b, const T* p, size_t count, std::vector<T>& tmp, const T** out) {
@@ -1990,17 +2054,23 @@ int batch_create_impl(pdlp_batch* b, int64_t count, const int64_t* hm, const int
   int64_t* drpT;
   int32_t* dci;
   int32_t* dciT;
+  double* dv0;
+  double* dvT0;
   if ((rc = batch_upload(b, b->inst.data(), b->inst.size(), &dinst)) ||
       (rc = batch_upload(b, rp, size_t(rp_total), &drp)) || (rc = batch_upload(b, rpT.data(), rpT.size(), &drpT)) ||
       (rc = batch_upload(b, ci, size_t(nz_total), &dci)) || (rc = batch_upload(b, ciT.data(), ciT.size(), &dciT)) ||
-      (rc = batch_upload(b, v, size_t(nz_total), &D.v)) || (rc = batch_upload(b, vT.data(), vT.size(), &D.vT)) ||
+      (rc = batch_upload(b, v, size_t(nz_total), &dv0)) || (rc = batch_upload(b, vT.data(), vT.size(), &dvT0)) ||
       (rc = batch_upload(b, hc, size_t(tn), &D.c0)) || (rc = batch_upload(b, hl, size_t(tn), &D.l0)) ||
       (rc = batch_upload(b, hu, size_t(tn), &D.u0)) || (rc = batch_upload(b, hq, size_t(tm), &D.q0)))
     return rc;
   D.inst = dinst;
+  D.v0 = dv0;
+  D.vT0 = dvT0;
+  PDLP_HIP(b, b->alloc(&D.v, size_t(nz_total)));
+  PDLP_HIP(b, b->alloc(&D.vT, size_t(nz_total)));
   {
     // workgroup order: members with the most nonzeros first (ties by index), so the longest
-    // solves start early and the small ones fill in behind them
+    // solves start early and the small ones fill in behind them; grouped by size class
     std::vector<int32_t> order(static_cast<size_t>(count));
     for (int64_t k = 0; k < count; ++k) order[size_t(k)] = int32_t(k);
     auto nz_of = [&](int32_t k) {
@@ -2011,7 +2081,25 @@ int batch_create_impl(pdlp_batch* b, int64_t count, const int64_t* hm, const int
     int32_t* dorder;
     if ((rc = batch_upload(b, order.data(), order.size(), &dorder))) return rc;
     D.order = dorder;
+    // classes are contiguous in this order (largest class first)
+    int64_t pos = 0;
+    for (int c = kBatchClasses - 1; c >= 0; --c) {
+      int64_t cnt = 0;
+      while (pos + cnt < count && batch_class_of(nz_of(order[size_t(pos + cnt)])) == c) ++cnt;
+      b->cls_count[c] = cnt;
+      b->cls_order[c] = dorder + pos;
+      pos += cnt;
+    }
+    if (pos != count) {
+      b->err = "internal error: size classes do not cover the members";
+      return PDLP_ERR_DEVICE;
+    }
   }
+  for (int c = 0; c < kBatchClasses; ++c) {
+    PDLP_HIP(b, hipStreamCreateWithFlags(&b->cls_stream[c], hipStreamNonBlocking));
+    PDLP_HIP(b, hipEventCreateWithFlags(&b->cls_ev[c], hipEventDisableTiming));
+  }
+  PDLP_HIP(b, hipEventCreateWithFlags(&b->ev_start, hipEventDisableTiming));
   D.rp = drp;
   D.rpT = drpT;
   D.ci = dci;
@@ -2103,20 +2191,82 @@ int pdlp_batch_solve(pdlp_batch* b, double tol, int64_t iter_limit) {
     b->err = "tol must be >= 0 and iter_limit >= 0";
     return PDLP_ERR_INVALID_ARGUMENT;
   }
-  if (b->solved) {
-    b->err = "a batch is solved once (create a new batch to solve again)";
-    return PDLP_ERR_INVALID_STATE;
-  }
   const double t0 = now_s();
-  k_batch_solve<<<unsigned(b->count), kBlock, 0, b->stream>>>(b->D, b->tmpl, tol, iter_limit,
-                                                             b->opts.ruiz_iters, b->opts.pock_chambolle,
-                                                             b->opts.primal_importance);
-  PDLP_LAUNCH(b);
-  PDLP_HIP(b, hipStreamSynchronize(b->stream));
+  int rc;
+  if ((rc = batch_run(b, tol, iter_limit))) return rc;
   b->solved = true;
   b->solve_seconds = now_s() - t0;
   return 0;
 }
+
+int pdlp_batch_tune(pdlp_batch* b, int64_t steps, int32_t* block_size) {
+  if (!b) return PDLP_ERR_INVALID_ARGUMENT;
+  if (steps < 1) {
+    b->err = "steps must be >= 1";
+    return PDLP_ERR_INVALID_ARGUMENT;
+  }
+  const double t0 = now_s();
+  hipEvent_t e0, e1;
+  PDLP_HIP(b, hipEventCreate(&e0));
+  PDLP_HIP(b, hipEventCreate(&e1));
+  int rc = 0;
+  for (int c = 0; c < kBatchClasses && rc == 0; ++c) {
+    if (b->cls_count[c] == 0) continue;
+    float best = 0.f;
+    int best_bs = b->cls_bs[c];
+    for (int bs : kBatchSizes) {
+      // a run of every member of the class for `steps` accepted steps (tol 0: none stops early)
+      if ((rc = batch_launch(b, c, bs, 0.0, steps, b->stream))) break;        // warm-up
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PDLP_ERR_DEVICE; break; }
+      if ((rc = batch_launch(b, c, bs, 0.0, steps, b->stream))) break;
+      float ms = 0.f;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        b->err = "batch tune: event timing failed";
+        rc = PDLP_ERR_DEVICE;
+        break;
+      }
+      if (best == 0.f || ms < best) {
+        best = ms;
+        best_bs = bs;
+      }
+    }
+    b->cls_bs[c] = best_bs;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  b->solved = false;             // the timing runs are not a solve
+  if (block_size)
+    for (int c = 0; c < kBatchClasses; ++c) block_size[c] = b->cls_bs[c];
+  b->tune_seconds = now_s() - t0;
+  return 0;
+}
+
+int pdlp_batch_set_block_sizes(pdlp_batch* b, const int32_t* block_size) {
+  if (!b || !block_size) return PDLP_ERR_INVALID_ARGUMENT;
+  for (int c = 0; c < kBatchClasses; ++c) {
+    bool ok = false;
+    for (int bs : kBatchSizes) ok = ok || block_size[c] == bs;
+    if (!ok) {
+      b->err = "workgroup sizes must be 64, 128, 256, 512 or 1024";
+      return PDLP_ERR_INVALID_ARGUMENT;
+    }
+  }
+  for (int c = 0; c < kBatchClasses; ++c) b->cls_bs[c] = block_size[c];
+  return 0;
+}
+
+int pdlp_batch_schedule(const pdlp_batch* b, int32_t* block_size, int64_t* members) {
+  if (!b) return PDLP_ERR_INVALID_ARGUMENT;
+  for (int c = 0; c < kBatchClasses; ++c) {
+    if (block_size) block_size[c] = b->cls_bs[c];
+    if (members) members[c] = b->cls_count[c];
+  }
+  return 0;
+}
+
+double pdlp_batch_tune_seconds(const pdlp_batch* b) { return b ? b->tune_seconds : -1.0; }
 
 int pdlp_batch_get(const pdlp_batch* cb, double* x, double* y, int32_t* status, int64_t* iterations,
                    double* kkt) {

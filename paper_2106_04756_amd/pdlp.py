@@ -27,6 +27,7 @@ EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pd
             "pdlp_reset_kernel_times",
             "pdlp_build_schedule", "pdlp_build_panel_layout", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
             "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error",
+            "pdlp_batch_tune", "pdlp_batch_set_block_sizes", "pdlp_batch_schedule", "pdlp_batch_tune_seconds",
             "pdlp_unroll_forward", "pdlp_unroll_forward_noalloc", "pdlp_unroll_backward",
             "pdlp_unroll_get_info"]
 
@@ -154,6 +155,14 @@ def lib() -> ctypes.CDLL:
         L.pdlp_batch_get.restype = ctypes.c_int
         L.pdlp_batch_solve_seconds.argtypes = [P]
         L.pdlp_batch_solve_seconds.restype = ctypes.c_double
+        L.pdlp_batch_tune.argtypes = [P, I64, P]
+        L.pdlp_batch_tune.restype = ctypes.c_int
+        L.pdlp_batch_set_block_sizes.argtypes = [P, P]
+        L.pdlp_batch_set_block_sizes.restype = ctypes.c_int
+        L.pdlp_batch_schedule.argtypes = [P, P, P]
+        L.pdlp_batch_schedule.restype = ctypes.c_int
+        L.pdlp_batch_tune_seconds.argtypes = [P]
+        L.pdlp_batch_tune_seconds.restype = ctypes.c_double
         L.pdlp_batch_destroy.argtypes = [P]
         L.pdlp_batch_destroy.restype = None
         L.pdlp_batch_last_error.argtypes = [P]
@@ -527,6 +536,31 @@ class Batch:
         """Solve every member; returns the wall time of the launch in seconds."""
         self._check(lib().pdlp_batch_solve(self._h, float(tol), int(iter_limit)))
         return lib().pdlp_batch_solve_seconds(self._h)
+
+    BATCH_CLASSES = 4
+
+    def tune(self, steps: int = 200):
+        """Pick each size class's workgroup size by timing every candidate (pdlp_batch_tune);
+        returns the sizes."""
+        bs = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
+        self._check(lib().pdlp_batch_tune(self._h, int(steps), bs.ctypes.data))
+        return [int(v) for v in bs]
+
+    def set_block_sizes(self, sizes):
+        bs = np.ascontiguousarray(sizes, dtype=np.int32)
+        if bs.size != self.BATCH_CLASSES:
+            raise ValueError(f"need {self.BATCH_CLASSES} sizes")
+        self._check(lib().pdlp_batch_set_block_sizes(self._h, bs.ctypes.data))
+
+    def schedule(self):
+        """(workgroup size per class, members per class)."""
+        bs = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
+        mc = np.zeros(self.BATCH_CLASSES, dtype=np.int64)
+        self._check(lib().pdlp_batch_schedule(self._h, bs.ctypes.data, mc.ctypes.data))
+        return [int(v) for v in bs], [int(v) for v in mc]
+
+    def tune_seconds(self) -> float:
+        return lib().pdlp_batch_tune_seconds(self._h)
 
     def get(self):
         """(list of x, list of y, status[count], iterations[count], kkt[count, 4])."""

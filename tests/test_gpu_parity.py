@@ -236,6 +236,7 @@ ABLATIONS = {
                      dict(primal_weight_update=0, primal_importance=0.1)),
     "no_scaling": (dict(ruiz_iters=0, pock_chambolle=False), dict(ruiz_iters=0, pock_chambolle=0)),
     "ruiz_only": (dict(pock_chambolle=False), dict(pock_chambolle=0)),
+    "pock_chambolle_only": (dict(ruiz_iters=0), dict(ruiz_iters=0)),
     "no_restart_weight_at_2j": (dict(restarts=False, pw_power_of_two=True),
                                 dict(adaptive_restarts=0, pw_power_of_two=1)),
 }
@@ -502,6 +503,51 @@ def test_batched_first_steps_match_oracle():
         ref = O.solve_lp(lp, tol=1e-30, iter_limit=40)
         assert st[k] == P.ITERATION_LIMIT and it[k] == 40
         assert rel(xs[k], ref.x) <= 1e-11 and rel(ys[k], ref.y) <= 1e-11, k
+
+
+@pytest.mark.parametrize("bs", [64, 128, 256, 512, 1024])
+def test_batched_workgroup_sizes_match_oracle(bs):
+    """Every workgroup size the tuner can pick for a size class: after 40 steps every member's
+    iterate equals the oracle's at the iterate tolerance, and a full solve is certified by the
+    oracle's KKT evaluation.  The members span three size classes."""
+    members = [lpgen.batched_instance(i) for i in (0, 2, 6, 9)] + \
+              [lpgen.add_empty_row_and_column(lpgen.tiny_plain(3, 60, 150, 20, 4))]
+    say("batch workgroup size", bs, [lp.nnz for lp in members])
+    b = P.Batch(members)
+    b.set_block_sizes([bs] * P.Batch.BATCH_CLASSES)
+    assert b.schedule()[0] == [bs] * P.Batch.BATCH_CLASSES
+    assert sum(b.schedule()[1]) == len(members)
+    b.solve(1e-30, 40)
+    xs, ys, st, it, _ = b.get()
+    for k, lp in enumerate(members):
+        ref = O.solve_lp(lp, tol=1e-30, iter_limit=40)
+        assert st[k] == P.ITERATION_LIMIT and it[k] == 40
+        assert rel(xs[k], ref.x) <= 1e-11 and rel(ys[k], ref.y) <= 1e-11, k
+    b.solve(1e-8, 100000)                    # a second solve starts again from the data
+    xs, ys, st, it, kkt = b.get()
+    for k, lp in enumerate(members):
+        assert st[k] == P.OPTIMAL, (k, st[k])
+        kk = O.kkt(lp.c, lp.K(), lp.q, lp.l, lp.u, lp.n_eq, xs[k], ys[k])
+        assert kk["kkt"] <= 1e-8 and abs(kk["kkt"] - kkt[k, 3]) <= 1e-10, (k, kk["kkt"])
+
+
+def test_batched_tune_then_solve_repeats_bitwise():
+    """The tuner's choice is one of the sizes, its timing runs leave no solve behind, and two
+    solves of the same batch give bit-identical points."""
+    members = [lpgen.batched_instance(i) for i in range(12)]
+    say("batch tune")
+    b = P.Batch(members)
+    sizes = b.tune(30)
+    assert all(v in (64, 128, 256, 512, 1024) for v in sizes) and b.schedule()[0] == sizes
+    with pytest.raises(P.PdlpError):
+        b.get()
+    b.solve(1e-8, 3000)
+    x1, y1, st1, it1, k1 = b.get()
+    b.solve(1e-8, 3000)
+    x2, y2, st2, it2, k2 = b.get()
+    for k in range(len(members)):
+        assert np.array_equal(x1[k], x2[k]) and np.array_equal(y1[k], y2[k])
+    assert np.array_equal(it1, it2) and np.array_equal(k1, k2)
 
 
 def test_batched_rejects_bad_member():

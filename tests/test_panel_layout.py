@@ -53,10 +53,21 @@ def _check(K, L, npanel, groups, aligned, cuts=None, emax=8):
     # slots: row r's panel rows in panel order, covering the row
     sptr, sidx = L["slot_ptr"], L["slot_idx"]
     assert sptr[-1] == nprow and np.array_equal(np.sort(sidx), np.arange(nprow))
+    piece = 512 if emax == 16 else None            # LDS layouts cut longer runs into pieces
     for r in range(m):
         ks = sidx[sptr[r]:sptr[r + 1]]
-        assert np.all(prow_row[ks] == r) and np.all(np.diff(panel_of[ks]) > 0)
+        assert np.all(prow_row[ks] == r) and np.all(np.diff(panel_of[ks]) >= 0)
         assert (pp[ks + 1] - pp[ks]).sum() == rp[r + 1] - rp[r]
+        # the row's entries in order: each panel row starts where the previous one ended
+        if ks.size:
+            starts = src[pp[ks]]
+            assert starts[0] == rp[r] and np.array_equal(starts[1:], src[pp[ks[:-1] + 1] - 1] + 1)
+        same = np.diff(panel_of[ks]) == 0
+        if piece is None:
+            assert not same.any()
+        else:
+            # pieces of one run: all but the run's last hold exactly 512 entries
+            assert np.all((pp[ks[:-1][same] + 1] - pp[ks[:-1][same]]) == piece)
     # wavefront tasks: inside their panel, E L >= every row, every short panel row once
     wave, wb = L["wave"], L["wave_begin"]
     lens = np.diff(pp)
@@ -71,7 +82,10 @@ def _check(K, L, npanel, groups, aligned, cuts=None, emax=8):
             assert lanes == 1 or np.all(lens[a:a + b] > emax * (lanes // 2))
             cov[a:a + b] += 1
     assert np.array_equal(cov, (lens <= 512).astype(np.int64))
-    assert L["nblock"] == int((lens > 512).sum())
+    long_ = lens[lens > 512]                        # a workgroup task each, chunks of 16384 beyond
+    assert L["nblock"] == int(np.where(long_ > 16384, -(-long_ // 16384), 1).sum())
+    if piece is not None:                           # runs beyond 16384 entries stay whole
+        assert np.all((lens <= piece) | (lens > 16384))
     # interleaved entries, walked as the kernel reads them
     off, cis, vs = L["task_off"], L["cis"], L["vs"]
     assert off[0] == 0 and off[-1] == cis.size
@@ -131,6 +145,48 @@ def test_panel_layout_width_slices(emax):
     cuts = np.minimum(np.arange(npanel + 1) * W, K.shape[1]).astype(np.int32)
     L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, cuts=cuts, groups=9, emax=emax)
     _check(K, L, npanel, 9, False, cuts=cuts, emax=emax)
+
+
+@pytest.mark.parametrize("npanel", [1, 3])
+def test_lds_layout_cuts_long_runs_into_pieces(npanel):
+    """Rows of 513 .. 2600 nonzeros inside one panel: the LDS layouts (16 entries per lane) hold
+    them as consecutive pieces of 512 entries, so they need no workgroup task."""
+    rng = np.random.default_rng(7)
+    m, n = 40, 3000
+    lens = rng.choice([1, 7, 600, 1100, 2600], size=m)
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        cs = rng.choice(n, size=ln, replace=False)
+        rows.append(np.full(cs.size, i))
+        cols.append(cs)
+    K = sp.csr_matrix((rng.standard_normal(int(lens.sum())), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(m, n))
+    K.sort_indices()
+    L = P.panel_layout(K.indptr, K.indices, K.data, n, npanel, groups=6, emax=16)
+    assert L["nblock"] == 0
+    _check(K, L, npanel, 6, False, emax=16)
+    L8 = P.panel_layout(K.indptr, K.indices, K.data, n, npanel, groups=6, emax=8)
+    assert L8["nblock"] > 0
+    _check(K, L8, npanel, 6, False, emax=8)
+
+
+def test_lds_layout_keeps_giant_runs_whole():
+    """A run of more than 16384 entries in one panel stays one workgroup task (its pieces would
+    serialize the combine); the shorter runs around it are cut."""
+    rng = np.random.default_rng(8)
+    m, n = 6, 20000
+    lens = [3, 17000, 700, 1, 16384, 40]
+    rows, cols = [], []
+    for i, ln in enumerate(lens):
+        cs = rng.choice(n, size=ln, replace=False)
+        rows.append(np.full(cs.size, i))
+        cols.append(cs)
+    K = sp.csr_matrix((rng.standard_normal(int(sum(lens))), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(m, n))
+    K.sort_indices()
+    L = P.panel_layout(K.indptr, K.indices, K.data, n, 1, groups=2, emax=16)
+    assert L["nblock"] == 2                          # the 17000-entry run in two chunks
+    _check(K, L, 1, 2, False, emax=16)
 
 
 def test_panel_layout_rejects_bad_arguments():
