@@ -285,7 +285,9 @@ def bench_batched(P, lpgen, count, iter_limit, sample=32, oracle_budget_s=20.0, 
     b = P.Batch(lps)
     default_sizes, members = b.schedule()
     sizes = b.tune(tune_steps)
-    log(f"batched: tuned workgroup sizes {sizes} for classes of {members} members in {b.tune_seconds():.2f}s")
+    tune_s = b.tune_seconds()
+    log(f"batched: tuned schedules (threads x rows per thread) {sizes} for classes of {members} members "
+        f"in {tune_s:.2f}s")
     secs = b.solve(1e-8, iter_limit)
     _, _, st, it, kkt = b.get()
     b.close()
@@ -306,8 +308,8 @@ def bench_batched(P, lpgen, count, iter_limit, sample=32, oracle_budget_s=20.0, 
     out = {"workload": f"{count} LPs, m log-uniform in [50,2000], n = U[2,3] m, 3-8 nonzeros per "
                        f"column, seeds 3000+i", "tol": 1e-8, "iter_limit": iter_limit,
            "schedule": {"class_nonzeros": ["<2^11", "2^11..2^13", "2^13..2^15", ">=2^15"],
-                        "members": members, "workgroup_sizes": sizes, "untuned_sizes": default_sizes,
-                        "tune_steps": tune_steps, "tune_seconds": b.tune_seconds()},
+                        "members": members, "threads_x_rows": sizes, "untuned": default_sizes,
+                        "tune_steps": tune_steps, "tune_seconds": tune_s},
            "seconds": secs, "count": count, "converged": conv, "not_converged": count - conv,
            "lps_per_s": count / secs if conv == count else None,
            "converged_per_s": conv / secs,

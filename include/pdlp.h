@@ -250,25 +250,28 @@ int pdlp_batch_create(pdlp_batch **out, int64_t count, const int64_t *m, const i
  * later call repeats the solve, with its own tol and iter_limit).
  * The members fall into PDLP_BATCH_CLASSES size classes by nonzeros ([0, 2^11), [2^11, 2^13),
  * [2^13, 2^15), [2^15, ...)); each class runs as one persistent launch, members largest first,
- * with the workgroup size (threads per member: 64, 128, 256, 512 or 1024) set for that class
- * (256 until pdlp_batch_tune or pdlp_batch_set_block_sizes), the classes concurrently. */
+ * classes concurrently, with the schedule set for that class: the threads per member (64, 128,
+ * 256, 512 or 1024) and the rows per thread whose products are in flight together (1 or 2;
+ * 2 only with 128, 256 or 512 threads).  Until pdlp_batch_tune or pdlp_batch_set_schedule,
+ * every class runs 256 threads x 1 row. */
 #define PDLP_BATCH_CLASSES 4
 int pdlp_batch_solve(pdlp_batch *b, double tol, int64_t iter_limit);
 
-/* pdlp_batch_tune - pick each class's workgroup size: every candidate size runs the class's
- * members for `steps` accepted steps (tol 0, so none stops early; the run is timed with HIP
- * events after one untimed run) and the fastest is kept.  block_size (may be NULL) receives
- * the PDLP_BATCH_CLASSES choices.  The timing runs leave no solve behind (pdlp_batch_get needs
- * a pdlp_batch_solve after it).  Errors: PDLP_ERR_INVALID_ARGUMENT for steps < 1. */
-int pdlp_batch_tune(pdlp_batch *b, int64_t steps, int32_t *block_size);
+/* pdlp_batch_tune - pick each class's schedule: every candidate (64x1, 128x1, 128x2, 256x1,
+ * 256x2, 512x1, 512x2, 1024x1 threads x rows) runs the class's members for `steps` accepted
+ * steps (tol 0, so none stops early; timed with HIP events after one untimed run) and the
+ * fastest is kept.  threads, rows (may be NULL) receive the PDLP_BATCH_CLASSES choices.  The
+ * timing runs leave no solve behind (pdlp_batch_get needs a pdlp_batch_solve after it).
+ * Errors: PDLP_ERR_INVALID_ARGUMENT for steps < 1. */
+int pdlp_batch_tune(pdlp_batch *b, int64_t steps, int32_t *threads, int32_t *rows);
 
-/* pdlp_batch_set_block_sizes - set the PDLP_BATCH_CLASSES workgroup sizes (each 64, 128, 256,
- * 512 or 1024; else PDLP_ERR_INVALID_ARGUMENT). */
-int pdlp_batch_set_block_sizes(pdlp_batch *b, const int32_t *block_size);
+/* pdlp_batch_set_schedule - set the PDLP_BATCH_CLASSES schedules (threads[c] x rows[c], one
+ * of the candidates of pdlp_batch_tune; else PDLP_ERR_INVALID_ARGUMENT). */
+int pdlp_batch_set_schedule(pdlp_batch *b, const int32_t *threads, const int32_t *rows);
 
-/* pdlp_batch_schedule - the current workgroup size and the member count of each class
- * (PDLP_BATCH_CLASSES values each; either pointer may be NULL). */
-int pdlp_batch_schedule(const pdlp_batch *b, int32_t *block_size, int64_t *members);
+/* pdlp_batch_schedule - the current schedule and the member count of each class
+ * (PDLP_BATCH_CLASSES values each; any pointer may be NULL). */
+int pdlp_batch_schedule(const pdlp_batch *b, int32_t *threads, int32_t *rows, int64_t *members);
 
 /* pdlp_batch_tune_seconds - host wall time of the last pdlp_batch_tune. */
 double pdlp_batch_tune_seconds(const pdlp_batch *b);

@@ -120,6 +120,46 @@ __device__ __forceinline__ double local_row_dot(const LocalCsr& A, int r, const 
   return s;
 }
 
+// Rows r[0..R) of A times x together (r[q] < 0: no row), each summed as local_row_dot sums
+// it: the offsets, then each chunk's loads and gathers of all R rows are in flight together.
+template <int C, int R>
+__device__ __forceinline__ void local_rows_dot(const LocalCsr& A, const int (&r)[R], const double* __restrict__ x,
+                                               double (&s)[R]) {
+  int64_t p0[R], p1[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    s[q] = 0.0;
+    p0[q] = r[q] >= 0 ? A.rp[r[q]] : 0;
+    p1[q] = r[q] >= 0 ? A.rp[r[q] + 1] : 0;
+  }
+  for (int64_t off = 0;; off += C) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < R; ++q) any = any || p0[q] + off < p1[q];
+    if (!any) break;
+    double v[R][C], xv[R][C];
+    int32_t c[R][C];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int64_t last = p1[q] > p0[q] ? p1[q] - 1 : 0;
+#pragma unroll
+      for (int k = 0; k < C; ++k) {
+        const int64_t e = (p0[q] + off + k < p1[q]) ? p0[q] + off + k : last;
+        v[q][k] = p1[q] > p0[q] ? A.v[e] : 0.0;
+        c[q][k] = p1[q] > p0[q] ? A.ci[e] : 0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int k = 0; k < C; ++k) xv[q][k] = (p1[q] > p0[q]) ? x[c[q][k]] : 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+      for (int k = 0; k < C; ++k) s[q] = s[q] + ((p0[q] + off + k < p1[q]) ? v[q][k] * xv[q][k] : 0.0);
+  }
+}
+
 #define PDLP_BLOCK_LOOP(idx, total) for (int64_t idx = threadIdx.x; idx < (total); idx += BS)
 
 // Sum over a workgroup of BS threads of N values per thread, valid in thread 0: wave sums,
@@ -253,7 +293,9 @@ __device__ void batch_kkt(DevState& S, const Bufs& B, int mode) {
   __syncthreads();
 }
 
-template <int BS>
+// BS threads per member; the attempt's products take RR rows per thread at a time, CC
+// nonzeros of each at a time (the schedule the host's tuner picks per size class).
+template <int BS, int CC = kRowChunk<BS>, int RR = 1>
 __global__ __launch_bounds__(BS) void k_batch_solve(BatchDev D, DevState tmpl, double tol,
                                                     int64_t iter_limit, int ruiz_iters,
                                                     int pock_chambolle, double primal_importance) {
@@ -394,19 +436,61 @@ __global__ __launch_bounds__(BS) void k_batch_solve(BatchDev D, DevState tmpl, d
       const PrimalEpi pe{B.c, B.l, B.u, pick(B.X, P), pick(B.X, P ^ 1), B.Sx, B.KTy, S.eta / S.omega, S.w_pending, !kty_valid};
       double ax[1] = {0.0};
       double c1[1];
-      PDLP_BLOCK_LOOP(j, n) {
-        const double s = kty_valid ? B.KTy[j] : local_row_dot<kRowChunk<BS>>(KT, int(j), pick(B.Y, P));
-        pe.row(int(j), s, c1);
-        ax[0] += c1[0];
+      if constexpr (RR == 1) {
+        PDLP_BLOCK_LOOP(j, n) {
+          const double s = kty_valid ? B.KTy[j] : local_row_dot<CC>(KT, int(j), pick(B.Y, P));
+          pe.row(int(j), s, c1);
+          ax[0] += c1[0];
+        }
+      } else {
+        // rows j0, j0 + BS, ..., j0 + (RR - 1) BS together; each thread still updates its rows
+        // in the order of the one-row loop
+        for (int64_t j0 = threadIdx.x; j0 < n; j0 += int64_t(RR) * BS) {
+          int rows[RR];
+          double sv[RR];
+#pragma unroll
+          for (int q = 0; q < RR; ++q) rows[q] = (j0 + int64_t(q) * BS < n) ? int(j0 + int64_t(q) * BS) : -1;
+          if (kty_valid) {
+#pragma unroll
+            for (int q = 0; q < RR; ++q) sv[q] = rows[q] >= 0 ? B.KTy[rows[q]] : 0.0;
+          } else {
+            local_rows_dot<CC, RR>(KT, rows, pick(B.Y, P), sv);
+          }
+#pragma unroll
+          for (int q = 0; q < RR; ++q) {
+            if (rows[q] >= 0) {
+              pe.row(rows[q], sv[q], c1);
+              ax[0] += c1[0];
+            }
+          }
+        }
       }
       bsum<1, BS>(ax);      // its barriers also publish x' to the whole workgroup
       const DualEpi de{B.q, pick(B.Y, P), pick(B.KX, P), pick(B.Y, P ^ 1), pick(B.KX, P ^ 1), B.Sy, S.eta * S.omega, S.w_pending, B.m1};
       double ay[2] = {0.0, 0.0};
       double c2[2];
-      PDLP_BLOCK_LOOP(i, m) {
-        de.row(int(i), local_row_dot<kRowChunk<BS>>(K, int(i), pick(B.X, P ^ 1)), c2);
-        ay[0] += c2[0];
-        ay[1] += c2[1];
+      if constexpr (RR == 1) {
+        PDLP_BLOCK_LOOP(i, m) {
+          de.row(int(i), local_row_dot<CC>(K, int(i), pick(B.X, P ^ 1)), c2);
+          ay[0] += c2[0];
+          ay[1] += c2[1];
+        }
+      } else {
+        for (int64_t i0 = threadIdx.x; i0 < m; i0 += int64_t(RR) * BS) {
+          int rows[RR];
+          double sv[RR];
+#pragma unroll
+          for (int q = 0; q < RR; ++q) rows[q] = (i0 + int64_t(q) * BS < m) ? int(i0 + int64_t(q) * BS) : -1;
+          local_rows_dot<CC, RR>(K, rows, pick(B.X, P ^ 1), sv);
+#pragma unroll
+          for (int q = 0; q < RR; ++q) {
+            if (rows[q] >= 0) {
+              de.row(rows[q], sv[q], c2);
+              ay[0] += c2[0];
+              ay[1] += c2[1];
+            }
+          }
+        }
       }
       bsum<2, BS>(ay);
       if (threadIdx.x == 0) {

@@ -1844,7 +1844,14 @@ int pdlp_unroll_get_info(const pdlp_solver* s, pdlp_unroll_info* info) {
 // Size classes of the batched solve, by member nonzeros: [0, 2^11), [2^11, 2^13), [2^13, 2^15),
 // [2^15, ..).  Each class runs as one launch with its own workgroup size.
 constexpr int kBatchClasses = PDLP_BATCH_CLASSES;
-constexpr int kBatchSizes[] = {64, 128, 256, 512, 1024};
+// The schedules a class can run with: threads per member, and rows per thread whose products
+// are in flight together (2 with 4 nonzeros of each at a time, else 1 row with 8, or 4 at 1024
+// threads, whose 16 waves per CU allow 128 registers per thread).
+struct BatchSchedule {
+  int threads, rows;
+};
+constexpr BatchSchedule kBatchSchedules[] = {{64, 1},  {128, 1}, {128, 2}, {256, 1},
+                                             {256, 2}, {512, 1}, {512, 2}, {1024, 1}};
 
 int batch_class_of(int64_t nnz) {
   return nnz < (int64_t(1) << 11) ? 0 : nnz < (int64_t(1) << 13) ? 1 : nnz < (int64_t(1) << 15) ? 2 : 3;
@@ -1866,7 +1873,8 @@ struct pdlp_batch {
   // members of each size class, largest first, and the workgroup size of each class
   int64_t cls_count[kBatchClasses] = {0, 0, 0, 0};
   const int32_t* cls_order[kBatchClasses] = {nullptr, nullptr, nullptr, nullptr};
-  int32_t cls_bs[kBatchClasses] = {256, 256, 256, 256};
+  int32_t cls_bs[kBatchClasses] = {256, 256, 256, 256};     // threads per member
+  int32_t cls_rows[kBatchClasses] = {1, 1, 1, 1};           // rows per thread in flight
   hipStream_t cls_stream[kBatchClasses] = {nullptr, nullptr, nullptr, nullptr};
   hipEvent_t ev_start = nullptr;
   hipEvent_t cls_ev[kBatchClasses] = {nullptr, nullptr, nullptr, nullptr};
@@ -1896,22 +1904,34 @@ namespace {
 
 thread_local std::string g_batch_error;
 
-// One launch of the batched kernel over the members of size class c, with bs threads each.
-int batch_launch(pdlp_batch* b, int c, int bs, double tol, int64_t iter_limit, hipStream_t st) {
+bool batch_schedule_valid(int threads, int rows) {
+  for (const BatchSchedule& q : kBatchSchedules)
+    if (q.threads == threads && q.rows == rows) return true;
+  return false;
+}
+
+// One launch of the batched kernel over the members of size class c with the schedule
+// (bs threads per member, rows per thread).
+int batch_launch(pdlp_batch* b, int c, int bs, int rows, double tol, int64_t iter_limit, hipStream_t st) {
   const unsigned g = unsigned(b->cls_count[c]);
   if (g == 0) return 0;
   BatchDev D = b->D;
   D.order = b->cls_order[c];
   const int ri = b->opts.ruiz_iters, pc = b->opts.pock_chambolle;
   const double pi = b->opts.primal_importance;
-  switch (bs) {
-    case 64: k_batch_solve<64><<<g, 64, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
-    case 128: k_batch_solve<128><<<g, 128, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
-    case 256: k_batch_solve<256><<<g, 256, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
-    case 512: k_batch_solve<512><<<g, 512, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
-    case 1024: k_batch_solve<1024><<<g, 1024, 0, st>>>(D, b->tmpl, tol, iter_limit, ri, pc, pi); break;
+  const DevState& T = b->tmpl;
+  const int key = bs * 10 + rows;
+  switch (key) {
+    case 641: k_batch_solve<64><<<g, 64, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 1281: k_batch_solve<128><<<g, 128, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 1282: k_batch_solve<128, 4, 2><<<g, 128, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 2561: k_batch_solve<256><<<g, 256, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 2562: k_batch_solve<256, 4, 2><<<g, 256, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 5121: k_batch_solve<512><<<g, 512, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 5122: k_batch_solve<512, 4, 2><<<g, 512, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
+    case 10241: k_batch_solve<1024><<<g, 1024, 0, st>>>(D, T, tol, iter_limit, ri, pc, pi); break;
     default:
-      b->err = "internal error: unknown workgroup size";
+      b->err = "internal error: unknown batch schedule";
       return PDLP_ERR_DEVICE;
   }
   PDLP_LAUNCH(b);
@@ -1926,7 +1946,7 @@ int batch_run(pdlp_batch* b, double tol, int64_t iter_limit) {
     if (b->cls_count[c] == 0) continue;
     PDLP_HIP(b, hipStreamWaitEvent(b->cls_stream[c], b->ev_start, 0));
     int rc;
-    if ((rc = batch_launch(b, c, b->cls_bs[c], tol, iter_limit, b->cls_stream[c]))) return rc;
+    if ((rc = batch_launch(b, c, b->cls_bs[c], b->cls_rows[c], tol, iter_limit, b->cls_stream[c]))) return rc;
     PDLP_HIP(b, hipEventRecord(b->cls_ev[c], b->cls_stream[c]));
     PDLP_HIP(b, hipStreamWaitEvent(b->stream, b->cls_ev[c], 0));
   }
@@ -2199,7 +2219,7 @@ int pdlp_batch_solve(pdlp_batch* b, double tol, int64_t iter_limit) {
   return 0;
 }
 
-int pdlp_batch_tune(pdlp_batch* b, int64_t steps, int32_t* block_size) {
+int pdlp_batch_tune(pdlp_batch* b, int64_t steps, int32_t* threads, int32_t* rows) {
   if (!b) return PDLP_ERR_INVALID_ARGUMENT;
   if (steps < 1) {
     b->err = "steps must be >= 1";
@@ -2213,12 +2233,13 @@ int pdlp_batch_tune(pdlp_batch* b, int64_t steps, int32_t* block_size) {
   for (int c = 0; c < kBatchClasses && rc == 0; ++c) {
     if (b->cls_count[c] == 0) continue;
     float best = 0.f;
-    int best_bs = b->cls_bs[c];
-    for (int bs : kBatchSizes) {
+    BatchSchedule best_q{b->cls_bs[c], b->cls_rows[c]};
+    for (const BatchSchedule& q : kBatchSchedules) {
+      const int bs = q.threads;
       // a run of every member of the class for `steps` accepted steps (tol 0: none stops early)
-      if ((rc = batch_launch(b, c, bs, 0.0, steps, b->stream))) break;        // warm-up
+      if ((rc = batch_launch(b, c, bs, q.rows, 0.0, steps, b->stream))) break;        // warm-up
       if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = PDLP_ERR_DEVICE; break; }
-      if ((rc = batch_launch(b, c, bs, 0.0, steps, b->stream))) break;
+      if ((rc = batch_launch(b, c, bs, q.rows, 0.0, steps, b->stream))) break;
       float ms = 0.f;
       if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
           hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
@@ -2228,39 +2249,45 @@ int pdlp_batch_tune(pdlp_batch* b, int64_t steps, int32_t* block_size) {
       }
       if (best == 0.f || ms < best) {
         best = ms;
-        best_bs = bs;
+        best_q = q;
       }
     }
-    b->cls_bs[c] = best_bs;
+    b->cls_bs[c] = best_q.threads;
+    b->cls_rows[c] = best_q.rows;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (rc) return rc;
   b->solved = false;             // the timing runs are not a solve
-  if (block_size)
-    for (int c = 0; c < kBatchClasses; ++c) block_size[c] = b->cls_bs[c];
+  for (int c = 0; c < kBatchClasses; ++c) {
+    if (threads) threads[c] = b->cls_bs[c];
+    if (rows) rows[c] = b->cls_rows[c];
+  }
   b->tune_seconds = now_s() - t0;
   return 0;
 }
 
-int pdlp_batch_set_block_sizes(pdlp_batch* b, const int32_t* block_size) {
-  if (!b || !block_size) return PDLP_ERR_INVALID_ARGUMENT;
+int pdlp_batch_set_schedule(pdlp_batch* b, const int32_t* threads, const int32_t* rows) {
+  if (!b || !threads || !rows) return PDLP_ERR_INVALID_ARGUMENT;
   for (int c = 0; c < kBatchClasses; ++c) {
-    bool ok = false;
-    for (int bs : kBatchSizes) ok = ok || block_size[c] == bs;
-    if (!ok) {
-      b->err = "workgroup sizes must be 64, 128, 256, 512 or 1024";
+    if (!batch_schedule_valid(threads[c], rows[c])) {
+      b->err = "batch schedule must be one of 64x1, 128x1, 128x2, 256x1, 256x2, 512x1, 512x2, "
+               "1024x1 (threads x rows per thread)";
       return PDLP_ERR_INVALID_ARGUMENT;
     }
   }
-  for (int c = 0; c < kBatchClasses; ++c) b->cls_bs[c] = block_size[c];
+  for (int c = 0; c < kBatchClasses; ++c) {
+    b->cls_bs[c] = threads[c];
+    b->cls_rows[c] = rows[c];
+  }
   return 0;
 }
 
-int pdlp_batch_schedule(const pdlp_batch* b, int32_t* block_size, int64_t* members) {
+int pdlp_batch_schedule(const pdlp_batch* b, int32_t* threads, int32_t* rows, int64_t* members) {
   if (!b) return PDLP_ERR_INVALID_ARGUMENT;
   for (int c = 0; c < kBatchClasses; ++c) {
-    if (block_size) block_size[c] = b->cls_bs[c];
+    if (threads) threads[c] = b->cls_bs[c];
+    if (rows) rows[c] = b->cls_rows[c];
     if (members) members[c] = b->cls_count[c];
   }
   return 0;

@@ -27,7 +27,7 @@ EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pd
             "pdlp_reset_kernel_times",
             "pdlp_build_schedule", "pdlp_build_panel_layout", "pdlp_batch_create", "pdlp_batch_solve", "pdlp_batch_get",
             "pdlp_batch_solve_seconds", "pdlp_batch_destroy", "pdlp_batch_last_error",
-            "pdlp_batch_tune", "pdlp_batch_set_block_sizes", "pdlp_batch_schedule", "pdlp_batch_tune_seconds",
+            "pdlp_batch_tune", "pdlp_batch_set_schedule", "pdlp_batch_schedule", "pdlp_batch_tune_seconds",
             "pdlp_unroll_forward", "pdlp_unroll_forward_noalloc", "pdlp_unroll_backward",
             "pdlp_unroll_get_info"]
 
@@ -155,11 +155,11 @@ def lib() -> ctypes.CDLL:
         L.pdlp_batch_get.restype = ctypes.c_int
         L.pdlp_batch_solve_seconds.argtypes = [P]
         L.pdlp_batch_solve_seconds.restype = ctypes.c_double
-        L.pdlp_batch_tune.argtypes = [P, I64, P]
+        L.pdlp_batch_tune.argtypes = [P, I64, P, P]
         L.pdlp_batch_tune.restype = ctypes.c_int
-        L.pdlp_batch_set_block_sizes.argtypes = [P, P]
-        L.pdlp_batch_set_block_sizes.restype = ctypes.c_int
-        L.pdlp_batch_schedule.argtypes = [P, P, P]
+        L.pdlp_batch_set_schedule.argtypes = [P, P, P]
+        L.pdlp_batch_set_schedule.restype = ctypes.c_int
+        L.pdlp_batch_schedule.argtypes = [P, P, P, P]
         L.pdlp_batch_schedule.restype = ctypes.c_int
         L.pdlp_batch_tune_seconds.argtypes = [P]
         L.pdlp_batch_tune_seconds.restype = ctypes.c_double
@@ -539,25 +539,31 @@ class Batch:
 
     BATCH_CLASSES = 4
 
-    def tune(self, steps: int = 200):
-        """Pick each size class's workgroup size by timing every candidate (pdlp_batch_tune);
-        returns the sizes."""
-        bs = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
-        self._check(lib().pdlp_batch_tune(self._h, int(steps), bs.ctypes.data))
-        return [int(v) for v in bs]
+    SCHEDULES = [(64, 1), (128, 1), (128, 2), (256, 1), (256, 2), (512, 1), (512, 2), (1024, 1)]
 
-    def set_block_sizes(self, sizes):
-        bs = np.ascontiguousarray(sizes, dtype=np.int32)
-        if bs.size != self.BATCH_CLASSES:
-            raise ValueError(f"need {self.BATCH_CLASSES} sizes")
-        self._check(lib().pdlp_batch_set_block_sizes(self._h, bs.ctypes.data))
+    def tune(self, steps: int = 200):
+        """Pick each size class's schedule by timing every candidate (pdlp_batch_tune);
+        returns [(threads, rows per thread)] per class."""
+        th = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
+        rw = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
+        self._check(lib().pdlp_batch_tune(self._h, int(steps), th.ctypes.data, rw.ctypes.data))
+        return [(int(a), int(b)) for a, b in zip(th, rw)]
+
+    def set_schedule(self, schedule):
+        """schedule: (threads, rows per thread) per class."""
+        if len(schedule) != self.BATCH_CLASSES:
+            raise ValueError(f"need {self.BATCH_CLASSES} schedules")
+        th = np.ascontiguousarray([a for a, _ in schedule], dtype=np.int32)
+        rw = np.ascontiguousarray([b for _, b in schedule], dtype=np.int32)
+        self._check(lib().pdlp_batch_set_schedule(self._h, th.ctypes.data, rw.ctypes.data))
 
     def schedule(self):
-        """(workgroup size per class, members per class)."""
-        bs = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
+        """([(threads, rows per thread)] per class, members per class)."""
+        th = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
+        rw = np.zeros(self.BATCH_CLASSES, dtype=np.int32)
         mc = np.zeros(self.BATCH_CLASSES, dtype=np.int64)
-        self._check(lib().pdlp_batch_schedule(self._h, bs.ctypes.data, mc.ctypes.data))
-        return [int(v) for v in bs], [int(v) for v in mc]
+        self._check(lib().pdlp_batch_schedule(self._h, th.ctypes.data, rw.ctypes.data, mc.ctypes.data))
+        return [(int(a), int(b)) for a, b in zip(th, rw)], [int(v) for v in mc]
 
     def tune_seconds(self) -> float:
         return lib().pdlp_batch_tune_seconds(self._h)

@@ -505,17 +505,18 @@ def test_batched_first_steps_match_oracle():
         assert rel(xs[k], ref.x) <= 1e-11 and rel(ys[k], ref.y) <= 1e-11, k
 
 
-@pytest.mark.parametrize("bs", [64, 128, 256, 512, 1024])
-def test_batched_workgroup_sizes_match_oracle(bs):
-    """Every workgroup size the tuner can pick for a size class: after 40 steps every member's
-    iterate equals the oracle's at the iterate tolerance, and a full solve is certified by the
-    oracle's KKT evaluation.  The members span three size classes."""
+@pytest.mark.parametrize("sched", P.Batch.SCHEDULES)
+def test_batched_schedules_match_oracle(sched):
+    """Every schedule the tuner can pick for a size class (threads per member x rows per thread
+    in flight): after 40 steps every member's iterate equals the oracle's at the iterate
+    tolerance, and a full solve is certified by the oracle's KKT evaluation.  The members span
+    three size classes."""
     members = [lpgen.batched_instance(i) for i in (0, 2, 6, 9)] + \
               [lpgen.add_empty_row_and_column(lpgen.tiny_plain(3, 60, 150, 20, 4))]
-    say("batch workgroup size", bs, [lp.nnz for lp in members])
+    say("batch schedule", sched, [lp.nnz for lp in members])
     b = P.Batch(members)
-    b.set_block_sizes([bs] * P.Batch.BATCH_CLASSES)
-    assert b.schedule()[0] == [bs] * P.Batch.BATCH_CLASSES
+    b.set_schedule([sched] * P.Batch.BATCH_CLASSES)
+    assert b.schedule()[0] == [sched] * P.Batch.BATCH_CLASSES
     assert sum(b.schedule()[1]) == len(members)
     b.solve(1e-30, 40)
     xs, ys, st, it, _ = b.get()
@@ -532,13 +533,14 @@ def test_batched_workgroup_sizes_match_oracle(bs):
 
 
 def test_batched_tune_then_solve_repeats_bitwise():
-    """The tuner's choice is one of the sizes, its timing runs leave no solve behind, and two
-    solves of the same batch give bit-identical points."""
+    """The tuner's choice is one of the schedules, its timing runs leave no solve behind, and
+    two solves of the same batch give bit-identical points, also under another schedule
+    (every schedule sums each row in the same order)."""
     members = [lpgen.batched_instance(i) for i in range(12)]
     say("batch tune")
     b = P.Batch(members)
-    sizes = b.tune(30)
-    assert all(v in (64, 128, 256, 512, 1024) for v in sizes) and b.schedule()[0] == sizes
+    sched = b.tune(30)
+    assert all(q in P.Batch.SCHEDULES for q in sched) and b.schedule()[0] == sched
     with pytest.raises(P.PdlpError):
         b.get()
     b.solve(1e-8, 3000)
@@ -548,6 +550,15 @@ def test_batched_tune_then_solve_repeats_bitwise():
     for k in range(len(members)):
         assert np.array_equal(x1[k], x2[k]) and np.array_equal(y1[k], y2[k])
     assert np.array_equal(it1, it2) and np.array_equal(k1, k2)
+    for t in (128, 256, 512):                  # the same threads with 1 or 2 rows in flight
+        pts = []
+        for rows in (1, 2):
+            b.set_schedule([(t, rows)] * P.Batch.BATCH_CLASSES)
+            b.solve(1e-8, 3000)
+            pts.append(b.get())
+        for k in range(len(members)):
+            assert np.array_equal(pts[0][0][k], pts[1][0][k]) and np.array_equal(pts[0][1][k], pts[1][1][k])
+        assert np.array_equal(pts[0][3], pts[1][3])
 
 
 def test_batched_rejects_bad_member():
