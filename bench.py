@@ -557,6 +557,14 @@ def summarize_profile(d):
                 cal[cnt] = float(np.median(vals))
     nbytes = 1 << 30
     scale = {c: (nbytes / (cal[c] * 1024.0) if cal.get(c) else None) for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    bl = os.path.join(d, "bench_trace.json")
+    if os.path.exists(bl):
+        with open(bl) as fh:
+            line = [ln for ln in fh if ln.startswith("{")][-1]
+        bj = json.loads(line)
+        print("   bench.py line of the traced run: " + f"{bj['value']:.1f} iters/s; HIP-event averages of the passes "
+              "that ran (us): " + ", ".join(f"{k} {v['avg_us']:.1f}" for k, v in bj["passes"].items()))
+        print()
     print("2. Counter calibration: a 1 GiB device copy (1 GiB read, 1 GiB written) gives "
           + ", ".join(f"{c} {cal.get(c, float('nan')):.0f} KiB" for c in ("FETCH_SIZE", "WRITE_SIZE"))
           + " per dispatch,")

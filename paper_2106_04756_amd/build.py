@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdlp_hip.so")
 
 SOURCES = ["pdlp_solver.hip", "host_prep.cpp"]
-HEADERS = ["pdlp_kernels.hip", "pdlp_batch.hip", "pdlp_unroll.hip", "pdlp_device.h", "pdlp_internal.h",
+HEADERS = ["pdlp_kernels.hip", "pdlp_batch.hip", "pdlp_batch_host.hip", "pdlp_unroll.hip", "pdlp_device.h", "pdlp_internal.h",
            "host_prep.h"]
 
 FLAGS = [
