@@ -47,7 +47,10 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "pdlp_step_passes_large_plain_lp.txt")
+# rocprofv3 summaries of the step passes per workload (bench.py --summarize-profile)
+PROFILES = {"large": os.path.join(ROOT, "profiles", "pdlp_step_passes_large_plain_lp.txt"),
+            "truncated": os.path.join(ROOT, "profiles", "pdlp_step_passes_truncated_large_lp.txt"),
+            "pagerank": os.path.join(ROOT, "profiles", "pdlp_step_passes_pagerank_5m.txt")}
 
 # Sources that define the timed step kernels and their launches (the batched solver and the
 # unrolled adjoint live in files of their own and do not take part in the timed step).
@@ -86,12 +89,12 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def profiled_bytes():
-    """HBM bytes per product dispatch of each step kernel on the large plain LP, from the
-    rocprofv3 byte counters in the committed profile summary; None when the summary was taken
-    on other kernel sources."""
+def profiled_bytes(which="large"):
+    """HBM bytes per product dispatch of each step kernel on one workload, from the rocprofv3
+    byte counters in its committed profile summary; None when the summary was taken on other
+    kernel sources."""
     try:
-        with open(PROFILE) as fh:
+        with open(PROFILES[which]) as fh:
             for line in fh:
                 if line.startswith("bench-traffic: "):
                     d = json.loads(line[len("bench-traffic: "):])
@@ -209,6 +212,9 @@ def measure_lp(P, torch, lp, W, K, tol=1e-8, label="lp"):
         ms = float(tms[j]) / max(launches, 1)
         bpl = alg[name] / max(launches, 1)
         passes[name] = {"avg_us": 1e3 * ms, "launches": launches, "algorithmic_bytes_per_launch": bpl,
+                        "algorithmic_bytes_per_product": pb[name] + (pb[name.replace("combine", "pass1")]
+                                                                     if (name == "primal_combine" and plain_T)
+                                                                     or (name == "dual_combine" and plain_K) else 0.0),
                         "achieved_gbs": bpl / (ms * 1e-3) / 1e9 if ms > 0 else None}
     slots = {}
     for slot, (a, b) in (("primal", ("primal_pass1", "primal_combine")), ("dual", ("dual_pass1", "dual_combine"))):
@@ -255,15 +261,15 @@ def measure_lp(P, torch, lp, W, K, tol=1e-8, label="lp"):
             "layouts": {"K": inf["layout_K"], "KT": inf["layout_KT"]}}
 
 
-def attach_traffic(r, lp):
+def attach_traffic(r, lp, which="large"):
     """roofline.traffic of the dominant pass: the HBM bytes per product dispatch of its kernel
     in the committed profile, scaled to the timed launches (a first pass after a rejected
     attempt returns at once: it moves no matrix); null when the profile was taken on other
     kernel sources or does not cover the kernel."""
-    prof = profiled_bytes()
+    prof = profiled_bytes(which)
     roof = r["roofline"]
-    kern = roof["kernel"].split(":")[0]
-    if not prof or kern not in prof:
+    kern = _match_kernel(roof["kernel"].split(":")[0], prof or {})
+    if not kern:
         return
     name = roof["pass"]
     full = pass_bytes(lp)[name]
@@ -511,6 +517,15 @@ def _short_kernel(name):
     return n
 
 
+def _match_kernel(kern, names):
+    """The profiled kernel name that a PASS_KERNELS entry denotes: 'k_panel_rows<1>' matches
+    'k_panel_rows<1, 8>' (the entry count per lane is a second template argument)."""
+    if kern in names:
+        return kern
+    hits = [k for k in names if kern.endswith(">") and k.startswith(kern[:-1] + ",")]
+    return hits[0] if len(hits) == 1 else None
+
+
 def _read_csv(path):
     import csv
     with open(path, newline="") as fh:
@@ -527,7 +542,16 @@ def summarize_profile(d):
         hits = sorted(glob.glob(os.path.join(d, sub, "**", f"*{suffix}"), recursive=True))
         return hits[0] if hits else None
 
-    print("rocprofv3 profile: PDLP step passes on the large plain LP (m=1e6, n=2e6, nnz=1.354e8), one MI355X")
+    title = "the large plain LP (m=1e6, n=2e6, nnz=1.354e8)"
+    bj0 = {}
+    bl = os.path.join(d, "bench_trace.json")
+    if os.path.exists(bl):
+        with open(bl) as fh:
+            lines = [ln for ln in fh if ln.startswith("{")]
+        if lines:
+            bj0 = json.loads(lines[-1])
+            title = bj0.get("workload") or bj0.get("config", {}).get("workload", title)
+    print(f"rocprofv3 profile: PDLP step passes on {title}, one MI355X")
     print(f"step-kernel sources sha256 {kernel_sources_digest()} (bench.STEP_SOURCES under paper_2106_04756_amd/csrc)")
     print()
     trace = find("trace", "kernel_trace.csv")
@@ -579,6 +603,8 @@ def summarize_profile(d):
             if not r["Counter_Name"].startswith(cnt):
                 continue
             k = _short_kernel(r["Kernel_Name"])
+            if not k.startswith("k_"):
+                continue   # the solver's kernels only (not the copy-rate probe's)
             byk.setdefault(k, {}).setdefault(cnt, []).append(float(r["Counter_Value"]) * 1024.0 * scale[cnt])
     print("3. HBM bytes per dispatch that formed its product (dispatches above 20% of the kernel's largest")
     print("   fetch; the median of those), scaled by the calibration:")
@@ -596,6 +622,37 @@ def summarize_profile(d):
         if fmed + wmed > 1e6:
             print(f"{k:34s} {int(sel.sum()):10d} {fmed / 1e6:9.1f} {wmed / 1e6:9.1f} {(fmed + wmed) / 1e6:9.1f}")
     print()
+    import re
+    sizes = re.search(r"m=(\d+) n=(\d+) nnz=(\d+)", title)
+    if bj0.get("layouts") and sizes:
+        lay = bj0["layouts"]
+
+        class _Sz:
+            m, n, nnz = (int(v) for v in sizes.groups())
+        pb = pass_bytes(_Sz)
+        print("4. The passes of the timed step: HBM bytes per dispatch that formed its product against the")
+        print("   algorithmic bytes of one product (bench.pass_bytes), and the kernel's average duration here")
+        print(f"{'pass':16s} {'kernel':22s} {'measured_MB':>12s} {'algorithmic_MB':>15s} {'ratio':>6s} {'trace_us':>9s}")
+        for name, v in bj0.get("passes", {}).items():
+            lk = lay.get("KT" if name.startswith("primal") else "K", 0)
+            kern = _match_kernel(PASS_KERNELS[name].get(lk, ""), per_dispatch)
+            if not kern:
+                continue
+            alg = pb[name]
+            if (name == "primal_combine" and lay.get("KT") == 0) or (name == "dual_combine" and lay.get("K") == 0):
+                alg += pb[name.replace("combine", "pass1")]
+            tr = per.get(kern) if trace else None
+            tr_us = float(np.mean([t for t in tr if t > 0.2 * max(tr)])) if tr else float("nan")
+            print(f"{name:16s} {kern:22s} {per_dispatch[kern] / 1e6:12.1f} {alg / 1e6:15.1f} "
+                  f"{per_dispatch[kern] / alg:6.2f} {tr_us:9.1f}")
+        print()
+    cmd = os.path.join(d, "commands.txt")
+    if os.path.exists(cmd):
+        print("Commands (repository root R on the GPU host; `cd /tmp && export TMPDIR=/tmp` first):")
+        with open(cmd) as fh:
+            for ln in fh:
+                print("  " + ln.rstrip())
+        print()
     print("bench-traffic: " + json.dumps({"sources_sha256": kernel_sources_digest(),
                                          "bytes_per_dispatch": {k: round(v) for k, v in per_dispatch.items()
                                                                 if v > 1e6}}))
@@ -616,6 +673,9 @@ def main():
     ap.add_argument("--no-policies", action="store_true", help="skip the other step policies")
     ap.add_argument("--no-ablations", action="store_true", help="skip the ablation switches")
     ap.add_argument("--only-large", action="store_true", help="only the large plain LP (profiling runs)")
+    ap.add_argument("--only-lp", choices=["truncated", "pagerank"],
+                    help="only the truncated large LP or the PageRank LP, headline windows as for the "
+                         "large LP (profiling runs; the JSON line carries that LP's figures)")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-iter-limit", type=int, default=100000)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -641,6 +701,15 @@ def main():
     from workloads import lpgen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_lp:
+        t = time.time()
+        lpo = lpgen.large_lp_truncated(args.seed) if args.only_lp == "truncated" else lpgen.pagerank_5m()
+        log(f"generated {lpo.name}: nnz={lpo.nnz} in {time.time() - t:.1f}s")
+        ro = measure_lp(P, torch, lpo, args.warmup, args.steps, label=args.only_lp)
+        attach_traffic(ro, lpo, args.only_lp)
+        print(json.dumps({"workload": f"{lpo.name}, m={lpo.m} n={lpo.n} nnz={lpo.nnz}", "value": ro["iters_per_s"],
+                          "steps": args.steps, "warmup": args.warmup, **ro}), flush=True)
+        return
     t = time.time()
     lp = lpgen.large_lp(args.seed)
     log(f"generated {lp.name}: m={lp.m} n={lp.n} nnz={lp.nnz} in {time.time() - t:.1f}s")
@@ -676,11 +745,13 @@ def main():
         "slots": r["slots"],
         "step_gbs_algorithmic": r["step_gbs_algorithmic"],
         "create_seconds": r["create_seconds"],
+        "layouts": r["layouts"],
     }
     if not args.no_truncated:
         lpb = lpgen.large_lp_truncated(args.seed)
         log(f"generated {lpb.name}: nnz={lpb.nnz}")
         rb = measure_lp(P, torch, lpb, W, K, label="truncated LP")
+        attach_traffic(rb, lpb, "truncated")
         out["large_lp_truncated"] = {
             "workload": f"large plain LP m={lpb.m} n={lpb.n} nnz={lpb.nnz} (Zipf(1.5) column "
                         f"counts truncated to [1,190]), seed {args.seed}", **rb}
@@ -689,6 +760,7 @@ def main():
         lpr = lpgen.pagerank_5m()
         log(f"generated {lpr.name}: nnz={lpr.nnz} in {time.time() - t:.1f}s")
         rp = measure_lp(P, torch, lpr, W, K, label="PageRank LP")
+        attach_traffic(rp, lpr, "pagerank")
         out["pagerank_5m"] = {"workload": f"{lpr.name}, m={lpr.m} n={lpr.n} nnz={lpr.nnz}", **rp}
         del lpr
     # the tiny plain LP (launch-bound regime): wall time of a whole solve to KKT 1e-8
