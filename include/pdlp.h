@@ -219,6 +219,13 @@ void pdlp_destroy(pdlp_solver *s);
  * NULL).  Owned by the library, valid until the next call on s. */
 const char *pdlp_last_error(const pdlp_solver *s);
 
+/* pdlp_set_host_threads - host threads of the preparation work of the next pdlp_create calls
+ * in this process (transpose, column order, panel layouts, interleaved entries): n >= 1, or 0
+ * for the default (the hardware threads, at most 16).  The prepared data, and so every result,
+ * are the same for any n.  Returns the count now in effect.  Not for calls that overlap a
+ * pdlp_create on another thread. */
+int pdlp_set_host_threads(int n);
+
 /* ---- batched solve: many independent LPs in one launch ----------------------------------- */
 
 typedef struct pdlp_batch pdlp_batch;

@@ -2,10 +2,14 @@
 // CSR copy of K (deterministic counting sort, so no value atomics are ever needed on the
 // device) and the row-block schedule that load-balances the CSR products.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <exception>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/pdlp.h"
@@ -15,6 +19,23 @@
 namespace pdlp {
 
 namespace {
+
+std::atomic<int> g_host_threads{0};
+
+// Matrices below this many nonzeros are prepared on one thread.
+constexpr int64_t kParallelNnz = int64_t(1) << 20;
+
+// Stable sort of ids by key(id) in [0, kmax]: a counting sort, which gives the order of a
+// stable comparison sort in linear time.
+template <class Id, class Key>
+void counting_sort_by(std::vector<Id>& ids, int64_t kmax, Key key) {
+  std::vector<int64_t> cnt(size_t(kmax) + 2, 0);
+  for (const Id& x : ids) cnt[size_t(key(x)) + 1]++;
+  for (size_t i = 1; i < cnt.size(); ++i) cnt[i] += cnt[i - 1];
+  std::vector<Id> out(ids.size());
+  for (const Id& x : ids) out[size_t(cnt[size_t(key(x))]++)] = x;
+  ids.swap(out);
+}
 
 // smallest p (p <= 6) with len <= emax * 2^p
 int lanes_log2_for(int64_t len, int emax = kElemsPerLane) {
@@ -30,6 +51,62 @@ int32_t entries_per_lane(int64_t maxlen, int p, int emax = kElemsPerLane) {
 }
 
 }  // namespace
+
+int host_threads() {
+  const int n = g_host_threads.load();
+  if (n > 0) return n;
+  const unsigned hw = std::thread::hardware_concurrency();
+  return int(std::max(1u, std::min(16u, hw)));
+}
+
+void set_host_threads(int n) { g_host_threads.store(std::max(0, n)); }
+
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f, int64_t min_chunk) {
+  if (n <= 0) return;
+  const int64_t T = std::max<int64_t>(1, std::min<int64_t>(host_threads(), (n + std::max<int64_t>(min_chunk, 1) - 1) /
+                                                                                std::max<int64_t>(min_chunk, 1)));
+  if (T == 1) {
+    f(0, n);
+    return;
+  }
+  std::exception_ptr err;
+  std::mutex mu;
+  auto run = [&](int64_t t) {
+    try {
+      f(n * t / T, n * (t + 1) / T);
+    } catch (...) {
+      std::lock_guard<std::mutex> g(mu);
+      if (!err) err = std::current_exception();
+    }
+  };
+  std::vector<std::thread> th;
+  th.reserve(size_t(T - 1));
+  try {
+    for (int64_t t = 1; t < T; ++t) th.emplace_back(run, t);
+  } catch (...) {
+    // no more threads: this thread runs the chunks that have none
+    for (int64_t t = int64_t(th.size()) + 1; t < T; ++t) run(t);
+  }
+  run(0);
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
+
+std::vector<int64_t> column_counts(const int32_t* ci, int64_t nnz, int64_t ncols) {
+  std::vector<int64_t> cnt(size_t(std::max<int64_t>(ncols, 0)), 0);
+  const int64_t T = nnz < kParallelNnz ? 1 : host_threads();
+  // thread t counts the columns of its range over all nonzeros
+  parallel_for(T, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t c0 = ncols * t / T, c1 = ncols * (t + 1) / T;
+      for (int64_t e = 0; e < nnz; ++e) {
+        const int64_t j = ci[e];
+        if (j >= c0 && j < c1) cnt[size_t(j)]++;
+      }
+    }
+  }, 1);
+  return cnt;
+}
 
 Schedule build_schedule(const int64_t* rp, int64_t nrows) {
   Schedule s;
@@ -60,9 +137,7 @@ Schedule build_schedule(const int64_t* rp, int64_t nrows) {
     std::vector<int32_t>& b = bins[size_t(p)];
     // rows of one lane class ordered by length, so a task's rows need about the same number of
     // entries per lane
-    std::stable_sort(b.begin(), b.end(), [&](int32_t x, int32_t y) {
-      return rp[x + 1] - rp[x] < rp[y + 1] - rp[y];
-    });
+    counting_sort_by(b, kWaveMaxLen, [&](int32_t x) { return rp[x + 1] - rp[x]; });
     const int32_t per_task = int32_t((64 >> p) * rounds);
     for (size_t off = 0; off < b.size(); off += size_t(per_task)) {
       const int32_t cnt = int32_t(std::min<size_t>(size_t(per_task), b.size() - off));
@@ -79,27 +154,12 @@ Schedule build_schedule(const int64_t* rp, int64_t nrows) {
   return s;
 }
 
-namespace {
-
-// Appends wavefront tasks for the panel rows [k0, k1) (all of one lane class `lg`, ordered by
-// length) with offsets prow_ptr.
-void push_wave_tasks(Schedule& s, const std::vector<int64_t>& prow_ptr, int64_t k0, int64_t k1, int lg,
-                     int emax) {
-  const int64_t per_task = int64_t((64 >> lg) * kRounds);
-  for (int64_t off = k0; off < k1; off += per_task) {
-    const int32_t cnt = int32_t(std::min<int64_t>(per_task, k1 - off));
-    int64_t maxlen = 0;
-    for (int64_t k = off; k < off + cnt; ++k) maxlen = std::max(maxlen, prow_ptr[size_t(k) + 1] - prow_ptr[size_t(k)]);
-    s.wave.push_back(RowDesc{int32_t(off), cnt, int32_t(kWaveRows | (lg << 8)), entries_per_lane(maxlen, lg, emax)});
-  }
-}
-
-}  // namespace
-
 std::vector<int32_t> panel_cuts(const int32_t* ci, int64_t nnz, int64_t ncols, int P) {
   std::vector<int64_t> colcnt(size_t(ncols) + 1, 0);
-  for (int64_t e = 0; e < nnz; ++e) colcnt[size_t(ci[e]) + 1]++;
-  for (int64_t j = 0; j < ncols; ++j) colcnt[size_t(j) + 1] += colcnt[size_t(j)];
+  {
+    const std::vector<int64_t> cnt = column_counts(ci, nnz, ncols);
+    for (int64_t j = 0; j < ncols; ++j) colcnt[size_t(j) + 1] = colcnt[size_t(j)] + cnt[size_t(j)];
+  }
   std::vector<int32_t> cut(size_t(P) + 1, int32_t(ncols));
   cut[0] = 0;
   for (int p = 1; p < P; ++p) {
@@ -113,13 +173,14 @@ std::vector<int32_t> panel_cuts(const int32_t* ci, int64_t nnz, int64_t ncols, i
 std::vector<int32_t> hot_column_order(const int32_t* ci, int64_t nnz, int64_t ncols,
                                       const std::vector<int32_t>& cut) {
   const int P = int(cut.size()) - 1;
-  std::vector<int64_t> cnt(size_t(ncols), 0);
-  for (int64_t e = 0; e < nnz; ++e) cnt[size_t(ci[e])]++;
+  const std::vector<int64_t> cnt = column_counts(ci, nnz, ncols);
   std::vector<int32_t> order(static_cast<size_t>(ncols));
   for (int64_t j = 0; j < ncols; ++j) order[size_t(j)] = int32_t(j);
-  for (int p = 0; p < P; ++p)
-    std::stable_sort(order.begin() + cut[size_t(p)], order.begin() + cut[size_t(p) + 1],
-                     [&](int32_t a, int32_t b) { return cnt[size_t(a)] > cnt[size_t(b)]; });
+  parallel_for(P, [&](int64_t p0, int64_t p1) {
+    for (int64_t p = p0; p < p1; ++p)
+      std::stable_sort(order.begin() + cut[size_t(p)], order.begin() + cut[size_t(p) + 1],
+                       [&](int32_t a, int32_t b) { return cnt[size_t(a)] > cnt[size_t(b)]; });
+  }, 1);
   return order;
 }
 
@@ -141,121 +202,193 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
   };
   // Row segments: the panel rows of row r are segments sp[r] .. sp[r + 1], in panel order,
   // with their panel and length (a sparse form of the rows x panels length table).
+  // (rows in parallel chunks; each writes only its own rows' entries)
+  const int64_t row_chunk = nnz < kParallelNnz ? std::max<int64_t>(nrows, 1) : int64_t(1) << 14;
   std::vector<int64_t> sp(size_t(nrows) + 1, 0);
-  for (int64_t r = 0; r < nrows; ++r) {
-    int64_t cntr = 0, run = 0;
-    int p = -1;
-    for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
-      int q = p < 0 ? 0 : p;
-      while (ci[e] >= cut[size_t(q) + 1]) ++q;
-      if (q != p) {
-        if (p >= 0) cntr += pieces(run);
-        p = q;
-        run = 0;
+  parallel_for(nrows, [&](int64_t r0, int64_t r1) {
+    for (int64_t r = r0; r < r1; ++r) {
+      int64_t cntr = 0, run = 0;
+      int p = -1;
+      for (int64_t e = rp[r]; e < rp[r + 1]; ++e) {
+        int q = p < 0 ? 0 : p;
+        while (ci[e] >= cut[size_t(q) + 1]) ++q;
+        if (q != p) {
+          if (p >= 0) cntr += pieces(run);
+          p = q;
+          run = 0;
+        }
+        ++run;
       }
-      ++run;
+      if (p >= 0) cntr += pieces(run);
+      sp[size_t(r) + 1] = cntr;
     }
-    if (p >= 0) cntr += pieces(run);
-    sp[size_t(r) + 1] = sp[size_t(r)] + cntr;
-  }
+  }, row_chunk);
+  for (int64_t r = 0; r < nrows; ++r) sp[size_t(r) + 1] += sp[size_t(r)];
   const int64_t nprow = sp[size_t(nrows)];
   if (double(nprow) > max_prow_frac * double(std::max<int64_t>(nnz, 1))) return false;
   std::vector<int32_t> seg_p(static_cast<size_t>(nprow)), seg_len(static_cast<size_t>(nprow));
-  for (int64_t r = 0; r < nrows; ++r) {
-    int64_t k = sp[size_t(r)];
-    int64_t e = rp[r];
-    int q = 0;
-    while (e < rp[r + 1]) {
-      // the run of panel q starting at e, then its pieces
-      while (ci[e] >= cut[size_t(q) + 1]) ++q;
-      int64_t e1 = e + 1;
-      while (e1 < rp[r + 1] && ci[e1] < cut[size_t(q) + 1]) ++e1;
-      const int64_t np = pieces(e1 - e);
-      for (int64_t i = 0; i < np; ++i) {
-        const int64_t a = e + i * kWaveMaxLen;
-        seg_p[size_t(k)] = q;
-        seg_len[size_t(k)] = int32_t(np > 1 ? std::min<int64_t>(kWaveMaxLen, e1 - a) : e1 - e);
-        ++k;
+  std::vector<int32_t> seg_row(static_cast<size_t>(nprow));
+  parallel_for(nrows, [&](int64_t r0, int64_t r1) {
+    for (int64_t r = r0; r < r1; ++r) {
+      int64_t k = sp[size_t(r)];
+      int64_t e = rp[r];
+      int q = 0;
+      while (e < rp[r + 1]) {
+        // the run of panel q starting at e, then its pieces
+        while (ci[e] >= cut[size_t(q) + 1]) ++q;
+        int64_t e1 = e + 1;
+        while (e1 < rp[r + 1] && ci[e1] < cut[size_t(q) + 1]) ++e1;
+        const int64_t np = pieces(e1 - e);
+        for (int64_t i = 0; i < np; ++i) {
+          const int64_t a = e + i * kWaveMaxLen;
+          seg_p[size_t(k)] = q;
+          seg_len[size_t(k)] = int32_t(np > 1 ? std::min<int64_t>(kWaveMaxLen, e1 - a) : e1 - e);
+          seg_row[size_t(k)] = int32_t(r);
+          ++k;
+        }
+        e = e1;
       }
-      e = e1;
     }
-  }
+  }, row_chunk);
   // segments of each panel in row order (counting sort by panel)
   std::vector<int64_t> pp(size_t(P) + 1, 0);
   for (int64_t k = 0; k < nprow; ++k) pp[size_t(seg_p[size_t(k)]) + 1]++;
   for (int p = 0; p < P; ++p) pp[size_t(p) + 1] += pp[size_t(p)];
   std::vector<int64_t> by_panel(static_cast<size_t>(nprow)), fill(pp.begin(), pp.end() - 1);
-  std::vector<int32_t> seg_row(static_cast<size_t>(nprow));
-  for (int64_t r = 0; r < nrows; ++r)
-    for (int64_t k = sp[size_t(r)]; k < sp[size_t(r) + 1]; ++k) {
-      seg_row[size_t(k)] = int32_t(r);
-      by_panel[size_t(fill[size_t(seg_p[size_t(k)])]++)] = k;
-    }
+  for (int64_t k = 0; k < nprow; ++k) by_panel[size_t(fill[size_t(seg_p[size_t(k)])]++)] = k;
   // order panel rows: panel, then lane class (wavefront rows by p, then long rows), then
-  // length (wavefront classes), then row
-  L.prow_ptr.reserve(size_t(nprow) + 1);
-  L.prow_ptr.push_back(0);
-  L.prow_row.reserve(size_t(nprow));
-  std::vector<int32_t> prow_of(static_cast<size_t>(nprow), -1);   // panel row id of each segment
-  L.wave_begin.push_back(0);
-  L.block_begin.push_back(0);
-  Schedule& S = L.sched;
-  std::vector<int64_t> cls_segs[8];
-  for (int p = 0; p < P; ++p) {
-    for (auto& v : cls_segs) v.clear();
-    for (int64_t i = pp[size_t(p)]; i < pp[size_t(p) + 1]; ++i) {
-      const int64_t k = by_panel[size_t(i)];
-      const int64_t len = seg_len[size_t(k)];
-      cls_segs[(len <= kWaveMaxLen) ? lanes_log2_for(len, emax) : 7].push_back(k);
-    }
-    for (int cls = 0; cls <= 7; ++cls) {           // 0..6 lane classes, 7 = long rows
-      const int64_t k0 = int64_t(L.prow_row.size());
-      std::vector<int64_t>& segs = cls_segs[cls];
-      if (cls < 7)
-        std::stable_sort(segs.begin(), segs.end(), [&](int64_t x, int64_t y) {
-          return seg_len[size_t(x)] < seg_len[size_t(y)];
-        });
-      for (const int64_t k : segs) {
+  // length (wavefront classes), then row.  Each panel is ordered and gets its tasks on its own
+  // (panels in parallel, indices relative to the panel), then placed at its offsets.
+  struct Part {
+    std::vector<int64_t> order;        // the panel's segments in panel-row order
+    int64_t nnz = 0;
+    std::vector<RowDesc> wave, block;  // .a relative to the panel's first panel row
+    std::vector<int32_t> split_prow;   // relative panel row and chunk count of each split row
+    std::vector<int32_t> split_nch;
+    int64_t nchunks = 0;
+  };
+  std::vector<Part> part(static_cast<size_t>(P));
+  parallel_for(P, [&](int64_t p0, int64_t p1) {
+    std::vector<int64_t> cls_segs[8];
+    for (int64_t p = p0; p < p1; ++p) {
+      Part& W = part[size_t(p)];
+      for (auto& v : cls_segs) v.clear();
+      for (int64_t i = pp[size_t(p)]; i < pp[size_t(p) + 1]; ++i) {
+        const int64_t k = by_panel[size_t(i)];
         const int64_t len = seg_len[size_t(k)];
-        prow_of[size_t(k)] = int32_t(L.prow_row.size());
-        L.prow_row.push_back(seg_row[size_t(k)]);
-        L.prow_ptr.push_back(L.prow_ptr.back() + len);
-        if (cls == 7) {
-          const int32_t kk = int32_t(L.prow_row.size() - 1);
-          if (len <= kVectorMax) {
-            S.block.push_back(RowDesc{kk, 0, kVector, 0});
-          } else {
-            const int32_t id = int32_t(S.split_row.size());
-            const int32_t nch = int32_t((len + kChunk - 1) / kChunk);
-            S.split_row.push_back(kk);
-            S.split_nchunks.push_back(nch);
-            S.split_base.push_back(int32_t(S.total_chunks));
-            S.total_chunks += nch;
-            for (int32_t cc = 0; cc < nch; ++cc) S.block.push_back(RowDesc{kk, cc, kSplit, id});
+        cls_segs[(len <= kWaveMaxLen) ? lanes_log2_for(len, emax) : 7].push_back(k);
+      }
+      W.order.reserve(size_t(pp[size_t(p) + 1] - pp[size_t(p)]));
+      for (int cls = 0; cls <= 7; ++cls) {           // 0..6 lane classes, 7 = long rows
+        std::vector<int64_t>& segs = cls_segs[cls];
+        const int32_t k0 = int32_t(W.order.size());
+        if (cls < 7) counting_sort_by(segs, kWaveMaxLen, [&](int64_t x) { return seg_len[size_t(x)]; });
+        for (const int64_t k : segs) {
+          const int64_t len = seg_len[size_t(k)];
+          const int32_t kk = int32_t(W.order.size());
+          W.order.push_back(k);
+          W.nnz += len;
+          if (cls == 7) {
+            if (len <= kVectorMax) {
+              W.block.push_back(RowDesc{kk, 0, kVector, 0});
+            } else {
+              const int32_t id = int32_t(W.split_prow.size());
+              const int32_t nch = int32_t((len + kChunk - 1) / kChunk);
+              W.split_prow.push_back(kk);
+              W.split_nch.push_back(nch);
+              W.nchunks += nch;
+              for (int32_t cc = 0; cc < nch; ++cc) W.block.push_back(RowDesc{kk, cc, kSplit, id});
+            }
+          }
+        }
+        if (cls < 7) {
+          // wavefront tasks of (64 >> cls) * kRounds rows of this lane class
+          const int32_t k1 = int32_t(W.order.size());
+          const int32_t per_task = int32_t((64 >> cls) * kRounds);
+          for (int32_t off = k0; off < k1; off += per_task) {
+            const int32_t cnt = std::min(per_task, k1 - off);
+            int64_t maxlen = 0;
+            for (int32_t i = off; i < off + cnt; ++i) maxlen = std::max<int64_t>(maxlen, seg_len[size_t(W.order[size_t(i)])]);
+            W.wave.push_back(RowDesc{off, cnt, int32_t(kWaveRows | (cls << 8)), entries_per_lane(maxlen, cls, emax)});
           }
         }
       }
-      if (cls < 7) push_wave_tasks(S, L.prow_ptr, k0, int64_t(L.prow_row.size()), cls, emax);
     }
-    L.wave_begin.push_back(int32_t(S.wave.size()));
-    L.block_begin.push_back(int32_t(S.block.size()));
+  }, 1);
+  // offsets of each panel's panel rows, entries, tasks and split rows
+  std::vector<int64_t> prow_base(size_t(P) + 1, 0), nnz_base(size_t(P) + 1, 0), split_id_base(size_t(P) + 1, 0),
+      chunk_base(size_t(P) + 1, 0);
+  Schedule& S = L.sched;
+  L.wave_begin.assign(size_t(P) + 1, 0);
+  L.block_begin.assign(size_t(P) + 1, 0);
+  for (int p = 0; p < P; ++p) {
+    const Part& W = part[size_t(p)];
+    prow_base[size_t(p) + 1] = prow_base[size_t(p)] + int64_t(W.order.size());
+    nnz_base[size_t(p) + 1] = nnz_base[size_t(p)] + W.nnz;
+    split_id_base[size_t(p) + 1] = split_id_base[size_t(p)] + int64_t(W.split_prow.size());
+    chunk_base[size_t(p) + 1] = chunk_base[size_t(p)] + W.nchunks;
+    L.wave_begin[size_t(p) + 1] = L.wave_begin[size_t(p)] + int32_t(W.wave.size());
+    L.block_begin[size_t(p) + 1] = L.block_begin[size_t(p)] + int32_t(W.block.size());
   }
-  // source index of every panel-ordered nonzero, and each row's panel rows in panel order
+  L.prow_ptr.assign(size_t(nprow) + 1, 0);
+  L.prow_row.resize(size_t(nprow));
+  std::vector<int32_t> prow_of(static_cast<size_t>(nprow));     // panel row id of each segment
+  S.wave.resize(size_t(L.wave_begin[size_t(P)]));
+  S.block.resize(size_t(L.block_begin[size_t(P)]));
+  S.split_row.resize(size_t(split_id_base[size_t(P)]));
+  S.split_nchunks.resize(size_t(split_id_base[size_t(P)]));
+  S.split_base.resize(size_t(split_id_base[size_t(P)]));
+  S.total_chunks = chunk_base[size_t(P)];
+  parallel_for(P, [&](int64_t p0, int64_t p1) {
+    for (int64_t p = p0; p < p1; ++p) {
+      Part& W = part[size_t(p)];
+      const int64_t pb = prow_base[size_t(p)];
+      int64_t e = nnz_base[size_t(p)];
+      for (size_t i = 0; i < W.order.size(); ++i) {
+        const int64_t k = W.order[i];
+        prow_of[size_t(k)] = int32_t(pb + int64_t(i));
+        L.prow_row[size_t(pb) + i] = seg_row[size_t(k)];
+        e += seg_len[size_t(k)];
+        L.prow_ptr[size_t(pb) + i + 1] = e;
+      }
+      for (size_t t = 0; t < W.wave.size(); ++t) {
+        RowDesc D = W.wave[t];
+        D.a += int32_t(pb);
+        S.wave[size_t(L.wave_begin[size_t(p)]) + t] = D;
+      }
+      for (size_t t = 0; t < W.block.size(); ++t) {
+        RowDesc D = W.block[t];
+        D.a += int32_t(pb);
+        if (D.kind_l == kSplit) D.aux += int32_t(split_id_base[size_t(p)]);
+        S.block[size_t(L.block_begin[size_t(p)]) + t] = D;
+      }
+      int64_t cb = chunk_base[size_t(p)];
+      for (size_t j = 0; j < W.split_prow.size(); ++j) {
+        const size_t id = size_t(split_id_base[size_t(p)]) + j;
+        S.split_row[id] = int32_t(pb) + W.split_prow[j];
+        S.split_nchunks[id] = W.split_nch[j];
+        S.split_base[id] = int32_t(cb);
+        cb += W.split_nch[j];
+      }
+      std::vector<int64_t>().swap(W.order);
+    }
+  }, 1);
+  // source index of every panel-ordered nonzero, and each row's panel rows in panel order (the
+  // segments of row r, sp[r] .. sp[r + 1], are its panel rows)
   L.src.resize(size_t(nnz));
-  L.slot_ptr.assign(size_t(nrows) + 1, 0);
-  L.slot_idx.reserve(size_t(nprow));
-  for (int64_t r = 0; r < nrows; ++r) {
-    int64_t e = rp[r];
-    for (int64_t k = sp[size_t(r)]; k < sp[size_t(r) + 1]; ++k) {
-      const int32_t len = seg_len[size_t(k)];
-      const int32_t id = prow_of[size_t(k)];
-      const int64_t dst = L.prow_ptr[size_t(id)];
-      for (int32_t t = 0; t < len; ++t) L.src[size_t(dst + t)] = e + t;
-      e += len;
-      L.slot_idx.push_back(id);
+  L.slot_ptr = sp;
+  L.slot_idx = prow_of;
+  parallel_for(nrows, [&](int64_t r0, int64_t r1) {
+    for (int64_t r = r0; r < r1; ++r) {
+      int64_t e = rp[r];
+      for (int64_t k = sp[size_t(r)]; k < sp[size_t(r) + 1]; ++k) {
+        const int32_t len = seg_len[size_t(k)];
+        const int64_t dst = L.prow_ptr[size_t(prow_of[size_t(k)])];
+        for (int32_t t = 0; t < len; ++t) L.src[size_t(dst + t)] = e + t;
+        e += len;
+      }
     }
-    L.slot_ptr[size_t(r) + 1] = int64_t(L.slot_idx.size());
-  }
+  }, row_chunk);
   return true;
 }
 
@@ -273,7 +406,8 @@ void build_interleaved(const Schedule& S, const int64_t* rp, const int32_t* ci, 
   }
   cis.assign(size_t(off[nt]), 0);
   vs.assign(size_t(off[nt]), 0.0);
-  for (size_t t = 0; t < nt; ++t) {
+  // tasks in parallel chunks (each task owns its slots off[t] .. off[t + 1])
+  auto fill_task = [&](size_t t) {
     const RowDesc& D = S.wave[t];
     const int lg = D.kind_l >> 8, L = 1 << lg, E = D.aux;
     const int per_round = 64 >> lg;
@@ -300,7 +434,10 @@ void build_interleaved(const Schedule& S, const int64_t* rp, const int32_t* ci, 
         }
       }
     }
-  }
+  };
+  parallel_for(int64_t(nt), [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) fill_task(size_t(t));
+  }, off[nt] < kParallelNnz ? std::max<int64_t>(int64_t(nt), 1) : 1024);
 }
 
 std::vector<int32_t> lds_segments(const PanelLayout& L, int G, bool aligned, std::vector<LdsSeg>& seg) {
@@ -374,16 +511,33 @@ void transpose_csr(int64_t m, int64_t n, const int64_t* rp, const int32_t* ci, c
   rpT.assign(size_t(n) + 1, 0);
   ciT.resize(size_t(nnz));
   vT.resize(size_t(nnz));
-  for (int64_t e = 0; e < nnz; ++e) rpT[size_t(ci[e]) + 1]++;
-  for (int64_t j = 0; j < n; ++j) rpT[j + 1] += rpT[j];
-  std::vector<int64_t> pos(rpT.begin(), rpT.end() - 1);
-  for (int64_t i = 0; i < m; ++i) {
-    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-      const int64_t p = pos[ci[e]]++;
-      ciT[size_t(p)] = int32_t(i);
-      vT[size_t(p)] = v[e];
-    }
+  {
+    const std::vector<int64_t> cnt = column_counts(ci, nnz, n);
+    for (int64_t j = 0; j < n; ++j) rpT[size_t(j) + 1] = rpT[size_t(j)] + cnt[size_t(j)];
   }
+  // thread t fills the transposed rows (columns of K) of a range holding about nnz / T
+  // entries, scanning the rows of K in order, so each transposed row keeps increasing rows
+  const int64_t T = nnz < kParallelNnz ? 1 : host_threads();
+  std::vector<int64_t> cut(size_t(T) + 1, n);
+  cut[0] = 0;
+  for (int64_t t = 1; t < T; ++t)
+    cut[size_t(t)] = std::min(n, std::max(cut[size_t(t) - 1],
+                                          int64_t(std::lower_bound(rpT.begin(), rpT.end(), nnz * t / T) - rpT.begin())));
+  std::vector<int64_t> pos(rpT.begin(), rpT.end() - 1);
+  parallel_for(T, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      const int64_t c0 = cut[size_t(t)], c1 = cut[size_t(t) + 1];
+      if (c0 >= c1) continue;
+      for (int64_t i = 0; i < m; ++i)
+        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+          const int64_t j = ci[e];
+          if (j < c0 || j >= c1) continue;
+          const int64_t p = pos[size_t(j)]++;
+          ciT[size_t(p)] = int32_t(i);
+          vT[size_t(p)] = v[e];
+        }
+    }
+  }, 1);
 }
 
 }  // namespace pdlp
@@ -431,10 +585,12 @@ extern "C" int pdlp_build_panel_layout(const int64_t* row_ptr, const int32_t* co
   const int64_t nnz = row_ptr[nrows];
   std::vector<int32_t> ciP(static_cast<size_t>(nnz));
   std::vector<double> vP(static_cast<size_t>(nnz));
-  for (int64_t k = 0; k < nnz; ++k) {
-    ciP[size_t(k)] = col_idx[L.src[size_t(k)]];
-    vP[size_t(k)] = val[L.src[size_t(k)]];
-  }
+  pdlp::parallel_for(nnz, [&](int64_t k0, int64_t k1) {
+    for (int64_t k = k0; k < k1; ++k) {
+      ciP[size_t(k)] = col_idx[L.src[size_t(k)]];
+      vP[size_t(k)] = val[L.src[size_t(k)]];
+    }
+  }, int64_t(1) << 20);
   std::vector<int64_t> off;
   std::vector<int32_t> cis;
   std::vector<double> vs;

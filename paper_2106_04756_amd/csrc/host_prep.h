@@ -2,10 +2,25 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
 namespace pdlp {
+
+// Host threads of the preparation work in pdlp_create (default: the hardware threads, at most
+// 16).  Every parallel loop below splits its index range into contiguous chunks whose writes
+// are disjoint, so the prepared data do not depend on the thread count.
+int host_threads();
+void set_host_threads(int n);
+
+// f(lo, hi) over contiguous chunks of [0, n) of at least min_chunk indices, on up to
+// host_threads() threads; returns when all are done.  An exception thrown by f is rethrown
+// here (the first one).
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f, int64_t min_chunk = 1 << 15);
+
+// Nonzeros of each column 0..ncols-1 (each thread counts the columns of its own range).
+std::vector<int64_t> column_counts(const int32_t* ci, int64_t nnz, int64_t ncols);
 
 // Returns "" if the LP is well formed, else a description of the first problem found.
 std::string validate_lp(int64_t m, int64_t n, int64_t n_eq, const double* c, const int64_t* rp,

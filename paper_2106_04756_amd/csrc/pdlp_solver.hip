@@ -421,10 +421,12 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
     const int64_t nprow = int64_t(PL.prow_row.size());
     std::vector<int32_t> ciP(static_cast<size_t>(nnz));
     std::vector<double> vP(static_cast<size_t>(nnz));
-    for (int64_t k = 0; k < nnz; ++k) {
-      ciP[size_t(k)] = ci[PL.src[size_t(k)]];
-      vP[size_t(k)] = v[PL.src[size_t(k)]];
-    }
+    parallel_for(nnz, [&](int64_t k0, int64_t k1) {
+      for (int64_t k = k0; k < k1; ++k) {
+        ciP[size_t(k)] = ci[PL.src[size_t(k)]];
+        vP[size_t(k)] = v[PL.src[size_t(k)]];
+      }
+    }, int64_t(1) << 20);
     std::vector<int64_t>().swap(PL.src);
     if ((rc = upload_interleaved(s, PL.sched, PL.prow_ptr.data(), nprow, ciP.data(), vP.data(), nullptr, A, vsdev,
                                  slices ? &PL.cut : nullptr, &PL.wave_begin)))
@@ -889,25 +891,24 @@ int create_impl(pdlp_solver* s, int64_t m, int64_t n, int64_t n_eq, const double
     s->col_user = hot_column_order(ci, nnz, n, cuts);
     s->col_int.assign(size_t(n), 0);
     for (int64_t j = 0; j < n; ++j) s->col_int[size_t(s->col_user[size_t(j)])] = int32_t(j);
+    // each row's entries in the new column order (hot columns of a panel first); the panel of
+    // an entry still never decreases along a row.  Rows in parallel chunks.
     ci_r.resize(static_cast<size_t>(nnz));
-    for (int64_t e = 0; e < nnz; ++e) ci_r[size_t(e)] = s->col_int[size_t(ci[e])];
-    {
-      // each row's entries in the new column order (hot columns of a panel first); the
-      // panel of an entry still never decreases along a row
-      v_r.assign(v, v + nnz);
+    v_r.resize(static_cast<size_t>(nnz));
+    parallel_for(m, [&](int64_t i0, int64_t i1) {
       std::vector<std::pair<int32_t, double>> tmp;
-      for (int64_t i = 0; i < m; ++i) {
+      for (int64_t i = i0; i < i1; ++i) {
         const int64_t a = rp[i], b = rp[i + 1];
         tmp.clear();
-        for (int64_t e = a; e < b; ++e) tmp.emplace_back(ci_r[size_t(e)], v[e]);
+        for (int64_t e = a; e < b; ++e) tmp.emplace_back(s->col_int[size_t(ci[e])], v[e]);
         std::sort(tmp.begin(), tmp.end());
         for (int64_t e = a; e < b; ++e) {
           ci_r[size_t(e)] = tmp[size_t(e - a)].first;
           v_r[size_t(e)] = tmp[size_t(e - a)].second;
         }
       }
-      v = v_r.data();
-    }
+    }, int64_t(1) << 12);
+    v = v_r.data();
     c_r.resize(size_t(n));
     l_r.resize(size_t(n));
     u_r.resize(size_t(n));
@@ -1749,6 +1750,11 @@ int pdlp_kernel_times(const pdlp_solver* s, double* times_ms, int64_t* counts) {
     counts[1] = s->t_cnt[2];
   }
   return 0;
+}
+
+int pdlp_set_host_threads(int n) {
+  pdlp::set_host_threads(n);
+  return pdlp::host_threads();
 }
 
 int pdlp_set_kernel_timing(pdlp_solver* s, int on) {

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "OPTIMAL", 1: "ITERATION_LIMIT", 2: "NUMERICAL_ERROR", 3: "NO
                 -1: "INVALID_ARGUMENT", -2: "OUT_OF_MEMORY", -3: "DEVICE", -4: "INVALID_STATE"}
 
 EXPORTED = ["pdlp_default_options", "pdlp_create", "pdlp_solve", "pdlp_get", "pdlp_get_info",
-            "pdlp_destroy", "pdlp_last_error", "pdlp_get_state", "pdlp_set_state",
+            "pdlp_destroy", "pdlp_last_error", "pdlp_set_host_threads", "pdlp_get_state", "pdlp_set_state",
             "pdlp_get_scaling", "pdlp_get_iterate",
             "pdlp_get_trace", "pdlp_spmv", "pdlp_kernel_times", "pdlp_pass_times", "pdlp_set_kernel_timing",
             "pdlp_reset_kernel_times",
@@ -141,6 +141,8 @@ def lib() -> ctypes.CDLL:
         L.pdlp_pass_times.restype = ctypes.c_int
         L.pdlp_reset_kernel_times.argtypes = [P]
         L.pdlp_reset_kernel_times.restype = ctypes.c_int
+        L.pdlp_set_host_threads.argtypes = [ctypes.c_int]
+        L.pdlp_set_host_threads.restype = ctypes.c_int
         L.pdlp_build_schedule.argtypes = [P, I64, P, I64, P, P, P]
         L.pdlp_build_schedule.restype = ctypes.c_int
         L.pdlp_build_panel_layout.argtypes = [P, P, P, I64, I64, ctypes.c_int32, P, ctypes.c_int32,
@@ -259,6 +261,12 @@ class PanelLayoutC(ctypes.Structure):
                 ("nslots", ctypes.c_int64), ("nseg", ctypes.c_int64)] + \
                [(k, ctypes.c_void_p) for k in ("cut", "prow_ptr", "prow_row", "src", "slot_ptr", "slot_idx",
                                                "wave", "wave_begin", "task_off", "cis", "vs", "seg_ptr", "seg")]
+
+
+def set_host_threads(n: int = 0) -> int:
+    """Host threads of the preparation in the next solver creations (0 = the default); returns
+    the count in effect (pdlp_set_host_threads)."""
+    return int(lib().pdlp_set_host_threads(int(n)))
 
 
 def panel_layout(row_ptr, col_idx, val, ncols, npanel, cuts=None, groups=256, aligned=False, emax=8):

@@ -201,3 +201,35 @@ def test_panel_layout_rejects_bad_arguments():
         P.panel_layout(K.indptr, bad, K.data, K.shape[1], 3)
     with pytest.raises(P.PdlpError):                           # cuts not ending at ncols
         P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], 2, cuts=np.array([0, 50, 100], np.int32))
+
+
+def test_layouts_do_not_depend_on_the_host_thread_count():
+    """Above 2^20 nonzeros the host preparation runs in parallel chunks (rows, tasks, column
+    ranges); every array of the layout must be the same for 1, 3 and 8 threads."""
+    rng = np.random.default_rng(12)
+    m, n = 70000, 50000
+    lens = rng.choice([0, 1, 3, 9, 20, 60, 300, 700], size=m, p=[.05, .2, .2, .2, .15, .15, .04, .01])
+    cols = np.concatenate([rng.choice(n, size=ln, replace=False) for ln in lens])
+    rows = np.repeat(np.arange(m), lens)
+    K = sp.csr_matrix((rng.standard_normal(cols.size), (rows, cols)), shape=(m, n))
+    K.sort_indices()
+    assert K.nnz > (1 << 20)
+    W = 4096
+    npanel = -(-n // W)
+    cuts = np.minimum(np.arange(npanel + 1) * W, n).astype(np.int32)
+    out = {}
+    try:
+        for th in (1, 3, 8):
+            P.set_host_threads(th)
+            out[th] = (P.panel_layout(K.indptr, K.indices, K.data, n, 8, groups=256, aligned=True, emax=16),
+                       P.panel_layout(K.indptr, K.indices, K.data, n, npanel, cuts=cuts, groups=64, emax=16),
+                       P.schedule(K.indptr))
+    finally:
+        P.set_host_threads(0)
+    for th in (3, 8):
+        for a, b in zip(out[1][:2], out[th][:2]):
+            assert a.keys() == b.keys()
+            for k in a:
+                assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), (th, k)
+        for a, b in zip(out[1][2], out[th][2]):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), th
