@@ -102,7 +102,8 @@ typedef struct pdlp_options {
                                     the hot-first K~ copy stages each XCD panel's first
                                     lds_entries columns; a copy whose columns keep their order
                                     gets slices of lds_entries columns, one panel each, when
-                                    its panel rows stay below 0.4 of its nonzeros), 0 off,
+                                    its panel rows stay below 0.4 of its nonzeros, or below
+                                    0.7 when it would otherwise be in XCD panels), 0 off,
                                     1 the slices whenever a copy is in panels, 2 XCD panels
                                     with each panel's first lds_entries columns staged.  Never
                                     for a copy with a panel row longer than 512 nonzeros.      */

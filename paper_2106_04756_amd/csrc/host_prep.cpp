@@ -184,27 +184,25 @@ std::vector<int32_t> hot_column_order(const int32_t* ci, int64_t nnz, int64_t nc
   return order;
 }
 
-bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
-                  double max_prow_frac, PanelLayout& L, const std::vector<int32_t>* given_cuts, int emax) {
+namespace {
+
+// Layouts for the LDS-staged kernel (emax = kElemsPerLaneLds) hold wavefront tasks: a row's run
+// inside a panel of kWaveMaxLen + 1 .. kVectorMax entries is cut into pieces of kWaveMaxLen
+// entries (the last one shorter), each a panel row of its own, added in order by the combine.
+// Longer runs stay whole (a workgroup task): the combine adds a row's panel rows one thread at
+// a time, and thousands of pieces would serialize it.  The panel rows of a run of len entries:
+int64_t run_pieces(int64_t len, int emax) {
+  return (emax == kElemsPerLaneLds && len > kWaveMaxLen && len <= kVectorMax) ? (len + kWaveMaxLen - 1) / kWaveMaxLen
+                                                                             : 1;
+}
+
+// The panel rows of each row under the column cuts `cut`, as offsets: row r's are
+// sp[r] .. sp[r + 1] (rows in parallel chunks).  Returns their total.
+int64_t panel_row_offsets(const int64_t* rp, const int32_t* ci, int64_t nrows, const std::vector<int32_t>& cut,
+                          int emax, std::vector<int64_t>& sp) {
   const int64_t nnz = rp[nrows];
-  L = PanelLayout();
-  L.P = P;
-  L.cut = given_cuts ? *given_cuts : panel_cuts(ci, nnz, ncols, P);
-  const std::vector<int32_t>& cut = L.cut;
-  // Layouts for the LDS-staged kernel (emax = kElemsPerLaneLds) hold wavefront tasks: a row's
-  // run inside a panel of kWaveMaxLen + 1 .. kVectorMax entries is cut into pieces of
-  // kWaveMaxLen entries (the last one shorter), each a panel row of its own, added in order by
-  // the combine.  Longer runs stay whole (a workgroup task): the combine adds a row's panel
-  // rows one thread at a time, and thousands of pieces would serialize it.
-  const bool cut_runs = emax == kElemsPerLaneLds;
-  auto pieces = [&](int64_t len) -> int64_t {
-    return (cut_runs && len > kWaveMaxLen && len <= kVectorMax) ? (len + kWaveMaxLen - 1) / kWaveMaxLen : 1;
-  };
-  // Row segments: the panel rows of row r are segments sp[r] .. sp[r + 1], in panel order,
-  // with their panel and length (a sparse form of the rows x panels length table).
-  // (rows in parallel chunks; each writes only its own rows' entries)
   const int64_t row_chunk = nnz < kParallelNnz ? std::max<int64_t>(nrows, 1) : int64_t(1) << 14;
-  std::vector<int64_t> sp(size_t(nrows) + 1, 0);
+  sp.assign(size_t(nrows) + 1, 0);
   parallel_for(nrows, [&](int64_t r0, int64_t r1) {
     for (int64_t r = r0; r < r1; ++r) {
       int64_t cntr = 0, run = 0;
@@ -213,18 +211,42 @@ bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t n
         int q = p < 0 ? 0 : p;
         while (ci[e] >= cut[size_t(q) + 1]) ++q;
         if (q != p) {
-          if (p >= 0) cntr += pieces(run);
+          if (p >= 0) cntr += run_pieces(run, emax);
           p = q;
           run = 0;
         }
         ++run;
       }
-      if (p >= 0) cntr += pieces(run);
+      if (p >= 0) cntr += run_pieces(run, emax);
       sp[size_t(r) + 1] = cntr;
     }
   }, row_chunk);
   for (int64_t r = 0; r < nrows; ++r) sp[size_t(r) + 1] += sp[size_t(r)];
-  const int64_t nprow = sp[size_t(nrows)];
+  return sp[size_t(nrows)];
+}
+
+}  // namespace
+
+int64_t count_panel_rows(const int64_t* rp, const int32_t* ci, int64_t nrows, const std::vector<int32_t>& cut,
+                         int emax) {
+  std::vector<int64_t> sp;
+  return panel_row_offsets(rp, ci, nrows, cut, emax, sp);
+}
+
+bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
+                  double max_prow_frac, PanelLayout& L, const std::vector<int32_t>* given_cuts, int emax) {
+  const int64_t nnz = rp[nrows];
+  L = PanelLayout();
+  L.P = P;
+  L.cut = given_cuts ? *given_cuts : panel_cuts(ci, nnz, ncols, P);
+  const std::vector<int32_t>& cut = L.cut;
+  auto pieces = [&](int64_t len) -> int64_t { return run_pieces(len, emax); };
+  // Row segments: the panel rows of row r are segments sp[r] .. sp[r + 1], in panel order,
+  // with their panel and length (a sparse form of the rows x panels length table).
+  // (rows in parallel chunks; each writes only its own rows' entries)
+  const int64_t row_chunk = nnz < kParallelNnz ? std::max<int64_t>(nrows, 1) : int64_t(1) << 14;
+  std::vector<int64_t> sp;
+  const int64_t nprow = panel_row_offsets(rp, ci, nrows, cut, emax, sp);
   if (double(nprow) > max_prow_frac * double(std::max<int64_t>(nnz, 1))) return false;
   std::vector<int32_t> seg_p(static_cast<size_t>(nprow)), seg_len(static_cast<size_t>(nprow));
   std::vector<int32_t> seg_row(static_cast<size_t>(nprow));

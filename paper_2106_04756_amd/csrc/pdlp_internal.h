@@ -31,6 +31,12 @@ constexpr int kLdsWaves = kLdsBlock / 64;
 constexpr int kLdsEntries = 19456;
 constexpr int kMaxLdsPanels = 4096;
 constexpr double kLdsRowFrac = 0.4;
+// ... or at most kLdsRowFracVsPanels when the alternative is XCD panels (the copy's panel rows
+// there below kPanelRowFrac): gathers from LDS instead of L2 are then worth a larger combine
+// (on the 1e6 x 2e6 LP with 2.1e7 nonzeros, slices at 0.64 against XCD panels at 0.29 gave
+// +4.7% PDHG iterations per second; the PageRank LP's transposed copy, at 0.61 against a plain
+// layout, lost 29%).
+constexpr double kLdsRowFracVsPanels = 0.7;
 
 enum DescKind : int32_t { kWaveRows = 0, kVector = 1, kSplit = 2 };
 
@@ -93,6 +99,10 @@ struct LdsSeg {
 bool build_panels(const int64_t* rp, const int32_t* ci, int64_t nrows, int64_t ncols, int P,
                   double max_prow_frac, PanelLayout& out,
                   const std::vector<int32_t>* given_cuts = nullptr, int emax = kElemsPerLane);
+
+// Number of panel rows build_panels would make under the column cuts `cut` (P + 1 offsets).
+int64_t count_panel_rows(const int64_t* rp, const int32_t* ci, int64_t nrows, const std::vector<int32_t>& cut,
+                         int emax = kElemsPerLane);
 
 // Interleaved entries of the wavefront tasks (a sliced-ELL form): round i of task t, with E
 // entries per lane, owns 64 E slots from off[t] + 64 E i; entry k of lane j (row group

@@ -374,9 +374,15 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
     if (Pw >= 2 && Pw <= kMaxLdsPanels) {
       std::vector<int32_t> wc(size_t(Pw) + 1);
       for (int64_t p = 0; p <= Pw; ++p) wc[size_t(p)] = int32_t(std::min<int64_t>(p * W, ncols));
-      panel = build_panels(rp, ci, nrows, ncols, int(Pw), lmode == 1 ? 1e300 : kLdsRowFrac, PL, &wc,
-                           kElemsPerLaneLds) &&
-              PL.sched.block.empty();
+      double frac = lmode == 1 ? 1e300 : kLdsRowFrac;
+      if (lmode < 0) {
+        // with XCD panels as the alternative (forced, or their panel rows below
+        // kPanelRowFrac), slices may cost more panel rows
+        const std::vector<int32_t> xc = cuts ? *cuts : panel_cuts(ci, nnz, ncols, kMaxPanels);
+        if (mode == 1 || double(count_panel_rows(rp, ci, nrows, xc)) <= kPanelRowFrac * double(nnz))
+          frac = kLdsRowFracVsPanels;
+      }
+      panel = build_panels(rp, ci, nrows, ncols, int(Pw), frac, PL, &wc, kElemsPerLaneLds) && PL.sched.block.empty();
       if (panel) {
         lds_h = W;
         slices = true;
