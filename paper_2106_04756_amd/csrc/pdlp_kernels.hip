@@ -131,11 +131,27 @@ __device__ void sum_slots(const double* part, int nslot, double (&a)[N]) {
     }
     __syncthreads();
   } else {
+    // thread t adds slots t, t + kBlock, ... in that order; the loads of Q slots (8 values)
+    // are issued before their adds (one slot at a time, the chain of loads set the time of the
+    // one-workgroup tail kernels)
+    constexpr int Q = N >= 8 ? 1 : 8 / N;
 #pragma unroll
     for (int k = 0; k < N; ++k) a[k] = 0.0;
-    for (int sl = threadIdx.x; sl < nslot; sl += kBlock) {
+    for (int sl0 = threadIdx.x; sl0 < nslot; sl0 += Q * kBlock) {
+      double v[Q][N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) a[k] += part[size_t(sl) * N + k];
+      for (int q = 0; q < Q; ++q) {
+        const int sl = sl0 + q * kBlock;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[q][k] = sl < nslot ? part[size_t(sl) * N + k] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        if (sl0 + q * kBlock < nslot) {
+#pragma unroll
+          for (int k = 0; k < N; ++k) a[k] += v[q][k];
+        }
+      }
     }
     block_sum<N>(a);
   }
