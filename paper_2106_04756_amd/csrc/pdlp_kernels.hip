@@ -99,62 +99,64 @@ __device__ double block_max(double v) {
 
 // Sum over `nslot` partial slots of N values each (slot-major), value k in a[k] of thread 0.
 // Slots are plain memory: they are read after a kernel boundary (k_tail) or after the acquire
-// fence of arrive_last, which pairs with the release fence every writer passed.  When N
-// divides the workgroup size, thread t sums value k = t mod N of every (kBlock / N)-th slot, so
-// each pass over the slots is one contiguous read; the kBlock / N partial sums of each k are
-// then added in a fixed order.
+// fence of arrive_last, which pairs with the release fence every writer passed.  Thread t adds
+// slots t, t + kBlock, ... in that order, the loads of Q slots (8 values) issued before their
+// adds (one slot at a time, the chain of loads set the time of the one-workgroup tail
+// kernels); then the workgroup's sums are added in a fixed order.  Many values per slot:
+// sum_slots_shared.
 template <int N>
 __device__ void sum_slots(const double* part, int nslot, double (&a)[N]) {
-  if constexpr (N >= 8 && kBlock % N == 0) {
-    constexpr int G = kBlock / N;
-    __shared__ double lds[kBlock];
-    const int k = threadIdx.x % N, g = threadIdx.x / N;
-    // eight interleaved partial sums keep eight loads in flight per thread
-    double u8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    int sl = g;
-    for (; sl + 7 * G < nslot; sl += 8 * G) {
+  static_assert(N < 8, "use sum_slots_shared");
+  constexpr int Q = 8 / N;
 #pragma unroll
-      for (int q = 0; q < 8; ++q) u8[q] += part[size_t(sl + q * G) * N + k];
+  for (int k = 0; k < N; ++k) a[k] = 0.0;
+  for (int sl0 = threadIdx.x; sl0 < nslot; sl0 += Q * kBlock) {
+    double v[Q][N];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int sl = sl0 + q * kBlock;
+#pragma unroll
+      for (int k = 0; k < N; ++k) v[q][k] = sl < nslot ? part[size_t(sl) * N + k] : 0.0;
     }
-    for (int q = 0; sl < nslot; sl += G, ++q) u8[q] += part[size_t(sl) * N + k];
-    const double t = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
-    __syncthreads();
-    lds[threadIdx.x] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
 #pragma unroll
-      for (int kk = 0; kk < N; ++kk) {
-        double u = 0.0;
-        for (int gg = 0; gg < G; ++gg) u += lds[gg * N + kk];
-        a[kk] = u;
+    for (int q = 0; q < Q; ++q) {
+      if (sl0 + q * kBlock < nslot) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) a[k] += v[q][k];
       }
     }
-    __syncthreads();
-  } else {
-    // thread t adds slots t, t + kBlock, ... in that order; the loads of Q slots (8 values)
-    // are issued before their adds (one slot at a time, the chain of loads set the time of the
-    // one-workgroup tail kernels)
-    constexpr int Q = N >= 8 ? 1 : 8 / N;
-#pragma unroll
-    for (int k = 0; k < N; ++k) a[k] = 0.0;
-    for (int sl0 = threadIdx.x; sl0 < nslot; sl0 += Q * kBlock) {
-      double v[Q][N];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        const int sl = sl0 + q * kBlock;
-#pragma unroll
-        for (int k = 0; k < N; ++k) v[q][k] = sl < nslot ? part[size_t(sl) * N + k] : 0.0;
-      }
-#pragma unroll
-      for (int q = 0; q < Q; ++q) {
-        if (sl0 + q * kBlock < nslot) {
-#pragma unroll
-          for (int k = 0; k < N; ++k) a[k] += v[q][k];
-        }
-      }
-    }
-    block_sum<N>(a);
   }
+  block_sum<N>(a);
+}
+
+// Sum over `nslot` slots of N >= 8 values each (N dividing the workgroup size): thread t sums
+// value k = t mod N of every (kBlock / N)-th slot, so each pass over the slots is one
+// contiguous read, with eight interleaved partial sums keeping eight loads in flight; then
+// threads 0 .. N - 1 add the kBlock / N partial sums of their k in a fixed order into out[k] in
+// LDS, visible to the whole workgroup on return (no thread holds all N in registers).
+template <int N>
+__device__ void sum_slots_shared(const double* part, int nslot, double* out) {
+  static_assert(N >= 8 && kBlock % N == 0, "N must divide the workgroup size");
+  constexpr int G = kBlock / N;
+  __shared__ double lds[kBlock];
+  const int k = threadIdx.x % N, g = threadIdx.x / N;
+  double u8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int sl = g;
+  for (; sl + 7 * G < nslot; sl += 8 * G) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) u8[q] += part[size_t(sl + q * G) * N + k];
+  }
+  for (int q = 0; sl < nslot; sl += G, ++q) u8[q] += part[size_t(sl) * N + k];
+  const double t = ((u8[0] + u8[1]) + (u8[2] + u8[3])) + ((u8[4] + u8[5]) + (u8[6] + u8[7]));
+  __syncthreads();
+  lds[threadIdx.x] = t;
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double u = 0.0;
+    for (int gg = 0; gg < G; ++gg) u += lds[gg * N + threadIdx.x];
+    out[threadIdx.x] = u;
+  }
+  __syncthreads();
 }
 
 template <int N>
@@ -1694,8 +1696,8 @@ __device__ void gap_setup_tail(DevState* st, int mode, const double* part, int n
   if (threadIdx.x == 0) gap_setup_decide(*st, mode, t);
 }
 __device__ void gap_bisect_tail(DevState* st, int mode, const double* part, int nslot) {
-  double t[2 * kGapPts];
-  sum_slots<2 * kGapPts>(part, nslot, t);
+  __shared__ double t[2 * kGapPts];
+  sum_slots_shared<2 * kGapPts>(part, nslot, t);
   if (threadIdx.x == 0) gap_bisect_decide(*st, mode, t);
 }
 __device__ void gap_final_tail(DevState* st, const Bufs& B, int mode, const double* part, int nslot) {
