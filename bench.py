@@ -3,8 +3,10 @@ column counts, nnz ~1.35e8), one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-batched]
                     [--no-unroll] [--no-truncated] [--no-pagerank] [--no-policies]
-                    [--no-ablations] [--only-large] [--calibrate-copy]
+                    [--no-ablations] [--only-large | --only-lp truncated|pagerank | --only-unroll]
+                    [--calibrate-copy]
     python bench.py --summarize-profile DIR     # text summary of the rocprofv3 runs in DIR
+    python bench.py --summarize-unroll DIR      # the same for a trace of --only-unroll
 
 A step is one accepted PDHG iteration of Algorithm 1 on the whole LP: the K~^T product fused
 with the primal step, the K~ product fused with the dual step and the step-size rule, and
@@ -658,6 +660,44 @@ def summarize_profile(d):
                                                                 if v > 1e6}}))
 
 
+def summarize_unroll(d):
+    """Summary of the rocprofv3 kernel trace of `bench.py --only-unroll` under d/trace (kernel
+    statistics of the unrolled-PDHG kernels) with that run's bench line (d/bench_trace.json)."""
+    trace = sorted(glob.glob(os.path.join(d, "trace", "**", "*kernel_stats.csv"), recursive=True))
+    bl = os.path.join(d, "bench_trace.json")
+    bj = {}
+    if os.path.exists(bl):
+        with open(bl) as fh:
+            lines = [ln for ln in fh if ln.startswith("{")]
+        if lines:
+            bj = json.loads(lines[-1])
+    print(f"rocprofv3 profile: unrolled PDHG kernels on {bj.get('workload', 'the unroll LP')}, one MI355X")
+    print(f"step-kernel sources sha256 {kernel_sources_digest()} (bench.STEP_SOURCES under paper_2106_04756_amd/csrc)")
+    print()
+    print("Kernel statistics (one forward step = UFwdPrimal + UFwdDual, one adjoint step = UBwdPrimal +")
+    print("UBwdDual; the run makes 6 forward and 6 backward passes with segment 50, then 6 with every")
+    print("step's masks kept):")
+    print(f"{'kernel':32s} {'calls':>7s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'total_ms':>9s}")
+    if trace:
+        rows = [r for r in _read_csv(trace[0]) if "unroll" in r["Name"]]
+        for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"])):
+            print(f"{_short_kernel(r['Name']):32s} {int(r['Calls']):7d} {float(r['AverageNs']) * 1e-3:8.1f} "
+                  f"{float(r['MinNs']) * 1e-3:8.1f} {float(r['MaxNs']) * 1e-3:8.1f} "
+                  f"{float(r['TotalDurationNs']) * 1e-6:9.2f}")
+    print()
+    if bj:
+        c, a = bj["checkpointed"], bj["all_masks_kept"]
+        print(f"bench.py unroll line of the traced run: forward {c['forward_ms']:.2f} ms "
+              f"({c['forward_steps_per_s']:.0f} steps/s), adjoint {c['backward_ms']:.2f} ms, "
+              f"(forward + adjoint) / forward = {c['fwd_plus_adjoint_over_fwd']:.2f} (segment {bj['segment']}); "
+              f"all masks kept: {a['fwd_plus_adjoint_over_fwd']:.2f}")
+        print()
+    print("Commands (repository root R on the GPU host; `cd /tmp && export TMPDIR=/tmp` first):")
+    print("  rocprofv3 --kernel-trace --stats --output-format csv -d trace -o run -- python3 R/bench.py "
+          "--only-unroll > bench_trace.json")
+    print("  python3 R/bench.py --summarize-unroll <this directory>")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -676,6 +716,9 @@ def main():
     ap.add_argument("--only-lp", choices=["truncated", "pagerank"],
                     help="only the truncated large LP or the PageRank LP, headline windows as for the "
                          "large LP (profiling runs; the JSON line carries that LP's figures)")
+    ap.add_argument("--only-unroll", action="store_true",
+                    help="only the unrolled PDHG measurement (profiling runs; prints its JSON object)")
+    ap.add_argument("--summarize-unroll", metavar="DIR")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-iter-limit", type=int, default=100000)
     ap.add_argument("--calibrate-copy", action="store_true")
@@ -683,6 +726,9 @@ def main():
     args = ap.parse_args()
     if args.summarize_profile:
         summarize_profile(args.summarize_profile)
+        return
+    if args.summarize_unroll:
+        summarize_unroll(args.summarize_unroll)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -701,6 +747,9 @@ def main():
     from workloads import lpgen
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.only_unroll:
+        print(json.dumps(bench_unroll(P, lpgen)), flush=True)
+        return
     if args.only_lp:
         t = time.time()
         lpo = lpgen.large_lp_truncated(args.seed) if args.only_lp == "truncated" else lpgen.pagerank_5m()
