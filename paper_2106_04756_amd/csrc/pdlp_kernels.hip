@@ -1083,7 +1083,22 @@ __global__ __launch_bounds__(kLdsBlock) void k_lds_rows(CsrDev A, DevState* st, 
     const int32_t c0 = A.col_cut[G.p];
     const int32_t h = min(A.lds_h, A.col_cut[G.p + 1] - c0);
     if (sg > s0) __syncthreads();        // every wavefront is done with the previous stage
-    for (int i = threadIdx.x; i < h; i += kLdsBlock) stage[i] = in[c0 + i];
+    {
+      // all of a thread's stage loads in flight before its stores (one wait instead of a
+      // chain of them; the stage fill holds up every wavefront of the workgroup)
+      constexpr int kPer = (kLdsEntries + kLdsBlock - 1) / kLdsBlock;
+      double tmp[kPer];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kLdsBlock;
+        tmp[q] = i < h ? in[c0 + i] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int i = threadIdx.x + q * kLdsBlock;
+        if (i < h) stage[i] = tmp[q];
+      }
+    }
     __syncthreads();
     if (A.cis16) {            // a slice: every column is in the stage
       const StageGather gx{stage};
