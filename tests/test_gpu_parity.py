@@ -339,6 +339,35 @@ def test_two_runs_are_bitwise_equal_and_resume_is_seamless(panels):
     assert ia["iterations"] == ib["iterations"] == 300 and ia["omega"] == ib["omega"]
 
 
+def test_host_thread_count_does_not_change_the_solve():
+    """pdlp_create prepares the LP (internal column order, transpose, layouts, interleaved
+    entries) on 1 or on all host threads: above 2^20 nonzeros the parallel chunks are taken, and
+    the scaling vectors and 80 steps through two restart checks are bitwise the same.  XCD
+    panels and the internal column order forced: K~ in XCD panels with the hot stage, K~^T in
+    LDS slices."""
+    lp = lpgen.large_plain(32, 30000, 60000)
+    assert lp.nnz > (1 << 20)
+    say("host threads", lp.nnz)
+    runs = []
+    try:
+        for th in (1, 0):
+            P.set_host_threads(th)
+            s = make(lp, xcd_panels=1, column_order=1)
+            inf = s.info()
+            s.solve(1e-30, 80)
+            x, y = s.iterate()
+            D1, D2 = s.scaling()
+            runs.append((x, y, D1, D2, inf["layout_K"], inf["layout_KT"], s.info()["omega"]))
+            s.close()
+    finally:
+        P.set_host_threads(0)
+    a, b = runs
+    assert a[4:6] == b[4:6] and a[4] > 0 and a[5] > 0, (a[4:6], b[4:6])
+    for u, v in zip(a[:4], b[:4]):
+        assert np.array_equal(u, v)
+    assert a[6] == b[6]
+
+
 @pytest.mark.parametrize("kw", [dict(), dict(xcd_panels=1), dict(step_policy=2),
                                 dict(LDS_MODES["slices"]), dict(LDS_MODES["xcd_stage"], step_policy=2)])
 def test_graph_replay_equals_kernel_by_kernel(kw):
