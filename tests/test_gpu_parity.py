@@ -123,43 +123,84 @@ def test_preconditioning_matches_oracle(panels):
         assert np.max(np.abs(D2 / oD2 - 1)) < 1e-13
 
 
-def _trajectory_parity(lp, iters=100, opts=None, **kw):
+def _trajectory_parity(lp, iters=100, opts=None, calibrate=False, **kw):
+    """Free-running: the GPU's first `iters` iterates against the oracle's, 1e-11 relative per
+    iterate, the step sizes, decisions and checks beside them.  calibrate=True widens every
+    bar to 10 times the oracle's own divergence at that point when only the order of its sums
+    over the columns changes (_calibration), where the trajectory amplifies round-off beyond the
+    fixed bars; decisions must still be identical."""
     opts = opts or O.Options()
-    say("trajectory", lp.name, lp.m, lp.n, lp.nnz, kw)
+    say("trajectory", lp.name, lp.m, lp.n, lp.nnz, kw, "calibrated" if calibrate else "")
     s = make(lp, trace_iters=iters, **kw)
     st = s.solve(1e-30, iters)
     assert st == P.ITERATION_LIMIT
     tr = s.trace()
     ref = O.solve_lp(lp, tol=1e-30, iter_limit=iters, opts=opts, trace_iters=iters)
     assert tr["n_iter"] == iters == len(ref.trace.iterates)
+    cal = _calibration(lp, ref, iters, opts) if calibrate else None
     worst = 0.0
     for k in range(iters):
         kk, xo, yo = ref.trace.iterates[k]
         ex = rel(tr["xs"][k], xo)
         ey = rel(tr["ys"][k], yo) if lp.m else 0.0
-        worst = max(worst, ex, ey)
-        assert ex <= 1e-11 and ey <= 1e-11, (k + 1, ex, ey)
+        bar = max(1e-11, 10 * cal["iterate"][k]) if cal else 1e-11
+        worst = max(worst, ex / bar, ey / bar)
+        assert ex <= bar and ey <= bar, (k + 1, ex, ey, bar)
     ga = tr["attempts"]
     oa = ref.trace.attempts
     assert len(ga) == len(oa)
-    for g, o in zip(ga, oa):
+    for i, (g, o) in enumerate(zip(ga, oa)):
         assert g[0] == o[0] and g[3] == o[3]
         # the step tried is the previous proposal of Algorithm 2, min((1 - (k+1)^-0.3) eta_bar,
         # (1 + (k+1)^-0.6) eta): eta_bar's denominator 2 |dy^T K dx| cancels, so it carries the
         # last-bit differences of the dot products (summed in another order on the GPU) with a
         # gain of ~1e2 along a free-running trajectory; the iterates themselves stay at 1e-11
-        assert abs(g[1] - o[1]) <= 1e-10 * o[1]
+        assert abs(g[1] - o[1]) <= max(1e-10, 10 * cal["eta"][i] if cal else 0.0) * o[1]
         if math.isfinite(o[2]):
-            assert abs(g[2] - o[2]) <= 1e-9 * o[2]
+            assert abs(g[2] - o[2]) <= max(1e-9, 10 * cal["eta_bar"][i] if cal else 0.0) * o[2]
     gc, oc = tr["checks"], ref.trace.checks
     assert len(gc) == len(oc)
-    for g, o in zip(gc, oc):
+    for j, (g, o) in enumerate(zip(gc, oc)):
         assert g["k"] == o["k"] and g["use_avg"] == o["use_avg"] and g["mask"] == o["mask"]
-        assert abs(g["omega_after"] - o["omega_after"]) <= 1e-11 * o["omega_after"]
+        tol = max(1e-11, 10 * cal["omega_after"][j] if cal else 0.0)
+        assert abs(g["omega_after"] - o["omega_after"]) <= tol * o["omega_after"]
         for key in ("mu_cur", "mu_avg"):
             if math.isfinite(o[key]):
-                assert abs(g[key] - o[key]) <= 1e-9 * max(abs(o[key]), 1e-300), key
+                tol = max(1e-9, 10 * cal[key][j] if cal else 0.0)
+                assert abs(g[key] - o[key]) <= tol * max(abs(o[key]), 1e-300), key
     return worst
+
+
+def _calibration(lp, ref, iters, opts):
+    """The oracle's own sensitivity along this trajectory: the oracle run again on the same LP
+    with its columns in a random order (every sum over the columns taken in another order,
+    nothing else changed), and the relative difference of each iterate, each attempt's step
+    and step limit, and each check's gaps and primal weight.  Its decisions must match the
+    first run's, which is what makes the comparison point by point."""
+    perm = np.random.default_rng(5).permutation(lp.n)
+    K = lp.K()[:, perm].tocsr()
+    K.sort_indices()
+    lp2 = lpgen.from_csr(K, lp.c[perm], lp.q, lp.l[perm], lp.u[perm], lp.n_eq, name=lp.name + " permuted")
+    r2 = O.solve_lp(lp2, tol=1e-30, iter_limit=iters, opts=opts, trace_iters=iters)
+    out = {"iterate": np.zeros(iters)}
+    for k in range(iters):
+        _, x1, y1 = ref.trace.iterates[k]
+        _, x2, y2 = r2.trace.iterates[k]
+        xb = np.empty_like(x2)
+        xb[perm] = x2
+        out["iterate"][k] = max(rel(xb, x1), rel(y2, y1) if lp.m else 0.0)
+    oa, pa = ref.trace.attempts, r2.trace.attempts
+    assert len(oa) == len(pa) and all(o[0] == q[0] and o[3] == q[3] for o, q in zip(oa, pa))
+    out["eta"] = [abs(q[1] - o[1]) / o[1] for o, q in zip(oa, pa)]
+    out["eta_bar"] = [abs(q[2] - o[2]) / o[2] if math.isfinite(o[2]) and math.isfinite(q[2]) else 0.0
+                      for o, q in zip(oa, pa)]
+    oc, pc = ref.trace.checks, r2.trace.checks
+    assert len(oc) == len(pc) and all(o["k"] == q["k"] and o["use_avg"] == q["use_avg"] and o["mask"] == q["mask"]
+                                      for o, q in zip(oc, pc))
+    for key in ("omega_after", "mu_cur", "mu_avg"):
+        out[key] = [abs(q[key] - o[key]) / max(abs(o[key]), 1e-300) if math.isfinite(o[key]) else 0.0
+                    for o, q in zip(oc, pc)]
+    return out
 
 
 def test_trajectory_parity_tiny_lp():
@@ -171,6 +212,18 @@ def test_trajectory_parity_tiny_lp_reordered_columns():
     """The same with the internal column order (dense columns first in each XCD panel): every
     n-vector of the trace comes back in the user's order."""
     _trajectory_parity(lpgen.tiny_lp(), xcd_panels=1, column_order=1)
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+@pytest.mark.parametrize("kw", [dict(), dict(xcd_panels=1, column_order=1)])
+def test_trajectory_parity_400x900(seed, kw):
+    """Free-running on two 400 x 900 LPs of the large-LP recipe over the first 100 steps (two
+    restart checks): each iterate within 1e-11, or within 10 times the oracle's own divergence
+    at that step when only the order of its column sums changes, where this trajectory
+    amplifies round-off beyond 1e-11 (seed 22: 5e-11 at k = 57, 2e-10 at k = 100); the step
+    sizes and gaps likewise; accept/reject and restart decisions identical."""
+    worst = _trajectory_parity(lpgen.large_plain(seed, 400, 900), iters=100, calibrate=True, **kw)
+    say("worst error / bar", worst)
 
 
 def _replay_parity(lp, steps=100, opts=None, **kw):
@@ -288,7 +341,7 @@ def test_malitsky_pock_trajectory_parity(panels):
     layout and in forced XCD panels."""
     worst = _trajectory_parity(lpgen.tiny_lp(), opts=O.Options(step_policy="malitsky_pock"), step_policy=2,
                                xcd_panels=panels)
-    say("malitsky-pock worst iterate error", worst)
+    say("malitsky-pock worst iterate error / 1e-11", worst)
 
 
 def test_malitsky_pock_solve_to_1e8():
