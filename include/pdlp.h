@@ -105,8 +105,9 @@ typedef struct pdlp_options {
                                     its panel rows stay below 0.4 of its nonzeros, or below
                                     0.7 when it would otherwise be in XCD panels), 0 off,
                                     1 the slices whenever a copy is in panels, 2 XCD panels
-                                    with each panel's first lds_entries columns staged.  Never
-                                    for a copy with a panel row longer than 512 nonzeros.      */
+                                    with each panel's first lds_entries columns staged.  A
+                                    row's run of 513 .. 16384 nonzeros inside one panel is cut
+                                    into pieces of 512; never for a copy with a longer run.    */
   int32_t lds_entries;           /* operand entries staged per panel: 0 = 19456 (the most;
                                     152 KiB of LDS), else 1 .. 19456                           */
 } pdlp_options;
