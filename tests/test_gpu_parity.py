@@ -363,6 +363,16 @@ def test_malitsky_pock_trajectory_parity(panels):
     say("malitsky-pock worst iterate error / 1e-11", worst)
 
 
+@pytest.mark.parametrize("panels", [0, 1])
+def test_malitsky_pock_trajectory_parity_400x900(panels):
+    """The line search on a 400 x 900 LP of the large-LP recipe, free-running over 100
+    iterations, calibrated as in test_trajectory_parity_400x900 (on this LP the oracle's own
+    divergence stays below 1e-13, so the bar is 1e-11 throughout)."""
+    worst = _trajectory_parity(lpgen.large_plain(21, 400, 900), opts=O.Options(step_policy="malitsky_pock"),
+                               calibrate=True, step_policy=2, xcd_panels=panels, column_order=panels)
+    say("malitsky-pock 400x900 worst error / bar", worst)
+
+
 def test_malitsky_pock_solve_to_1e8():
     lp = lpgen.tiny_lp()
     say("solve tiny_lp malitsky-pock")
