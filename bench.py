@@ -650,7 +650,7 @@ def summarize_profile(d):
         print()
     cmd = os.path.join(d, "commands.txt")
     if os.path.exists(cmd):
-        print("Commands (repository root R on the GPU host; `cd /tmp && export TMPDIR=/tmp` first):")
+        print("Commands (R = the repository root; run from /tmp after `export TMPDIR=/tmp`):")
         with open(cmd) as fh:
             for ln in fh:
                 print("  " + ln.rstrip())
@@ -692,7 +692,7 @@ def summarize_unroll(d):
               f"(forward + adjoint) / forward = {c['fwd_plus_adjoint_over_fwd']:.2f} (segment {bj['segment']}); "
               f"all masks kept: {a['fwd_plus_adjoint_over_fwd']:.2f}")
         print()
-    print("Commands (repository root R on the GPU host; `cd /tmp && export TMPDIR=/tmp` first):")
+    print("Commands (R = the repository root; run from /tmp after `export TMPDIR=/tmp`):")
     print("  rocprofv3 --kernel-trace --stats --output-format csv -d trace -o run -- python3 R/bench.py "
           "--only-unroll > bench_trace.json")
     print("  python3 R/bench.py --summarize-unroll <this directory>")
