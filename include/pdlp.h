@@ -110,6 +110,15 @@ typedef struct pdlp_options {
                                     into pieces of 512; never for a copy with a longer run.    */
   int32_t lds_entries;           /* operand entries staged per panel: 0 = 19456 (the most;
                                     152 KiB of LDS), else 1 .. 19456                           */
+  int32_t xcd_subpanels;         /* a copy in XCD panels without an LDS stage: each panel's
+                                    column range cut into this many equal ranges, which the
+                                    XCD's workgroups take one after another, so that fewer
+                                    lines of the gathered operand are in use at a time): -1
+                                    automatic (default: none while each panel's range of the
+                                    operand fits in 1 MiB, else the fewest that keep each
+                                    within it, rounded up to an even count, at most 8; used
+                                    while the panel rows stay below 0.4 of the nonzeros),
+                                    0 or 1 none, 2 .. 8 that many                             */
 } pdlp_options;
 
 /* Counters and scalars of a solver (pdlp_get_info). */

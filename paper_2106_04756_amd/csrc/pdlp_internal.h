@@ -21,6 +21,15 @@ constexpr int kChunk = 16384;          // nonzeros per chunk of a split row
 // gave +28%).
 constexpr double kPanelRowFrac = 0.4;
 constexpr int kMaxPanels = 8;          // XCD column panels of a copy (one per XCD of an MI355X)
+// XCD panels without an LDS stage gather their operand slice through the XCD's 4 MiB L2.  A
+// slice wider than kSubpanelBytes is cut into equal column ranges (sub-panels), which the
+// XCD's workgroups take one after another, so that fewer lines of the operand are in use at a
+// time next to the streamed entries; an even number of them, at most kMaxSubpanels.  On the
+// PageRank LP on 5e6 nodes (4.8 MiB slices) the K~ x' first pass took 640 us whole and 622,
+// 580, 505, 548, 475, 516, 508 us in 2 .. 8 sub-panels, while its combine grew from 121 to
+// 137 .. 188 us (more panel rows); odd counts were slower in repeated runs.
+constexpr int64_t kSubpanelBytes = int64_t(1) << 20;
+constexpr int kMaxSubpanels = 8;
 // LDS-staged products: one workgroup of kLdsBlock threads per CU holds up to kLdsEntries
 // entries of the gathered vector (152 KiB of the CU's 160 KiB of LDS).  A copy whose
 // gathered vector, cut into slices of that width, costs at most kLdsRowFrac panel rows per

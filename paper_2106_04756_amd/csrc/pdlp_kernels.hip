@@ -214,26 +214,29 @@ __device__ double range_reduce(const CsrDev& A, const double* __restrict__ x, in
   return block_comb<MODE>(s);
 }
 
-// Long rows (kVector) and chunks of giant rows (kSplit), one workgroup each.
-// Task ranges of this workgroup: panel blockIdx mod npanel (its XCD when npanel = 8), and the
-// workgroup's index and count among those of that panel.
+// Task ranges of this workgroup: the panels of group g = blockIdx mod (npanel / nsub), that
+// is g nsub .. g nsub + nsub - 1, taken one after another (the group is the workgroup's XCD
+// when there are 8 groups), and the workgroup's index and count among those of its group.
 struct PanelSlice {
-  int p, lb, nb;
+  int p0, np, lb, nb;
 };
 __device__ __forceinline__ PanelSlice panel_slice(const CsrDev& A) {
   PanelSlice ps;
-  ps.p = int(blockIdx.x) % A.npanel;
-  ps.lb = int(blockIdx.x) / A.npanel;
-  ps.nb = int(gridDim.x) / A.npanel;
+  ps.np = A.nsub > 1 ? A.nsub : 1;
+  const int ng = A.npanel / ps.np;
+  ps.p0 = (int(blockIdx.x) % ng) * ps.np;
+  ps.lb = int(blockIdx.x) / ng;
+  ps.nb = int(gridDim.x) / ng;
   return ps;
 }
 
+// Long rows (kVector) and chunks of giant rows (kSplit) of panel p, one workgroup each.
 template <int MODE, class Epi>
-__device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const double* __restrict__ x,
-                                                const Epi& epi, double (&acc)[Epi::N], double* part) {
-  const PanelSlice ps = panel_slice(A);
-  const int d1 = A.block_begin[ps.p + 1];
-  for (int d = A.block_begin[ps.p] + ps.lb; d < d1; d += ps.nb) {
+__device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const PanelSlice& ps, int p,
+                                                const double* __restrict__ x, const Epi& epi,
+                                                double (&acc)[Epi::N], double* part) {
+  const int d1 = A.block_begin[p + 1];
+  for (int d = A.block_begin[p] + ps.lb; d < d1; d += ps.nb) {
     const RowDesc D = A.block[d];
     const int kind = D.kind_l & 0xff;
     const int r = D.a;
@@ -496,11 +499,14 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
   const int lane64 = threadIdx.x & 63;
   const PanelSlice ps = panel_slice(A);
   const int nw = ps.nb * kWaves;
-  const int t1 = A.wave_begin[ps.p + 1];
-  const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[ps.p] + ps.lb * kWaves + (threadIdx.x >> 6));
   const GlobalGather gx{x};
-  for (int t = w0; t < t1; t += nw) wave_task_e<MODE, 1, false, EMAX>(A, gx, epi, acc, t, lane64);
-  csr_block_tasks<MODE>(A, x, epi, acc, part);
+  for (int q = 0; q < ps.np; ++q) {
+    const int p = ps.p0 + q;
+    const int t1 = A.wave_begin[p + 1];
+    const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[p] + ps.lb * kWaves + (threadIdx.x >> 6));
+    for (int t = w0; t < t1; t += nw) wave_task_e<MODE, 1, false, EMAX>(A, gx, epi, acc, t, lane64);
+    csr_block_tasks<MODE>(A, ps, p, x, epi, acc, part);
+  }
 }
 
 // Same visit with the row values read from `stored` instead of recomputed.

@@ -56,7 +56,8 @@ bool options_valid(const pdlp_options& o) {
            !(o.mp_breaking_factor > 0.0) || !(o.mp_downscaling > 0.0 && o.mp_downscaling < 1.0) ||
            !(o.mp_interpolation >= 0.0 && o.mp_interpolation <= 1.0) || o.column_order < -1 ||
            o.column_order > 1 || (o.pw_power_of_two != 0 && (o.pw_power_of_two != 1 || o.adaptive_restarts)) ||
-           o.lds_gather < -1 || o.lds_gather > 2 || o.lds_entries < 0 || o.lds_entries > kLdsEntries);
+           o.lds_gather < -1 || o.lds_gather > 2 || o.lds_entries < 0 || o.lds_entries > kLdsEntries ||
+           o.xcd_subpanels < -1 || o.xcd_subpanels > kMaxSubpanels);
 }
 
 double now_s() {
@@ -348,6 +349,32 @@ int upload_interleaved(pdlp_solver* s, const Schedule& sc, const int64_t* rp, in
   return 0;
 }
 
+// Sub-panels per XCD panel: opt >= 1 as given (1 = none); automatic (-1): none while every
+// panel's operand slice fits in kSubpanelBytes, else the fewest that keep each within it,
+// rounded up to an even count, at most kMaxSubpanels.
+int subpanel_count(const std::vector<int32_t>& cut, int opt) {
+  if (opt >= 1) return opt;
+  if (opt == 0) return 1;
+  int64_t widest = 0;
+  for (size_t p = 0; p + 1 < cut.size(); ++p) widest = std::max<int64_t>(widest, cut[p + 1] - cut[p]);
+  int64_t S = (widest * 8 + kSubpanelBytes - 1) / kSubpanelBytes;
+  if (S <= 1) return 1;
+  S += S & 1;
+  return int(std::min<int64_t>(S, kMaxSubpanels));
+}
+
+// Each column range of `cut` cut into S ranges of (nearly) equal width.
+std::vector<int32_t> split_cuts(const std::vector<int32_t>& cut, int S) {
+  std::vector<int32_t> sc;
+  sc.reserve((cut.size() - 1) * size_t(S) + 1);
+  for (size_t p = 0; p + 1 < cut.size(); ++p) {
+    const int64_t a = cut[p], w = int64_t(cut[p + 1]) - a;
+    for (int k = 0; k < S; ++k) sc.push_back(int32_t(a + w * k / S));
+  }
+  sc.push_back(cut.back());
+  return sc;
+}
+
 // Uploads one CSR copy (nrows x ncols) in the plain row layout or, when it pays, in XCD
 // column panels; *vdev receives the device values (the scaling kernels rewrite them) and
 // *prow_part the panel-row partial buffer (panel mode only).
@@ -389,18 +416,33 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
       }
     }
   }
+  int nsub = 1;
   if (!panel && want) {
     // the first W columns of each panel staged in LDS: its hottest when the columns are
     // ordered hot-first, automatic for such a copy (on the 1e6 x 2e6 LP, K~ x took 0.55 ms
     // with the stage against 0.89 ms without and 1.21 ms in slices, measured together)
     const bool stage = lmode == 2 || (lmode < 0 && hot_first);
-    panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts,
-                         stage ? kElemsPerLaneLds : kElemsPerLane);
-    if (panel && stage) {
-      if (PL.sched.block.empty())
+    const double frac = mode == 1 ? 1e300 : kPanelRowFrac;
+    bool unstaged = !stage;
+    if (stage) {
+      panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, frac, PL, cuts, kElemsPerLaneLds);
+      if (panel && PL.sched.block.empty()) {
         lds_h = W;
-      else      // rows too long for the LDS kernel: the tasks of the other kernels
-        panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, mode == 1 ? 1e300 : kPanelRowFrac, PL, cuts);
+      } else if (panel) {     // rows too long for the LDS kernel: the tasks of the other kernels
+        panel = false;
+        unstaged = true;
+      }
+    }
+    if (unstaged) {
+      // operand slices wider than an XCD's L2 share: sub-panels, when their panel rows allow
+      const std::vector<int32_t> xc = cuts ? *cuts : panel_cuts(ci, nnz, ncols, kMaxPanels);
+      const int S = subpanel_count(xc, s->opts.xcd_subpanels);
+      if (S > 1) {
+        const std::vector<int32_t> sc = split_cuts(xc, S);
+        panel = build_panels(rp, ci, nrows, ncols, kMaxPanels * S, frac, PL, &sc);
+        if (panel) nsub = S;
+      }
+      if (!panel) panel = build_panels(rp, ci, nrows, ncols, kMaxPanels, frac, PL, &xc);
     }
   }
   A.nrows_orig = int32_t(nrows);
@@ -451,6 +493,7 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
     A.perm = nullptr;
     A.nrows = int32_t(nprow);
     A.npanel = PL.P;
+    A.nsub = nsub;
     PDLP_HIP(s, s->alloc(prow_part, size_t(nprow)));
     return 0;
   }
@@ -474,6 +517,7 @@ int upload_copy(pdlp_solver* s, int64_t nrows, int64_t ncols, const int64_t* rp,
   A.slot_idx = nullptr;
   A.nrows = int32_t(nrows);
   A.npanel = 1;
+  A.nsub = 1;
   return 0;
 }
 
@@ -497,13 +541,15 @@ void launch_panel_rows(pdlp_solver* s, const CsrDev& A, int grid, const double* 
   }
 }
 
-// Grid of a CSR pass: a multiple of npanel, enough workgroups for the busiest panel.
+// Grid of a CSR pass: a multiple of the panel groups (npanel / nsub), enough workgroups for
+// the busiest group.
 int grid_for(const CsrDev& A, int maxG) {
   if (A.npanel <= 1) {
     const int by_wave = (A.nwave + kWaves - 1) / kWaves;
     return std::max(1, std::min(std::max(by_wave, A.nblock), maxG));
   }
-  return A.npanel * std::max(1, maxG / A.npanel);
+  const int ng = A.npanel / std::max(1, A.nsub);
+  return ng * std::max(1, maxG / ng);
 }
 
 int grid_rows(int64_t nrows, int maxG) {
@@ -1405,6 +1451,7 @@ void pdlp_default_options(pdlp_options* o) {
   o->column_order = -1;
   o->lds_gather = -1;
   o->lds_entries = 0;
+  o->xcd_subpanels = -1;
   o->beta_sufficient = 0.1;
   o->beta_necessary = 0.9;
   o->beta_artificial = 0.5;

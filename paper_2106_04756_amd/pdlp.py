@@ -46,7 +46,7 @@ class Options(ctypes.Structure):
                 ("mp_breaking_factor", ctypes.c_double), ("mp_downscaling", ctypes.c_double),
                 ("mp_interpolation", ctypes.c_double), ("column_order", ctypes.c_int32),
                 ("pw_power_of_two", ctypes.c_int32), ("lds_gather", ctypes.c_int32),
-                ("lds_entries", ctypes.c_int32)]
+                ("lds_entries", ctypes.c_int32), ("xcd_subpanels", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

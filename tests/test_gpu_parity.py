@@ -38,11 +38,11 @@ def make(lp, **kw):
 
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("panels,order", [(0, 0), (1, 0), (1, 1)])
-def test_spmv_matches_scipy_on_ragged_shapes(panels, order):
+@pytest.mark.parametrize("panels,order,sub", [(0, 0, -1), (1, 0, -1), (1, 1, -1), (1, 0, 3), (1, 1, 2)])
+def test_spmv_matches_scipy_on_ragged_shapes(panels, order, sub):
     """Unscaled products (no preconditioning) on every schedule path: lane-group rows of
     every width, one-workgroup rows, split giant rows, empty rows/columns; in the plain row
-    layout and in XCD column panels."""
+    layout and in XCD column panels, whole or cut into sub-panels."""
     import torch
     rng = np.random.default_rng(5)
     m, n = 3000, 70000
@@ -56,8 +56,13 @@ def test_spmv_matches_scipy_on_ragged_shapes(panels, order):
                       shape=(m, n))
     K.sort_indices()
     lp = lpgen.from_csr(K, np.ones(n), np.zeros(m), np.zeros(n), np.full(n, 1.0), n_eq=0)
-    say("spmv ragged", m, n, K.nnz, "panels", panels, "column order", order)
-    s = make(lp, ruiz_iters=0, pock_chambolle=0, xcd_panels=panels, column_order=order)
+    say("spmv ragged", m, n, K.nnz, "panels", panels, "order", order, "sub-panels", sub)
+    kw = dict(xcd_panels=panels, column_order=order)
+    if sub > 0:
+        kw.update(lds_gather=0, xcd_subpanels=sub)
+    s = make(lp, ruiz_iters=0, pock_chambolle=0, **kw)
+    if sub > 0:
+        assert (s.info()["panels_K"], s.info()["panels_KT"]) == (8 * sub, 8 * sub)
     for trial in range(2):
         x = rng.standard_normal(n)
         y = rng.standard_normal(m)
@@ -278,6 +283,19 @@ def test_replayed_step_parity(maker):
 ])
 def test_replayed_step_parity_xcd_panels(maker):
     _replay_parity(maker(), xcd_panels=1)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: lpgen.large_plain(21, 400, 900),
+    lambda: lpgen.pagerank_lp(2, 20000),
+])
+def test_replayed_step_parity_xcd_subpanels(maker):
+    """Both copies in XCD panels cut into two sub-panels each, taken one after another."""
+    _replay_parity(maker(), xcd_panels=1, lds_gather=0, xcd_subpanels=2)
+
+
+def test_trajectory_parity_tiny_lp_xcd_subpanels():
+    _trajectory_parity(lpgen.tiny_lp(), xcd_panels=1, lds_gather=0, xcd_subpanels=3)
 
 
 @pytest.mark.parametrize("mode", sorted(LDS_MODES))

@@ -36,8 +36,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_layouts_match_header():
-    # pdlp_options: 10 int32 + 6 double + 4 int32 + 3 double + 4 int32; pdlp_info and the records
-    assert ctypes.sizeof(B.Options) == 10 * 4 + 6 * 8 + 4 * 4 + 3 * 8 + 4 * 4
+    # pdlp_options: 10 int32 + 6 double + 4 int32 + 3 double + 5 int32 and 4 bytes of tail
+    # padding (8-byte alignment); pdlp_info and the records
+    assert ctypes.sizeof(B.Options) == 10 * 4 + 6 * 8 + 4 * 4 + 3 * 8 + 5 * 4 + 4
     assert ctypes.sizeof(B.AttemptRec) == 32
     assert ctypes.sizeof(B.CheckRec) == 8 + 5 * 8 + 4 * 4
     assert ctypes.sizeof(B.Info) == 2 * 4 + 10 * 8 + 2 * 8 + 4 * 8 + 3 * 8 + 4 * 4
@@ -53,7 +54,7 @@ def test_default_options_are_the_papers():
     assert (o.step_policy, o.restart_to_current, o.power_iters, o.xcd_panels) == (0, 1, 200, -1)
     assert (o.mp_breaking_factor, o.mp_downscaling, o.mp_interpolation) == (1.0, 0.5, 0.4)
     assert o.use_graphs == 1 and o.column_order == -1
-    assert (o.lds_gather, o.lds_entries) == (-1, 0)
+    assert (o.lds_gather, o.lds_entries, o.xcd_subpanels) == (-1, 0, -1)
 
 
 def _check_schedule(row_ptr):
@@ -164,7 +165,8 @@ def test_create_rejects_bad_sizes_and_options():
         _create(lp, pw_power_of_two=1)
     with pytest.raises(P.PdlpError, match="options"):
         _create(lp, step_policy=3)
-    for bad in (dict(lds_gather=3), dict(lds_gather=-2), dict(lds_entries=-1), dict(lds_entries=19457)):
+    for bad in (dict(lds_gather=3), dict(lds_gather=-2), dict(lds_entries=-1), dict(lds_entries=19457),
+                dict(xcd_subpanels=-2), dict(xcd_subpanels=9)):
         with pytest.raises(P.PdlpError, match="options"):
             _create(lp, **bad)
 
