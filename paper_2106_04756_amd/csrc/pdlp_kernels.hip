@@ -1418,38 +1418,26 @@ __device__ __forceinline__ uint64_t gap_point(uint64_t lo, uint64_t hi, int i) {
   return lo + (d >> 5) * uint64_t(i) + (((d & 31ull) * uint64_t(i)) >> 5);
 }
 
-// One bisection pass over the breakpoints of ||e(s)||^2 = sum min(s|a_i|, b_i)^2: it is
-// evaluated at 32 points splitting [lo, hi] (as bit patterns of positive doubles, which order
-// like the values) and the sub-interval where it crosses r^2 is kept.
-__device__ __forceinline__ void gap_bisect_points(const DevState& S, double (&sp)[2][kGapPts]) {
+// One bisection pass over the breakpoints of ||e(s)||^2 = sum min(s|a_i|, b_i)^2 of gap slot
+// sel: it is evaluated at 32 points splitting [lo, hi] (as bit patterns of positive doubles,
+// which order like the values) and the sub-interval where it crosses r^2 is kept.  The two
+// slots of a restart check run in one launch on separate workgroups (the first half of the
+// grid for slot 0, the second for slot 1): 32 sums per thread instead of 64 keep the pass at
+// more wavefronts per SIMD.
+__device__ __forceinline__ void gap_bisect_points(const DevState& S, int sel, double (&sp)[kGapPts]) {
 #pragma unroll
-  for (int i = 0; i < kGapPts; ++i) {
-    sp[0][i] = __longlong_as_double((long long)gap_point(S.gap_lo[0], S.gap_hi[0], i + 1));
-    sp[1][i] = __longlong_as_double((long long)gap_point(S.gap_lo[1], S.gap_hi[1], i + 1));
-  }
+  for (int i = 0; i < kGapPts; ++i)
+    sp[i] = __longlong_as_double((long long)gap_point(S.gap_lo[sel], S.gap_hi[sel], i + 1));
 }
 
-__device__ __forceinline__ void gap_bisect_elem(const Bufs& B, bool act0, bool act1,
-                                                const double (&sp)[2][kGapPts], int64_t idx,
-                                                double (&acc)[2 * kGapPts]) {
-  if (act0) {
-    const double aa = B.GA[0][idx], b = B.GB[0][idx];
-    if (aa != 0.0) {
+__device__ __forceinline__ void gap_bisect_elem(const Bufs& B, int sel, const double (&sp)[kGapPts],
+                                                int64_t idx, double (&acc)[kGapPts]) {
+  const double aa = (sel ? B.GA[1] : B.GA[0])[idx], b = (sel ? B.GB[1] : B.GB[0])[idx];
+  if (aa != 0.0) {
 #pragma unroll
-      for (int i = 0; i < kGapPts; ++i) {
-        const double e = fmin(sp[0][i] * aa, b);
-        acc[i] += e * e;
-      }
-    }
-  }
-  if (act1) {
-    const double aa = B.GA[1][idx], b = B.GB[1][idx];
-    if (aa != 0.0) {
-#pragma unroll
-      for (int i = 0; i < kGapPts; ++i) {
-        const double e = fmin(sp[1][i] * aa, b);
-        acc[kGapPts + i] += e * e;
-      }
+    for (int i = 0; i < kGapPts; ++i) {
+      const double e = fmin(sp[i] * aa, b);
+      acc[i] += e * e;
     }
   }
 }
@@ -1466,13 +1454,6 @@ __device__ void gap_bisect_decide_slot(DevState& W, int s, const double* t) {
   W.gap_lo[s] = nlo;
   W.gap_hi[s] = nhi;
   if (nhi - nlo <= 1) W.gap_state[s] = 3;
-}
-
-__device__ void gap_bisect_decide(DevState& W, int mode, const double (&t)[2 * kGapPts]) {
-  for (int s = 0; s < 2; ++s) {
-    if (W.gap_state[s] != 0 || (s == 1 && mode != 0)) continue;
-    gap_bisect_decide_slot(W, s, t + s * kGapPts);
-  }
 }
 
 // mu = a^T e(s*) / r with s* the upper end of the final bracket (or +inf).
@@ -1702,11 +1683,12 @@ __device__ void apply_decide(DevState& W) {
 __device__ __forceinline__ bool gap_active(const DevState& S, int mode) {
   return check_runs(S) && (mode == 0 || S.restart);
 }
-__device__ __forceinline__ bool gap_bisect_active(const DevState& S, int mode, bool& act0, bool& act1) {
-  act0 = S.gap_state[0] == 0;
-  act1 = (mode == 0) && S.gap_state[1] == 0;
-  return gap_active(S, mode) && (act0 || act1);
+// Gap slot sel still bisects (slot 1, the average, only in the restart check, mode 0).
+__device__ __forceinline__ bool gap_bisect_active(const DevState& S, int mode, int sel) {
+  return gap_active(S, mode) && S.gap_state[sel] == 0 && (sel == 0 || mode == 0);
 }
+// Workgroup groups of a bisection pass: one per gap slot the check evaluates.
+__device__ __forceinline__ int gap_groups(int mode) { return mode == 0 ? 2 : 1; }
 
 __device__ void prepare_tail(DevState* st) {
   if (threadIdx.x == 0) st->w_pending = 0.0;
@@ -1716,10 +1698,18 @@ __device__ void gap_setup_tail(DevState* st, int mode, const double* part, int n
   sum_slots<6>(part, nslot, t);
   if (threadIdx.x == 0) gap_setup_decide(*st, mode, t);
 }
+// nslot: slots of the whole pass, nslot / gap_groups(mode) per gap slot, group by group.
 __device__ void gap_bisect_tail(DevState* st, int mode, const double* part, int nslot) {
-  __shared__ double t[2 * kGapPts];
-  sum_slots_shared<2 * kGapPts>(part, nslot, t);
-  if (threadIdx.x == 0) gap_bisect_decide(*st, mode, t);
+  __shared__ double t[kGapPts];
+  const int ng = gap_groups(mode), per = nslot / ng;
+  bool act[2];
+  for (int sel = 0; sel < 2; ++sel) act[sel] = sel < ng && gap_bisect_active(*st, mode, sel);
+  __syncthreads();
+  for (int sel = 0; sel < ng; ++sel) {
+    if (!act[sel]) continue;
+    sum_slots_shared<kGapPts>(part + size_t(sel) * per * kGapPts, per, t);
+    if (threadIdx.x == 0) gap_bisect_decide_slot(*st, sel, t);
+  }
 }
 __device__ void gap_final_tail(DevState* st, const Bufs& B, int mode, const double* part, int nslot) {
   double t[2];
@@ -1763,19 +1753,24 @@ __global__ __launch_bounds__(kBlock) void k_gap_setup(DevState* st, Bufs B, int 
   gap_setup_tail(st, mode, part, gridDim.x);
 }
 
+// Grid: gap_groups(mode) groups of equal size; group sel bisects gap slot sel.
 __global__ __launch_bounds__(kBlock) void k_gap_bisect(DevState* st, Bufs B, int mode, double* part,
                                                        unsigned* ticket) {
   const DevState& S = *st;
-  bool act0, act1;
-  if (!gap_bisect_active(S, mode, act0, act1)) return;
-  double sp[2][kGapPts];
-  gap_bisect_points(S, sp);
-  double acc[2 * kGapPts];
+  if (!gap_bisect_active(S, mode, 0) && !gap_bisect_active(S, mode, 1)) return;
+  const int per = int(gridDim.x) / gap_groups(mode);
+  const int sel = int(blockIdx.x) / per, lb = int(blockIdx.x) % per;
+  double acc[kGapPts];
 #pragma unroll
-  for (int i = 0; i < 2 * kGapPts; ++i) acc[i] = 0.0;
-  PDLP_GRID_LOOP(idx, int64_t(B.n) + B.m) gap_bisect_elem(B, act0, act1, sp, idx, acc);
-  block_sum<2 * kGapPts>(acc);
-  write_slot<2 * kGapPts>(part, blockIdx.x, acc);
+  for (int i = 0; i < kGapPts; ++i) acc[i] = 0.0;
+  if (gap_bisect_active(S, mode, sel)) {
+    double sp[kGapPts];
+    gap_bisect_points(S, sel, sp);
+    for (int64_t idx = lb * int64_t(kBlock) + threadIdx.x; idx < int64_t(B.n) + B.m; idx += int64_t(per) * kBlock)
+      gap_bisect_elem(B, sel, sp, idx, acc);
+  }
+  block_sum<kGapPts>(acc);
+  write_slot<kGapPts>(part, blockIdx.x, acc);
   if (!ticket || !arrive_last(ticket, gridDim.x)) return;
   reset_ticket(ticket);
   gap_bisect_tail(st, mode, part, gridDim.x);
@@ -1843,7 +1838,6 @@ __global__ __launch_bounds__(kBlock) void k_tail(DevState* st, Bufs B, int kind,
                                                  int nslot, const double* partA, int nslotA, int pred,
                                                  int count_as) {
   const DevState& S = *st;
-  bool a0, a1;
   switch (kind) {
     case kTailAttempt:
       if (attempt_runs(S)) finish_attempt(st, B, partA, nslotA, part, nslot);
@@ -1858,7 +1852,7 @@ __global__ __launch_bounds__(kBlock) void k_tail(DevState* st, Bufs B, int kind,
       if (gap_active(S, mode)) gap_setup_tail(st, mode, part, nslot);
       break;
     case kTailGapBisect:
-      if (gap_bisect_active(S, mode, a0, a1)) gap_bisect_tail(st, mode, part, nslot);
+      if (gap_bisect_active(S, mode, 0) || gap_bisect_active(S, mode, 1)) gap_bisect_tail(st, mode, part, nslot);
       break;
     case kTailGapFinal:
       if (gap_active(S, mode)) gap_final_tail(st, B, mode, part, nslot);

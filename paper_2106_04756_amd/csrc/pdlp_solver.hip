@@ -610,9 +610,9 @@ int power_iterate(pdlp_solver* s, double* v, double* t, double* w) {
   return 0;
 }
 
-// The normalized-gap passes accumulate 2 x 32 sums per workgroup, so they run on a grid of at
-// most kGapGrid workgroups (fewer slots for the tail to add).
-constexpr int kGapGrid = 512;
+// The normalized-gap passes run on a grid of at most kGapGrid workgroups (per gap slot in the
+// bisection, whose workgroups accumulate 32 sums each), so that the tail has fewer slots to add.
+constexpr int kGapGrid = 640;
 
 int enqueue_gap(pdlp_solver* s, int mode) {
   int rc;
@@ -620,10 +620,14 @@ int enqueue_gap(pdlp_solver* s, int mode) {
   k_gap_setup<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapSetup));
   PDLP_LAUNCH(s);
   if ((rc = launch_tail(s, g, kTailGapSetup, mode, s->partX, g))) return rc;
+  // one group of workgroups per gap slot, at most 2 kGapGrid in all (32 sums each: within the
+  // 64 gE values of the slot buffer)
+  const int ng = mode == 0 ? 2 : 1;
+  const int gb = ng * std::min(s->gE, 2 * kGapGrid / ng);
   for (int p = 0; p < kBisectPasses; ++p) {
-    k_gap_bisect<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapBisect));
+    k_gap_bisect<<<gb, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, gb, kTkGapBisect));
     PDLP_LAUNCH(s);
-    if ((rc = launch_tail(s, g, kTailGapBisect, mode, s->partX, g))) return rc;
+    if ((rc = launch_tail(s, gb, kTailGapBisect, mode, s->partX, gb))) return rc;
   }
   k_gap_final<<<g, kBlock, 0, s->stream>>>(s->st, s->B, mode, s->partX, ticket_for(s, g, kTkGapFinal));
   PDLP_LAUNCH(s);
