@@ -49,9 +49,10 @@ def _products(s, K, seed, extra=0.0):
     assert np.all(np.abs(outT.cpu().numpy() - KT @ y) <= row_bound(KT, y) + extra * (abs(KT) @ np.abs(y)))
 
 
-def _scaled_case(lp, steps=40):
+def _scaled_case(lp, steps=40, panels=None):
     """Default options: scaling vectors, products of K~ and steps 1, 2 and `steps` (with its
-    restart check) replayed against the oracle."""
+    restart check) replayed against the oracle.  panels: the (K~, K~^T) panel counts the
+    automatic layout choice must make."""
     say("full size", lp.name, lp.m, lp.n, lp.nnz, "scaled, bench launch configuration")
     ref = O.solve_lp(lp, tol=1e-30, iter_limit=steps, record_states=steps, trace_iters=steps,
                      record_trace=True)
@@ -62,6 +63,10 @@ def _scaled_case(lp, steps=40):
     del K
     say("oracle done")
     s = P.Solver.from_lp(lp)
+    inf = s.info()
+    say("layouts", inf["layout_K"], inf["layout_KT"], "panels", inf["panels_K"], inf["panels_KT"])
+    if panels is not None:
+        assert (inf["panels_K"], inf["panels_KT"]) == panels
     D1, D2 = s.scaling()
     dmax = max(float(np.max(np.abs(D1 / oD1 - 1))), float(np.max(np.abs(D2 / oD2 - 1))))
     assert dmax < 1e-13, dmax
@@ -83,8 +88,10 @@ def test_large_lp_full_size_scaled_through_restart_check():
 
 @pytest.mark.timeout(900)
 def test_pagerank_full_size_scaled_through_restart_check():
-    """5e6 nodes: the sum(x) = 1 row of 5e6 nonzeros."""
-    _scaled_case(lpgen.pagerank_5m())
+    """5e6 nodes: the sum(x) = 1 row of 5e6 nonzeros.  K~ has no hot columns and that row
+    rules out the LDS kernel, so its 8 XCD panels (4.8 MiB of x each) are cut into 6
+    sub-panels each; K~^T stays in the plain layout."""
+    _scaled_case(lpgen.pagerank_5m(), panels=(48, 1))
 
 
 @pytest.mark.timeout(900)
