@@ -36,7 +36,7 @@ struct CsrDev {
   const int32_t* split_base;
   int32_t nsplit;
   int32_t nsub;          // panel mode: runs of nsub consecutive panels (column ranges), each
-                         // taken whole by one group of workgroups, one panel after another
+                         // run taken by one group of workgroups, one panel after another
   double* split_part;    // partial sums of split-row chunks
   unsigned* split_cnt;   // chunk arrival counters (reset to 0 by the last arrival)
   // LDS-staged products (lds_h > 0, panel mode, wavefront tasks only): lds_grid workgroups of

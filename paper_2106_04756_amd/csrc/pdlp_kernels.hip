@@ -214,29 +214,32 @@ __device__ double range_reduce(const CsrDev& A, const double* __restrict__ x, in
   return block_comb<MODE>(s);
 }
 
-// Task ranges of this workgroup: the panels of group g = blockIdx mod (npanel / nsub), that
-// is g nsub .. g nsub + nsub - 1, taken one after another (the group is the workgroup's XCD
-// when there are 8 groups), and the workgroup's index and count among those of its group.
+// Task range of this workgroup: panel p and the workgroup's index and count among those of p.
+// The grid holds npanel / nsub groups (the workgroup's XCD when there are 8) and nsub runs of
+// nb workgroups per group: workgroup b belongs to group g = b mod groups, takes run
+// q = (b / groups) / nb of that group, and works on panel g nsub + q.  Workgroups start in
+// the order of their index, so a group's sub-panels are taken one after another.
 struct PanelSlice {
-  int p0, np, lb, nb;
+  int p, lb, nb;
 };
 __device__ __forceinline__ PanelSlice panel_slice(const CsrDev& A) {
   PanelSlice ps;
-  ps.np = A.nsub > 1 ? A.nsub : 1;
-  const int ng = A.npanel / ps.np;
-  ps.p0 = (int(blockIdx.x) % ng) * ps.np;
-  ps.lb = int(blockIdx.x) / ng;
-  ps.nb = int(gridDim.x) / ng;
+  const int S = A.nsub > 1 ? A.nsub : 1;
+  const int ng = A.npanel / S;
+  const int rest = int(blockIdx.x) / ng;
+  ps.nb = int(gridDim.x) / A.npanel;
+  ps.p = (int(blockIdx.x) % ng) * S + rest / ps.nb;
+  ps.lb = rest % ps.nb;
   return ps;
 }
 
-// Long rows (kVector) and chunks of giant rows (kSplit) of panel p, one workgroup each.
+// Long rows (kVector) and chunks of giant rows (kSplit), one workgroup each.
 template <int MODE, class Epi>
-__device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const PanelSlice& ps, int p,
-                                                const double* __restrict__ x, const Epi& epi,
-                                                double (&acc)[Epi::N], double* part) {
-  const int d1 = A.block_begin[p + 1];
-  for (int d = A.block_begin[p] + ps.lb; d < d1; d += ps.nb) {
+__device__ __forceinline__ void csr_block_tasks(const CsrDev& A, const double* __restrict__ x,
+                                                const Epi& epi, double (&acc)[Epi::N], double* part) {
+  const PanelSlice ps = panel_slice(A);
+  const int d1 = A.block_begin[ps.p + 1];
+  for (int d = A.block_begin[ps.p] + ps.lb; d < d1; d += ps.nb) {
     const RowDesc D = A.block[d];
     const int kind = D.kind_l & 0xff;
     const int r = D.a;
@@ -499,14 +502,11 @@ __device__ void csr_rows(const CsrDev& A, const double* __restrict__ x, const Ep
   const int lane64 = threadIdx.x & 63;
   const PanelSlice ps = panel_slice(A);
   const int nw = ps.nb * kWaves;
+  const int t1 = A.wave_begin[ps.p + 1];
+  const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[ps.p] + ps.lb * kWaves + (threadIdx.x >> 6));
   const GlobalGather gx{x};
-  for (int q = 0; q < ps.np; ++q) {
-    const int p = ps.p0 + q;
-    const int t1 = A.wave_begin[p + 1];
-    const int w0 = __builtin_amdgcn_readfirstlane(A.wave_begin[p] + ps.lb * kWaves + (threadIdx.x >> 6));
-    for (int t = w0; t < t1; t += nw) wave_task_e<MODE, 1, false, EMAX>(A, gx, epi, acc, t, lane64);
-    csr_block_tasks<MODE>(A, ps, p, x, epi, acc, part);
-  }
+  for (int t = w0; t < t1; t += nw) wave_task_e<MODE, 1, false, EMAX>(A, gx, epi, acc, t, lane64);
+  csr_block_tasks<MODE>(A, x, epi, acc, part);
 }
 
 // Same visit with the row values read from `stored` instead of recomputed.

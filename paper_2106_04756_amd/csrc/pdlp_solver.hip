@@ -541,15 +541,15 @@ void launch_panel_rows(pdlp_solver* s, const CsrDev& A, int grid, const double* 
   }
 }
 
-// Grid of a CSR pass: a multiple of the panel groups (npanel / nsub), enough workgroups for
-// the busiest group.
+// Grid of a CSR pass: a multiple of npanel.  Each panel group (npanel / nsub of them) gets
+// maxG / groups workgroups for each of its nsub panels, which run one run after another.
 int grid_for(const CsrDev& A, int maxG) {
   if (A.npanel <= 1) {
     const int by_wave = (A.nwave + kWaves - 1) / kWaves;
     return std::max(1, std::min(std::max(by_wave, A.nblock), maxG));
   }
   const int ng = A.npanel / std::max(1, A.nsub);
-  return ng * std::max(1, maxG / ng);
+  return A.npanel * std::max(1, maxG / ng);
 }
 
 int grid_rows(int64_t nrows, int maxG) {
