@@ -147,6 +147,23 @@ def test_panel_layout_width_slices(emax):
     _check(K, L, npanel, 9, False, cuts=cuts, emax=emax)
 
 
+@pytest.mark.parametrize("sub", [2, 6])
+def test_panel_layout_sub_panel_cuts(sub):
+    """8 column ranges of equal nonzero count, each cut into `sub` ranges of equal width: the
+    sub-panels an XCD takes one after another."""
+    K = _matrix(13, 400, 1500)
+    counts = np.bincount(K.indices, minlength=K.shape[1])
+    pref = np.concatenate([[0], np.cumsum(counts)])
+    xcd = np.searchsorted(pref, np.arange(9) * (K.nnz / 8), side="left").clip(0, K.shape[1])
+    xcd[0], xcd[-1] = 0, K.shape[1]
+    cuts = [int(xcd[p] + (xcd[p + 1] - xcd[p]) * k // sub) for p in range(8) for k in range(sub)]
+    cuts = np.array(cuts + [K.shape[1]], dtype=np.int32)
+    assert np.all(np.diff(cuts) >= 0)
+    npanel = 8 * sub
+    L = P.panel_layout(K.indptr, K.indices, K.data, K.shape[1], npanel, cuts=cuts, groups=8 * 32)
+    _check(K, L, npanel, 8 * 32, False, cuts=cuts)
+
+
 @pytest.mark.parametrize("npanel", [1, 3])
 def test_lds_layout_cuts_long_runs_into_pieces(npanel):
     """Rows of 513 .. 2600 nonzeros inside one panel: the LDS layouts (16 entries per lane) hold
